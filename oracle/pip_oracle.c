@@ -1,0 +1,180 @@
+/*
+ * CPU oracle for the ray-casting point-in-polygon test -- TEST INFRASTRUCTURE.
+ *
+ * This file is the slow, obviously-correct reference that the GPU library is
+ * checked against.  It is used only by the tests, by the smoke check and by the
+ * benchmark's CPU-baseline leg; the product path never links or calls it, and it
+ * shares no code, header or table with the GPU library.
+ *
+ * What it computes (paper, Method section, "constraint 1", and Algorithm 1):
+ *   For a query point p and a closed ring of vertices v_0 .. v_{k-1} (the ring
+ *   closes implicitly: the last edge runs from v_{k-1} back to v_0), cast a ray
+ *   from p in direction (1, 0).  Edge (a, b) = (v_i, v_{i+1}) is a candidate
+ *   crossing when its endpoints lie on opposite sides of the ray's line
+ *   y = p_y.  For a candidate, take the edge normal n = (b_y - a_y, a_x - b_x),
+ *   negate it if its x component is negative (so n makes an acute angle with
+ *   the ray direction), and count the edge when (p - a) . n <= 0, i.e. when p
+ *   lies on or to the left of the edge, so the crossing is at or to the right
+ *   of p.  The point is inside when the count is odd.
+ *
+ * Readings taken where the paper is silent or ambiguous:
+ *   - Straddle rule: the paper's product test f_i * f_{i+1} <= 0 counts both
+ *     edges that meet at a vertex lying exactly on the ray.  We use the
+ *     half-open form: the edge straddles iff exactly one endpoint has
+ *     y > p_y (a vertex level with the ray counts as below).  Comparisons only,
+ *     so it is exact and never underflows.  A horizontal edge never straddles.
+ *   - Anchor: a = v_i, the first endpoint in stored order (as the listing).
+ *   - Operation order: t1 = p_x - a_x, t2 = p_y - a_y, s = t1*n_x + t2*n_y,
+ *     each operation rounded separately in IEEE binary64 round-to-nearest-even
+ *     with no fused multiply-add (build with -ffp-contract=off).
+ *   - Boundary: s <= 0 counts (a point on an edge counts that edge).
+ *   - Degenerate rings (k < 3, repeated vertices, self-intersections) get no
+ *     special case: the rule above is applied as is (even-odd semantics).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC -pthread
+ *
+ * PIP_ORACLE_MUTANT (compile-time, tests only): plants one deliberate mistake
+ * so the test suite can show that its pins catch it.  0 / undefined = correct.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <pthread.h>
+
+#ifndef PIP_ORACLE_MUTANT
+#define PIP_ORACLE_MUTANT 0
+#endif
+
+/* Parity of the ray crossings of point (x, y) against the ring vx/vy[0..k). */
+static int ring_parity(double x, double y, const double *vx, const double *vy, int64_t k)
+{
+    int64_t count = 0;
+#if PIP_ORACLE_MUTANT == 4
+    int64_t nedges = k > 0 ? k - 1 : 0;     /* mutant: closing edge dropped */
+#else
+    int64_t nedges = k;
+#endif
+    for (int64_t i = 0; i < nedges; ++i) {
+        int64_t j = (i + 1 == k) ? 0 : i + 1;
+        double ax = vx[i], ay = vy[i];
+        double bx = vx[j], by = vy[j];
+
+        /* candidate crossing: endpoints on opposite sides of y = p_y (half-open) */
+#if PIP_ORACLE_MUTANT == 5
+        int a_above = ay >= y, b_above = by >= y;
+#else
+        int a_above = ay > y, b_above = by > y;
+#endif
+        if (a_above == b_above)
+            continue;
+
+        /* edge normal, oriented to make an acute angle with the ray (1, 0) */
+        double nx = by - ay;
+#if PIP_ORACLE_MUTANT == 6
+        double ny = bx - ax;
+#else
+        double ny = ax - bx;
+#endif
+#if PIP_ORACLE_MUTANT != 3
+        if (nx < 0) {
+            nx = -nx;
+            ny = -ny;
+        }
+#endif
+        /* side of p relative to the edge's line, anchored at a */
+#if PIP_ORACLE_MUTANT == 2
+        double t1 = x - bx, t2 = y - by;
+#else
+        double t1 = x - ax, t2 = y - ay;
+#endif
+#if PIP_ORACLE_MUTANT == 7
+        double s = t1 * ny + t2 * nx;
+#else
+        double s = t1 * nx + t2 * ny;
+#endif
+#if PIP_ORACLE_MUTANT == 1
+        if (s < 0)
+#else
+        if (s <= 0)
+#endif
+            ++count;
+    }
+    return (int)(count & 1);
+}
+
+typedef struct {
+    const double *px, *py;
+    const int64_t *offsets;
+    const double *vx, *vy;
+    const int32_t *point_poly;
+    uint8_t *inside;
+    int64_t begin, end;
+} oracle_job;
+
+static void *oracle_worker(void *arg)
+{
+    oracle_job *j = (oracle_job *)arg;
+    for (int64_t i = j->begin; i < j->end; ++i) {
+        int64_t q = j->point_poly ? (int64_t)j->point_poly[i] : 0;
+        int64_t b = j->offsets[q], e = j->offsets[q + 1];
+        j->inside[i] = (uint8_t)ring_parity(j->px[i], j->py[i], j->vx + b, j->vy + b, e - b);
+    }
+    return NULL;
+}
+
+/*
+ * Classify n_points points.  Point i is tested against polygon point_poly[i]
+ * (or polygon 0 when point_poly is NULL).  Polygon q's ring is
+ * vx/vy[offsets[q] .. offsets[q+1]).  All pointers are host pointers.
+ * Writes inside[i] = 1 (inside) or 0 (outside).  Uses up to nthreads POSIX
+ * threads over contiguous ranges of points (results do not depend on it).
+ * Returns 0 on success, -1 on bad arguments.
+ */
+int pip_oracle_classify(const double *px, const double *py, int64_t n_points,
+                        const int64_t *offsets, int64_t n_polys,
+                        const double *vx, const double *vy,
+                        const int32_t *point_poly, uint8_t *inside, int nthreads)
+{
+    if (n_points < 0 || n_polys < 1 || !offsets || !inside)
+        return -1;
+    if (n_points == 0)
+        return 0;
+    if (!px || !py)
+        return -1;
+    if (!point_poly && n_polys != 1)
+        return -1;
+    if (point_poly) {
+        for (int64_t i = 0; i < n_points; ++i)
+            if (point_poly[i] < 0 || point_poly[i] >= n_polys)
+                return -1;
+    }
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    if ((int64_t)nthreads > n_points)
+        nthreads = (int)n_points;
+
+    oracle_job jobs[256];
+    pthread_t tids[256];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].px = px; jobs[t].py = py;
+        jobs[t].offsets = offsets;
+        jobs[t].vx = vx; jobs[t].vy = vy;
+        jobs[t].point_poly = point_poly;
+        jobs[t].inside = inside;
+        jobs[t].begin = n_points * t / nthreads;
+        jobs[t].end = n_points * (t + 1) / nthreads;
+    }
+    int started = 0;
+    for (int t = 1; t < nthreads; ++t) {
+        if (pthread_create(&tids[t], NULL, oracle_worker, &jobs[t]) != 0)
+            break;
+        started = t;
+    }
+    oracle_worker(&jobs[0]);
+    for (int t = 1; t <= started; ++t)
+        pthread_join(tids[t], NULL);
+    for (int t = started + 1; t < nthreads; ++t)   /* threads that failed to start */
+        oracle_worker(&jobs[t]);
+    return 0;
+}
