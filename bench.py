@@ -1,0 +1,237 @@
+"""Throughput of the ray-casting point-in-polygon hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--config 2] [--mode exact] [--kernel auto]
+
+A step classifies one full batch of the workload (default: the footprint
+workload, 100,000 building-footprint polygons and 10M point->polygon pairs)
+through the C ABI.  Inputs are resident in HBM before timing starts; the
+batch rotates over several device copies so that no step reads data the
+previous step left in the on-chip caches.  Prints one JSON line with
+throughput (point-edge tests/s, points/s), the dominant kernel's roofline
+fraction (kernel time from HIP events recorded on the launch stream), the
+bit-exact parity verdict against the CPU oracle, and the oracle's own speed
+on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+METRIC = "point-edge tests/s and points/s at bit-exact match; % of HBM/VALU roofline"
+
+WORKLOAD_TEXT = {
+    1: "star: 1 star-shaped polygon, 64 vertices, 100,000 points in its bbox",
+    2: "footprints: 100,000 footprint polygons (rotated rectangles / L-shapes, 4-32 vertices), "
+       "10,000,000 point->polygon pairs (100 per polygon, bbox x1.2), pairs sorted by polygon",
+    3: "fractal: 1 midpoint-displaced 1024-gon with 1,000,000 vertices, 10,000,000 points in its bbox",
+    4: "batched: 1,000,000 star polygons, k ~ k^-2 on [3,4096], Poisson(100) points each (~1e8 pairs)",
+    5: "stress: batched topology in metres (offset 5e6, 5-50 m), 3% of points on/near edges and vertices",
+}
+
+# Traffic measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE) for the dominant kernel at the
+# default workload, scaled by the calibration copy; None until counters exist for the current kernel.
+PROFILED_TRAFFIC = {}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mode", default="exact", choices=["exact"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "per_pair", "segmented"])
+    ap.add_argument("--copies", type=int, default=4, help="device copies the steps rotate over")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle timing budget")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--probe-copy-mb", type=int, default=0,
+                    help="run only the HBM calibration copy of this many MiB (for counter scaling)")
+    return ap.parse_args()
+
+
+def host_threads() -> int:
+    env = os.environ.get("OMP_NUM_THREADS")
+    n = int(env) if env and env.isdigit() else (os.cpu_count() or 1)
+    try:
+        n = min(n, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        pass
+    return max(1, n)
+
+
+def cpu_baseline(w, budget_s: float):
+    """Time the oracle as it stands on this host's cores over whole passes of a bounded sample."""
+    import oracle
+    th = host_threads()
+    n = w.n_points
+    # size a sample that takes about budget_s: probe with a small slice first
+    probe_n = min(n, 20_000)
+    t0 = time.perf_counter()
+    idx = np.arange(probe_n)
+    from paper_2306_04316_amd import workloads as W
+    oracle.classify_workload(W.subsample(w, idx), nthreads=th)
+    dt = max(time.perf_counter() - t0, 1e-6)
+    want = int(min(n, max(probe_n, probe_n * budget_s / dt)))
+    if want >= n:
+        s, label = w, f"the full workload ({n} pairs)"
+    else:
+        s = W.subsample(w, np.arange(want))
+        label = f"the first {want} of {n} pairs (contiguous, same polygons)"
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.classify_workload(s, nthreads=th)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= 0.5 * budget_s or reps >= 50:
+            break
+    per = el / reps
+    tests = s.n_tests
+    return {"value": tests / per, "unit": "tests/s", "points_per_s": s.n_points / per, "cores": th,
+            "kind": "oracle", "sample": f"{label}, {reps} pass(es), {per:.3f} s per pass",
+            "cpu_model": cpu_model()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
+                                   "(the pairs are independent: the multi-GPU split is a partition "
+                                   "of polygons with their points, with no exchange)"}), flush=True)
+        sys.exit(2)
+    import torch
+    import paper_2306_04316_amd as P
+    from paper_2306_04316_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+
+    if a.probe_copy_mb:
+        nb = a.probe_copy_mb << 20
+        src = torch.empty(nb, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty(nb, dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            P.probe_copy(dst, src)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe_copy_bytes": nb}), flush=True)
+        return
+
+    t_gen = time.perf_counter()
+    w = W.make(a.config, seed=a.seed)
+    t_gen = time.perf_counter() - t_gen
+    copies = []
+    for c in range(max(1, a.copies)):
+        d = P.to_device(w, dev)
+        d["out"] = torch.empty(w.n_points, dtype=torch.uint8, device=dev)
+        copies.append(d)
+    torch.cuda.synchronize()
+
+    def step(i, ev=None):
+        d = copies[i % len(copies)]
+        if ev is not None:
+            ev[0].record()
+        P.classify(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], kernel=a.kernel,
+                   out=d["out"])
+        if ev is not None:
+            ev[1].record()
+
+    for i in range(a.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for i in range(a.steps):
+        step(a.warmup + i, evs[i])
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = start.elapsed_time(stop)
+    kern_ms = [e0.elapsed_time(e1) for (e0, e1) in evs]
+    ms_per_step = gpu_ms / a.steps
+
+    T = w.n_tests
+    N = w.n_points
+    value = T / (ms_per_step * 1e-3)
+    kern_avg = float(np.mean(kern_ms))
+    alg_bytes = w.nbytes_algorithmic()
+    achieved = alg_bytes / (kern_avg * 1e-3) / 1e9
+
+    parity = "not checked"
+    if not a.no_parity:
+        import oracle
+        got = copies[(a.warmup + a.steps - 1) % len(copies)]["out"].cpu().numpy()
+        if w.n_tests <= 5_000_000_000:
+            want = oracle.classify_workload(w, nthreads=host_threads())
+            nbad = int(np.count_nonzero(got != want))
+            parity = "bit-exact (all pairs)" if nbad == 0 else f"MISMATCH in {nbad} pairs"
+        else:
+            rng = np.random.default_rng(1)
+            idx = np.sort(rng.choice(N, 2000, replace=False))
+            want = oracle.classify_workload(W.subsample(w, idx), nthreads=host_threads())
+            nbad = int(np.count_nonzero(got[idx] != want))
+            parity = (f"bit-exact (2000 sampled pairs)" if nbad == 0
+                      else f"MISMATCH in {nbad} of 2000 sampled pairs")
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(w, a.cpu_seconds)
+
+    traffic = PROFILED_TRAFFIC.get((a.config, a.mode, a.kernel))
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "tests/s",
+        "points_per_s": N / (ms_per_step * 1e-3),
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "parity": parity,
+        "config": {"workload": WORKLOAD_TEXT[a.config], "config_id": a.config, "seed": a.seed,
+                   "pairs": N, "polygons": w.n_polys, "vertices": w.n_vertices, "tests": T,
+                   "mode": a.mode, "kernel": a.kernel, "device_copies": len(copies)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "main classification kernel", "kernel_ms": kern_avg,
+                     "alg_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+        "wall_s_timed": wall,
+        "gen_s": t_gen,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

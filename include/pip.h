@@ -1,0 +1,139 @@
+/*
+ * pip.h -- C ABI of the MI355X (gfx950) ray-casting point-in-polygon library.
+ *
+ * The operation (paper, Method section, "constraint 1", and Algorithm 1):
+ * for a point p and a polygon ring v_0 .. v_{k-1} (closed implicitly: the last
+ * edge runs from v_{k-1} back to v_0) cast a ray from p in direction (1, 0).
+ * Edge (a, b) = (v_i, v_{i+1}) crosses the ray when exactly one of a_y > p_y,
+ * b_y > p_y holds (half-open rule: a vertex level with the ray counts as
+ * below) and (p - a) . n <= 0 for the edge normal n = (b_y - a_y, a_x - b_x)
+ * oriented so n_x > 0.  p is inside when the number of crossings is odd.
+ * Every side value is evaluated in IEEE binary64 with the operation order
+ * t1 = p_x - a_x, t2 = p_y - a_y, s = t1*n_x + t2*n_y, each operation rounded
+ * separately (no fused multiply-add).  Results are therefore bit-identical to
+ * a plain CPU binary64 evaluation of the same rule, in every mode.
+ *
+ * Layout (all arrays are DEVICE pointers, caller-owned, and must stay valid
+ * until the work enqueued on `stream` completes):
+ *   px, py        double[n_points]      query points (SoA)
+ *   offsets       int64_t[n_polys + 1]  CSR ring offsets; offsets[0] = 0,
+ *                                        non-decreasing, offsets[n_polys] =
+ *                                        n_vertices
+ *   vx, vy        double[n_vertices]    ring vertices (SoA), rings back to back
+ *   point_poly    int32_t[n_points]     pair index: point i is tested against
+ *                                        polygon point_poly[i]; may be NULL,
+ *                                        then every point is tested against
+ *                                        polygon 0 and n_polys must be 1.
+ *                                        Sorted (non-decreasing) indices are
+ *                                        fastest; any order is correct.
+ *   inside        uint8_t[n_points]     output, 1 = inside, 0 = outside;
+ *                                        fully overwritten.
+ * A ring may repeat its first vertex at its end or not: both give the same
+ * result (the repeated edge is horizontal and never crosses).  Rings with
+ * fewer than 3 vertices, repeated vertices and self-intersections are legal
+ * and follow the same rule (even-odd semantics).  Coordinates must be finite.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * Calls enqueue work and return without waiting, except where stated.
+ *
+ * Errors: every call returns a pip_status; pip_last_error() gives the text
+ * of the calling thread's last failure.  With validate = 1 the library also
+ * checks the data on the device (and then waits for the stream):
+ *   PIP_EINVAL   NULL required pointer, negative count, point_poly == NULL
+ *                with n_polys != 1, unknown mode/kernel, bad struct_size
+ *   PIP_ERANGE   offsets not a valid CSR over n_vertices, or a point_poly
+ *                entry outside [0, n_polys)       (validate = 1 only)
+ *   PIP_EDOM     a non-finite coordinate           (validate = 1 only)
+ *   PIP_ENOMEM   device workspace allocation failed
+ *   PIP_EHIP     a HIP runtime error (text in pip_last_error())
+ *   PIP_ENOTSUP  the current device is not gfx950
+ * Without validation, out-of-range indices and offsets are clamped so that
+ * no access leaves the arrays; the bits of such pairs are unspecified.
+ */
+#ifndef PIP_H
+#define PIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIP_ABI_VERSION 1
+
+#if defined(__GNUC__) || defined(__clang__)
+#define PIP_API __attribute__((visibility("default")))
+#else
+#define PIP_API
+#endif
+
+typedef enum {
+    PIP_OK = 0,
+    PIP_EINVAL = -1,
+    PIP_ERANGE = -2,
+    PIP_EDOM = -3,
+    PIP_ENOMEM = -4,
+    PIP_EHIP = -5,
+    PIP_ENOTSUP = -6
+} pip_status;
+
+/* Arithmetic of the bulk of the edge tests.  Both modes give the same bits. */
+typedef enum {
+    /* every side value in binary64, in the rule's operation order */
+    PIP_MODE_EXACT_FP64 = 0,
+    /* binary32 on per-polygon re-centred coordinates with a proven forward
+     * error bound; a pair with any undecided edge is re-run in binary64 in
+     * the rule's operation order (plans only) */
+    PIP_MODE_FILTERED_FP32 = 1
+} pip_mode;
+
+/* Work mapping of the main kernel. */
+typedef enum {
+    PIP_KERNEL_AUTO = 0,
+    /* one lane per pair, every vertex fetched per lane: the plain baseline */
+    PIP_KERNEL_PER_PAIR = 1,
+    /* one lane per pair; the lanes of a wavefront that share a polygon run
+     * together with the polygon's vertices wave-uniform (scalar loads) */
+    PIP_KERNEL_SEGMENTED = 2
+} pip_kernel;
+
+typedef struct {
+    uint32_t struct_size;   /* = sizeof(pip_options) */
+    int32_t mode;           /* pip_mode */
+    int32_t kernel;         /* pip_kernel */
+    int32_t validate;       /* 1: check the data on the device first (synchronises) */
+} pip_options;
+
+/* Fills *opts with the defaults (exact binary64, automatic kernel, no validation). */
+PIP_API void pip_options_init(pip_options *opts);
+
+/* ABI version of the loaded library (PIP_ABI_VERSION it was built with). */
+PIP_API int pip_abi_version(void);
+
+/* Text of the calling thread's last non-OK status ("" if none). */
+PIP_API const char *pip_last_error(void);
+
+/*
+ * Classify n_points points (see the layout above).  opts may be NULL
+ * (defaults).  n_points == 0 is a no-op.  Only PIP_MODE_EXACT_FP64 is
+ * accepted here (the filtered mode needs a plan's workspace).  Allocates
+ * nothing on the device.  Asynchronous on `stream` unless opts->validate.
+ */
+PIP_API int pip_classify(const double *px, const double *py, int64_t n_points,
+                 const int64_t *offsets, int64_t n_polys,
+                 const double *vx, const double *vy, int64_t n_vertices,
+                 const int32_t *point_poly, uint8_t *inside,
+                 const pip_options *opts, void *stream);
+
+/*
+ * Diagnostic: copy nbytes (a multiple of 16) from src to dst with a plain
+ * streaming kernel.  Used to calibrate HBM traffic counters against a
+ * kernel of known size.  Asynchronous on `stream`.
+ */
+PIP_API int pip_probe_copy(void *dst, const void *src, int64_t nbytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIP_H */

@@ -1,0 +1,101 @@
+"""MI355X (gfx950) ray-casting point-in-polygon (arxiv 2306.04316, constraint 1).
+
+The work runs in ``libpip.so`` (hand-written HIP kernels behind a C ABI,
+``include/pip.h``).  This package only marshals torch device tensors and
+streams into that ABI:
+
+    inside = classify(px, py, offsets, vx, vy, point_poly=None)
+
+Inputs are CUDA (HIP) tensors: px, py, vx, vy float64; offsets int64 CSR
+(offsets[0] = 0, offsets[-1] = len(vx)); point_poly int32 or None.  The result
+is a uint8 tensor (1 = inside).  Work is enqueued on the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import PipError  # noqa: F401
+
+__all__ = ["classify", "PipError", "abi_version", "probe_copy", "to_device"]
+
+
+def _require(t, dtype, name, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def options(mode="exact", kernel="auto", validate=False) -> _lib.pip_options:
+    o = _lib.pip_options()
+    _lib.load().pip_options_init(ctypes.byref(o))
+    o.mode = _lib.MODES[mode] if isinstance(mode, str) else int(mode)
+    o.kernel = _lib.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    o.validate = 1 if validate else 0
+    return o
+
+
+def classify(px, py, offsets, vx, vy, point_poly=None, *, kernel="auto", validate=False, out=None,
+             stream=None):
+    """inside[i] for point i against polygon point_poly[i] (or polygon 0)."""
+    import torch
+    lib = _lib.load()
+    n = px.numel()
+    _require(px, torch.float64, "px")
+    _require(py, torch.float64, "py", n)
+    _require(offsets, torch.int64, "offsets")
+    _require(vx, torch.float64, "vx")
+    _require(vy, torch.float64, "vy", vx.numel())
+    if point_poly is not None:
+        _require(point_poly, torch.int32, "point_poly", n)
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=px.device)
+    else:
+        _require(out, torch.uint8, "out", n)
+    o = options("exact", kernel, validate)
+    with torch.cuda.device(px.device):
+        rc = lib.pip_classify(_ptr(px), _ptr(py), n, _ptr(offsets), offsets.numel() - 1, _ptr(vx), _ptr(vy),
+                              vx.numel(), _ptr(point_poly), _ptr(out), ctypes.byref(o), _stream_handle(stream))
+    _lib.check(rc)
+    return out
+
+
+def probe_copy(dst, src, stream=None):
+    """Plain streaming copy of src into dst (same byte size, multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    _lib.check(_lib.load().pip_probe_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)))
+
+
+def abi_version() -> int:
+    return int(_lib.load().pip_abi_version())
+
+
+def to_device(w, device="cuda"):
+    """Copy a workloads.Workload's arrays to device tensors (dict of tensors)."""
+    import torch
+    d = dict(px=torch.from_numpy(w.px).to(device), py=torch.from_numpy(w.py).to(device),
+             offsets=torch.from_numpy(w.offsets).to(device), vx=torch.from_numpy(w.vx).to(device),
+             vy=torch.from_numpy(w.vy).to(device))
+    d["point_poly"] = None if w.point_poly is None else torch.from_numpy(w.point_poly).to(device)
+    return d

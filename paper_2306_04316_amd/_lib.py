@@ -1,0 +1,67 @@
+"""ctypes view of libpip.so (argument marshalling only; all work runs in the HIP library)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpip.so")
+
+PIP_OK, PIP_EINVAL, PIP_ERANGE, PIP_EDOM, PIP_ENOMEM, PIP_EHIP, PIP_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "PIP_OK", -1: "PIP_EINVAL", -2: "PIP_ERANGE", -3: "PIP_EDOM", -4: "PIP_ENOMEM",
+                -5: "PIP_EHIP", -6: "PIP_ENOTSUP"}
+
+MODES = {"exact": 0, "fp64": 0, "filtered": 1, "fp32": 1}
+KERNELS = {"auto": 0, "per_pair": 1, "segmented": 2}
+
+
+class PipError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class pip_options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("mode", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("validate", ctypes.c_int32)]
+
+
+_VP = ctypes.c_void_p
+_I64 = ctypes.c_int64
+
+_SIGS = {
+    "pip_options_init": (None, [ctypes.POINTER(pip_options)]),
+    "pip_abi_version": (ctypes.c_int, []),
+    "pip_last_error": (ctypes.c_char_p, []),
+    "pip_classify": (ctypes.c_int, [_VP, _VP, _I64, _VP, _I64, _VP, _VP, _I64, _VP, _VP,
+                                    ctypes.POINTER(pip_options), _VP]),
+    "pip_probe_copy": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree libpip.so; fails loudly when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2306_04316_amd.build` "
+                          "(there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> None:
+    if rc != PIP_OK:
+        raise PipError(rc, load().pip_last_error().decode(errors="replace"))
+
+
+def declared_symbols() -> list:
+    return list(_SIGS)

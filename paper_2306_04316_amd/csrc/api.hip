@@ -1,0 +1,159 @@
+// C ABI entry points: argument checks, device checks, kernel selection.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "pip_common.h"
+
+namespace pip {
+
+namespace {
+thread_local char g_err[512] = "";
+
+// Flag word written by the validation kernels (one per device; concurrent
+// validating calls on one device share it).
+__device__ unsigned g_validate_word;
+
+std::mutex g_dev_mu;
+std::vector<DeviceInfo *> g_devs;
+}  // namespace
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+int current_device(DeviceInfo **out)
+{
+    int dev = 0;
+    PIP_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if ((int)g_devs.size() <= dev)
+        g_devs.resize(dev + 1, nullptr);
+    if (!g_devs[dev]) {
+        hipDeviceProp_t prop;
+        PIP_HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        auto *d = new DeviceInfo;
+        d->device = dev;
+        d->cu_count = prop.multiProcessorCount;
+        d->gfx950 = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        void *sym = nullptr;
+        hipError_t e = hipGetSymbolAddress(&sym, HIP_SYMBOL(g_validate_word));
+        if (e != hipSuccess) {
+            delete d;
+            return fail(PIP_EHIP, "hipGetSymbolAddress(validate word) failed: %s", hipGetErrorString(e));
+        }
+        d->validate_flags = (unsigned *)sym;
+        g_devs[dev] = d;
+    }
+    if (!g_devs[dev]->gfx950)
+        return fail(PIP_ENOTSUP, "device %d is not gfx950", dev);
+    *out = g_devs[dev];
+    return PIP_OK;
+}
+
+int check_host_args(const Problem &p)
+{
+    if (p.n_points < 0 || p.n_polys < 1 || p.n_vertices < 0)
+        return fail(PIP_EINVAL, "negative count or n_polys < 1 (n_points=%lld n_polys=%lld n_vertices=%lld)",
+                    (long long)p.n_points, (long long)p.n_polys, (long long)p.n_vertices);
+    if (p.n_polys > INT32_MAX)
+        return fail(PIP_EINVAL, "n_polys exceeds the int32 pair index range");
+    if (!p.offsets)
+        return fail(PIP_EINVAL, "offsets is NULL");
+    if (p.n_vertices > 0 && (!p.vx || !p.vy))
+        return fail(PIP_EINVAL, "vx/vy is NULL");
+    if (p.n_points > 0 && (!p.px || !p.py || !p.inside))
+        return fail(PIP_EINVAL, "px/py/inside is NULL");
+    if (!p.point_poly && p.n_polys != 1)
+        return fail(PIP_EINVAL, "point_poly is NULL but n_polys=%lld (must be 1)", (long long)p.n_polys);
+    return PIP_OK;
+}
+
+int validate_on_device(const Problem &p, DeviceInfo *dev, hipStream_t stream)
+{
+    PIP_TRY(launch_validate(p, dev->validate_flags, stream));
+    unsigned flags = 0;
+    PIP_HIP_TRY(hipMemcpyAsync(&flags, dev->validate_flags, sizeof flags, hipMemcpyDeviceToHost, stream));
+    PIP_HIP_TRY(hipStreamSynchronize(stream));
+    if (flags & VALIDATE_ERANGE)
+        return fail(PIP_ERANGE, "offsets are not a CSR over n_vertices, or a point_poly entry is out of range");
+    if (flags & VALIDATE_EDOM)
+        return fail(PIP_EDOM, "non-finite coordinate");
+    return PIP_OK;
+}
+
+}  // namespace pip
+
+using namespace pip;
+
+extern "C" {
+
+void pip_options_init(pip_options *opts)
+{
+    if (!opts)
+        return;
+    memset(opts, 0, sizeof *opts);
+    opts->struct_size = sizeof *opts;
+    opts->mode = PIP_MODE_EXACT_FP64;
+    opts->kernel = PIP_KERNEL_AUTO;
+    opts->validate = 0;
+}
+
+int pip_abi_version(void) { return PIP_ABI_VERSION; }
+
+const char *pip_last_error(void) { return g_err; }
+
+int pip_classify(const double *px, const double *py, int64_t n_points, const int64_t *offsets, int64_t n_polys,
+                 const double *vx, const double *vy, int64_t n_vertices, const int32_t *point_poly,
+                 uint8_t *inside, const pip_options *opts, void *stream)
+{
+    clear_error();
+    pip_options o;
+    pip_options_init(&o);
+    if (opts) {
+        if (opts->struct_size != sizeof(pip_options))
+            return fail(PIP_EINVAL, "pip_options.struct_size=%u, expected %zu", opts->struct_size,
+                        sizeof(pip_options));
+        o = *opts;
+    }
+    if (o.mode != PIP_MODE_EXACT_FP64)
+        return fail(PIP_EINVAL, "pip_classify supports PIP_MODE_EXACT_FP64 only (mode=%d); use a plan", o.mode);
+    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_SEGMENTED)
+        return fail(PIP_EINVAL, "unknown kernel %d", o.kernel);
+    Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
+    PIP_TRY(check_host_args(p));
+    DeviceInfo *dev = nullptr;
+    PIP_TRY(current_device(&dev));
+    hipStream_t s = (hipStream_t)stream;
+    if (o.validate)
+        PIP_TRY(validate_on_device(p, dev, s));
+    if (n_points == 0)
+        return PIP_OK;
+    if (o.kernel == PIP_KERNEL_PER_PAIR)
+        return launch_per_pair(p, s);
+    return launch_segmented(p, s);
+}
+
+int pip_probe_copy(void *dst, const void *src, int64_t nbytes, void *stream)
+{
+    clear_error();
+    if (!dst || !src || nbytes < 0 || (nbytes % 16) != 0)
+        return fail(PIP_EINVAL, "pip_probe_copy: NULL pointer or nbytes not a non-negative multiple of 16");
+    DeviceInfo *dev = nullptr;
+    PIP_TRY(current_device(&dev));
+    if (nbytes == 0)
+        return PIP_OK;
+    return launch_copy(dst, src, nbytes, (hipStream_t)stream);
+}
+
+}  // extern "C"
