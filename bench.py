@@ -51,7 +51,10 @@ def parse():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", default="exact", choices=["exact"])
-    ap.add_argument("--kernel", default="auto", choices=["auto", "per_pair", "segmented"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "per_pair", "segmented", "staged"])
+    ap.add_argument("--pairs-per-lane", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--lds-slots", type=int, default=0)
     ap.add_argument("--copies", type=int, default=4, help="device copies the steps rotate over")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle timing budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -95,7 +98,7 @@ def cpu_baseline(w, budget_s: float):
         oracle.classify_workload(s, nthreads=th)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= 0.5 * budget_s or reps >= 50:
+        if el >= 0.5 * budget_s:
             break
     per = el / reps
     tests = s.n_tests
@@ -154,7 +157,7 @@ def main():
         if ev is not None:
             ev[0].record()
         P.classify(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], kernel=a.kernel,
-                   out=d["out"])
+                   out=d["out"], pairs_per_lane=a.pairs_per_lane, block=a.block, lds_slots=a.lds_slots)
         if ev is not None:
             ev[1].record()
 

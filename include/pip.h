@@ -40,7 +40,8 @@
  * of the calling thread's last failure.  With validate = 1 the library also
  * checks the data on the device (and then waits for the stream):
  *   PIP_EINVAL   NULL required pointer, negative count, point_poly == NULL
- *                with n_polys != 1, unknown mode/kernel, bad struct_size
+ *                with n_points > 0 and n_polys != 1, unknown mode/kernel,
+ *                bad struct_size
  *   PIP_ERANGE   offsets not a valid CSR over n_vertices, or a point_poly
  *                entry outside [0, n_polys)       (validate = 1 only)
  *   PIP_EDOM     a non-finite coordinate           (validate = 1 only)
@@ -94,7 +95,11 @@ typedef enum {
     PIP_KERNEL_PER_PAIR = 1,
     /* one lane per pair; the lanes of a wavefront that share a polygon run
      * together with the polygon's vertices wave-uniform (scalar loads) */
-    PIP_KERNEL_SEGMENTED = 2
+    PIP_KERNEL_SEGMENTED = 2,
+    /* one lane per pair; a workgroup copies the rings its (sorted) pairs
+     * test into LDS once and every lane walks its own ring from there;
+     * workgroups whose rings do not fit fall back to the segmented walk */
+    PIP_KERNEL_STAGED = 3
 } pip_kernel;
 
 typedef struct {
@@ -102,6 +107,10 @@ typedef struct {
     int32_t mode;           /* pip_mode */
     int32_t kernel;         /* pip_kernel */
     int32_t validate;       /* 1: check the data on the device first (synchronises) */
+    int32_t pairs_per_lane; /* tuning, segmented kernel: pairs per lane (1, 2, 4, 8); 0 = default */
+    int32_t block;          /* tuning: threads per workgroup (64, 128, 256); 0 = default */
+    int32_t lds_slots;      /* tuning, staged kernel: LDS vertex slots per workgroup
+                               (16 bytes each, at most 8192); 0 = default */
 } pip_options;
 
 /* Fills *opts with the defaults (exact binary64, automatic kernel, no validation). */

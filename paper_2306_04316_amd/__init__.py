@@ -45,17 +45,20 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def options(mode="exact", kernel="auto", validate=False) -> _lib.pip_options:
+def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block=0, lds_slots=0) -> _lib.pip_options:
     o = _lib.pip_options()
     _lib.load().pip_options_init(ctypes.byref(o))
     o.mode = _lib.MODES[mode] if isinstance(mode, str) else int(mode)
     o.kernel = _lib.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.validate = 1 if validate else 0
+    o.pairs_per_lane = int(pairs_per_lane)
+    o.block = int(block)
+    o.lds_slots = int(lds_slots)
     return o
 
 
 def classify(px, py, offsets, vx, vy, point_poly=None, *, kernel="auto", validate=False, out=None,
-             stream=None):
+             stream=None, pairs_per_lane=0, block=0, lds_slots=0):
     """inside[i] for point i against polygon point_poly[i] (or polygon 0)."""
     import torch
     lib = _lib.load()
@@ -71,7 +74,7 @@ def classify(px, py, offsets, vx, vy, point_poly=None, *, kernel="auto", validat
         out = torch.empty(n, dtype=torch.uint8, device=px.device)
     else:
         _require(out, torch.uint8, "out", n)
-    o = options("exact", kernel, validate)
+    o = options("exact", kernel, validate, pairs_per_lane, block, lds_slots)
     with torch.cuda.device(px.device):
         rc = lib.pip_classify(_ptr(px), _ptr(py), n, _ptr(offsets), offsets.numel() - 1, _ptr(vx), _ptr(vy),
                               vx.numel(), _ptr(point_poly), _ptr(out), ctypes.byref(o), _stream_handle(stream))

@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "PIP_OK", -1: "PIP_EINVAL", -2: "PIP_ERANGE", -3: "PIP_EDOM",
                 -5: "PIP_EHIP", -6: "PIP_ENOTSUP"}
 
 MODES = {"exact": 0, "fp64": 0, "filtered": 1, "fp32": 1}
-KERNELS = {"auto": 0, "per_pair": 1, "segmented": 2}
+KERNELS = {"auto": 0, "per_pair": 1, "segmented": 2, "staged": 3}
 
 
 class PipError(RuntimeError):
@@ -23,7 +23,8 @@ class PipError(RuntimeError):
 
 class pip_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("mode", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("validate", ctypes.c_int32)]
+                ("validate", ctypes.c_int32), ("pairs_per_lane", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("lds_slots", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p

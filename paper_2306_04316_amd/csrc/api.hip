@@ -74,7 +74,8 @@ int check_host_args(const Problem &p)
         return fail(PIP_EINVAL, "vx/vy is NULL");
     if (p.n_points > 0 && (!p.px || !p.py || !p.inside))
         return fail(PIP_EINVAL, "px/py/inside is NULL");
-    if (!p.point_poly && p.n_polys != 1)
+    // with no points there is no pair index to read (an empty array may be NULL)
+    if (p.n_points > 0 && !p.point_poly && p.n_polys != 1)
         return fail(PIP_EINVAL, "point_poly is NULL but n_polys=%lld (must be 1)", (long long)p.n_polys);
     return PIP_OK;
 }
@@ -128,7 +129,7 @@ int pip_classify(const double *px, const double *py, int64_t n_points, const int
     }
     if (o.mode != PIP_MODE_EXACT_FP64)
         return fail(PIP_EINVAL, "pip_classify supports PIP_MODE_EXACT_FP64 only (mode=%d); use a plan", o.mode);
-    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_SEGMENTED)
+    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_STAGED)
         return fail(PIP_EINVAL, "unknown kernel %d", o.kernel);
     Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
     PIP_TRY(check_host_args(p));
@@ -141,7 +142,9 @@ int pip_classify(const double *px, const double *py, int64_t n_points, const int
         return PIP_OK;
     if (o.kernel == PIP_KERNEL_PER_PAIR)
         return launch_per_pair(p, s);
-    return launch_segmented(p, s);
+    if (o.kernel == PIP_KERNEL_SEGMENTED)
+        return launch_segmented(p, s, o.pairs_per_lane, o.block);
+    return launch_staged(p, s, o.pairs_per_lane, o.lds_slots);
 }
 
 int pip_probe_copy(void *dst, const void *src, int64_t nbytes, void *stream)

@@ -22,11 +22,13 @@
 namespace pip {
 namespace {
 
-// Clamp a ring's [b, e) to the vertex array so no access leaves it.
+// Clamp a ring's [b, e) to the vertex array so no access leaves it, and to
+// at most INT32_MAX vertices per ring.
 __device__ __forceinline__ void clamp_ring(int64_t &b, int64_t &e, int64_t nv)
 {
     e = e < 0 ? 0 : (e > nv ? nv : e);
     b = b < 0 ? 0 : (b > e ? e : b);
+    e = (e - b > INT32_MAX) ? b + INT32_MAX : e;
 }
 
 // Make a value the compiler can prove wave-uniform (it is, by construction).
@@ -88,58 +90,318 @@ __global__ __launch_bounds__(256) void k_per_pair_fp64(
 }
 
 // ---------------------------------------------------------------- segmented (wave-uniform polygon)
-// One lane per pair.  Within a wavefront, the lanes that test the same polygon
-// run together: the polygon id of the first unfinished lane is broadcast
-// (readfirstlane), those lanes walk that ring with the vertex stream
-// wave-uniform (scalar loads, shared by all of them), then the next group
-// goes.  With pairs sorted by polygon a wavefront sees one or two groups.
-template <bool HAS_INDEX>
+// One lane per pair, U pairs per lane: a wavefront owns 64*U consecutive pairs
+// (row u holds pairs base + 64u + lane, so every load is coalesced) and issues
+// all of their loads before any arithmetic, to keep HBM busy.  Within a row,
+// the lanes that test the same polygon run together: the polygon id of the
+// first unfinished lane is broadcast (readfirstlane), those lanes walk that
+// ring with the vertex stream wave-uniform (scalar loads, 8 vertices per
+// batch, shared by all of them), then the next group goes.  With pairs sorted
+// by polygon a row sees one or two groups.
+
+// One edge step in lane-mask form, for a whole wavefront at once.  Every lane
+// runs it (uniform control flow); bit l of each mask belongs to lane l.
+//   ca/cb : lanes whose point is below a / b (a_y > p_y, b_y > p_y)
+//   st    : straddling lanes (exactly one endpoint above the ray)
+// The crossing test is (b above ? s' <= 0 : s' >= 0) with the unnegated normal
+// (see the note at the top of this file).  Returns the lanes whose crossing
+// count the edge increments; updates ca to cb.
+__device__ __forceinline__ uint64_t edge_step_mask(double x, double y, double ax, double ay, double bx, double by,
+                                                   uint64_t &ca)
+{
+    const uint64_t cb = __builtin_amdgcn_ballot_w64(by > y);
+    const uint64_t st = ca ^ cb;
+    const double nx = by - ay;
+    const double ny = ax - bx;
+    const double t1 = x - ax;
+    const double t2 = y - ay;
+    const double s = t1 * nx + t2 * ny;
+    const uint64_t le = __builtin_amdgcn_ballot_w64(s <= 0.0);
+    const uint64_t ge = __builtin_amdgcn_ballot_w64(s >= 0.0);
+    ca = cb;
+    return st & ((cb & le) | (~cb & ge));
+}
+
+// Walk ring [b, e) (wave-uniform, streamed through scalar loads) for every
+// lane's point; returns the lanes with an odd crossing count.  Must be called
+// with the whole wavefront active.
+__device__ __forceinline__ uint64_t ring_parity_uniform(double x, double y, const double *__restrict__ vx,
+                                                        const double *__restrict__ vy, int64_t b, int64_t e)
+{
+    // ring-relative 32-bit indices keep the loop control in scalar ALU
+    // instructions (gfx9 has no 64-bit scalar ordered compare)
+    const int k = (int)(e - b);
+    const double *__restrict__ rx = vx + b;
+    const double *__restrict__ ry = vy + b;
+    uint64_t par = 0;
+    if (k <= 0)
+        return 0;
+    double ax = rx[k - 1], ay = ry[k - 1];     // closing edge v_{k-1} -> v_0 first
+    uint64_t ca = __builtin_amdgcn_ballot_w64(ay > y);
+    for (int j0 = 0; j0 < k; j0 += 8) {
+        double bxs[8], bys[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int j = (j0 + t < k) ? j0 + t : k - 1;   // clamped: repeats v_{k-1}, a zero-length edge
+            bxs[t] = rx[j];
+            bys[t] = ry[j];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            par ^= edge_step_mask(x, y, ax, ay, bxs[t], bys[t], ca);
+            ax = bxs[t];
+            ay = bys[t];
+        }
+    }
+    return par;
+}
+
+template <bool HAS_INDEX, int U>
 __global__ __launch_bounds__(256) void k_segmented_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys,
     const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
     const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < n;
-    double x = 0.0, y = 0.0;
-    int q = 0;
-    if (valid) {
-        x = px[i];
-        y = py[i];
-        if (HAS_INDEX) {
-            q = point_poly[i];
-            q = ((uint32_t)q < (uint64_t)n_polys) ? q : 0;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t base = wave * (64 * U);
+    double x[U], y[U];
+    int q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = base + u * 64 + lane;
+        x[u] = 0.0;
+        y[u] = 0.0;
+        q[u] = 0;
+        if (i < n) {
+            x[u] = px[i];
+            y[u] = py[i];
+            if (HAS_INDEX)
+                q[u] = point_poly[i];
         }
     }
-    unsigned par = 0;
-    bool todo = valid;
-    while (todo) {
-        // Everything about the group's polygon is derived from the broadcast id
-        // before the divergent branch, so it stays in scalar registers.
-        const int qu = __builtin_amdgcn_readfirstlane(q);
-        int64_t b = offsets[qu], e = offsets[qu + 1];
-        clamp_ring(b, e, nv);
-        b = uniform64(b);
-        e = uniform64(e);
-        if (q == qu) {
-            todo = false;
-            if (e > b) {
-                double ax = vx[e - 1], ay = vy[e - 1];
-                bool a_above = ay > y;
-                for (int64_t j = b; j < e; ++j) {
-                    const double bx = vx[j], by = vy[j];
-                    const bool b_above = by > y;
-                    par ^= edge_cross(x, y, ax, ay, a_above, bx, by, b_above);
-                    ax = bx;
-                    ay = by;
-                    a_above = b_above;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = base + u * 64 + lane;
+        const bool valid = i < n;
+        if (HAS_INDEX)
+            q[u] = ((uint32_t)q[u] < (uint64_t)n_polys) ? q[u] : 0;
+        uint64_t todo = __builtin_amdgcn_ballot_w64(valid);
+        uint64_t par = 0;
+        while (todo) {
+            // Leader = first unfinished lane; its polygon is this round's group.
+            const int leader = __builtin_ctzll(todo);
+            const int qu = __builtin_amdgcn_readlane(q[u], leader);
+            int64_t b = offsets[qu], e = offsets[qu + 1];
+            clamp_ring(b, e, nv);
+            const uint64_t member = todo & __builtin_amdgcn_ballot_w64(q[u] == qu);
+            par |= ring_parity_uniform(x[u], y[u], vx, vy, b, e) & member;
+            todo &= ~member;
+        }
+        if (valid)
+            inside[i] = (uint8_t)((par >> lane) & 1u);
+    }
+}
+
+// ---------------------------------------------------------------- staged (rings in LDS, compacted side tests)
+// A workgroup owns 256*U consecutive pairs (thread t, row u: pair
+// base + 256u + t).  When the pairs are sorted by polygon, the rings they test
+// form one contiguous vertex range.  The workgroup stages it once in LDS as
+//   Y : per ring, y_{k-1}, y_0, .., y_{k-1}   (the straddle pass input)
+//   E : per edge j = (v_{j-1}, v_j), the record (a_x, a_y, n_x, n_y) with the
+//       normal n = (b_y - a_y, a_x - b_x) negated when n_x < 0, computed in
+//       binary64 exactly as the rule states (so the side value below is the
+//       rule's, bit for bit).
+// Each lane then runs two phases per 32-vertex chunk of its own ring:
+//   1. straddle pass: above_j = (y_j > p_y) for every vertex (one compare,
+//      exact), shifted into a 32-bit word; straddle bits = above XOR above
+//      shifted by one (half-open rule);
+//   2. side tests only for its straddling edges, taken one set bit at a time:
+//      s = (p_x - a_x) * n_x + (p_y - a_y) * n_y, crossing iff s <= 0.
+// Only about 2 of a footprint's edges straddle a given point, so phase 2 is
+// short; phase 1 costs two vector instructions per vertex.
+// A workgroup whose rings do not fit (or whose pairs are not sorted) falls
+// back to the scalar-load group walk.
+struct StageLayout {
+    int t_off;   // int   T[n_rings + 1]: ring start (edge index) relative to the range start
+    int y_off;   // double Y[n_edges + n_rings + pad]
+    int e_off;   // double4 E[n_edges]
+};
+
+template <int U>
+__global__ __launch_bounds__(256) void k_staged_fp64(
+    const double *__restrict__ px, const double *__restrict__ py, int64_t n,
+    const int64_t *__restrict__ offsets, int64_t n_polys,
+    const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
+    const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_kmax;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int64_t p0 = (int64_t)blockIdx.x * (256 * U);
+    const int ypad = 64;
+    const int y_alloc = max_edges + max_rings + ypad;
+
+    double x[U], y[U];
+    int q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = p0 + u * 256 + tid;
+        x[u] = 0.0;
+        y[u] = 0.0;
+        q[u] = -1;
+        if (i < n) {
+            x[u] = px[i];
+            y[u] = py[i];
+            q[u] = point_poly ? point_poly[i] : 0;
+        }
+    }
+
+    // polygon range of the workgroup, from its first and last pair (sorted input)
+    const int64_t plast = (p0 + 256 * U < n ? p0 + 256 * U : n) - 1;
+    int qf = 0, ql = 0;
+    if (point_poly) {
+        qf = point_poly[p0];
+        ql = point_poly[plast];
+    }
+    const bool range_ok = (uint32_t)qf < (uint64_t)n_polys && (uint32_t)ql < (uint64_t)n_polys && qf <= ql;
+    int64_t vb = 0, ve = 0;
+    if (range_ok) {
+        vb = offsets[qf];
+        ve = offsets[ql + 1];
+        clamp_ring(vb, ve, nv);
+    }
+    const int nr = ql - qf + 1;
+    bool mine_ok = true;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        mine_ok = mine_ok && (q[u] < 0 || (q[u] >= qf && q[u] <= ql));
+    const bool staged =
+        __syncthreads_and(range_ok && ve - vb <= max_edges && nr <= max_rings && mine_ok);
+
+    int *T = (int *)smem;
+    double *Y = (double *)(smem + (((max_rings + 1) * 4 + 15) & ~15));
+    double4 *E = (double4 *)((unsigned char *)Y + ((((int64_t)max_edges + max_rings + ypad) * 8 + 31) & ~31));
+
+    if (staged) {
+        if (tid == 0)
+            s_kmax = 0;
+        for (int r = tid; r <= nr; r += 256) {
+            int64_t o = offsets[qf + r];
+            o = o < vb ? vb : (o > ve ? ve : o);
+            T[r] = (int)(o - vb);
+        }
+        __syncthreads();
+        int kmax_local = 0;
+        for (int r = wid; r < nr; r += 4) {
+            const int e0 = T[r];
+            int e1 = T[r + 1];
+            e1 = e1 < e0 ? e0 : e1;
+            const int k = e1 - e0;
+            kmax_local = k > kmax_local ? k : kmax_local;
+            const int yb = e0 + r;
+            const double *__restrict__ rx = vx + vb + e0;
+            const double *__restrict__ ry = vy + vb + e0;
+            for (int j = lane; j < k; j += 64) {
+                const int jp = j == 0 ? k - 1 : j - 1;
+                const double ax = rx[jp], ay = ry[jp], bx = rx[j], by = ry[j];
+                double nx = by - ay;
+                double ny = ax - bx;
+                if (nx < 0.0) {
+                    nx = -nx;
+                    ny = -ny;
                 }
+                E[e0 + j] = make_double4(ax, ay, nx, ny);
+                Y[yb + 1 + j] = by;
+                if (j == k - 1)
+                    Y[yb] = by;
             }
         }
+        if (lane == 0)
+            atomicMax(&s_kmax, kmax_local);
+        const int ytot = (int)(ve - vb) + nr;
+        if (tid < ypad)
+            Y[ytot + tid] = 0.0;
+        __syncthreads();
+        const int kmax_b = s_kmax;
+
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = (q[u] < 0 ? qf : q[u]) - qf;
+            const int e0 = T[r];
+            int k = T[r + 1] - e0;
+            k = k < 0 ? 0 : k;
+            const int yb = e0 + r;
+            const double xu = x[u], yu = y[u];
+            uint64_t par = 0;
+            // anchor: above bit of v_{k-1}
+            uint32_t above_prev = (k > 0 && Y[yb] > yu) ? 1u : 0u;
+            for (int c0 = 0; c0 < kmax_b; c0 += 32) {
+                if (__builtin_amdgcn_ballot_w64(k > c0) == 0)
+                    break;
+                // phase 1: above bits of vertices c0 .. c0+31, first vertex in bit 31
+                uint32_t above = 0;
+                // Lanes whose ring ended read past it (their bits are masked
+                // below); the clamp keeps those reads inside the Y allocation.
+                // A lane still inside its ring is never clamped: its chunk
+                // starts at most at the last staged slot, 64 slots before the end.
+                const int ybase = yb + 1 + c0;
+                const double *yr = Y + (ybase < y_alloc - 32 ? ybase : y_alloc - 32);
+                int t = 0;
+                for (; t < 32; t += 4) {
+                    if (__builtin_amdgcn_ballot_w64(k > c0 + t) == 0)
+                        break;
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt)
+                        above = (above << 1) | (yr[t + tt] > yu ? 1u : 0u);
+                }
+                above = t < 32 ? above << (32 - t) : above;
+                uint32_t strad = above ^ ((above >> 1) | (above_prev << 31));
+                const int rem = k - c0;
+                if (rem < 32)
+                    strad &= rem <= 0 ? 0u : ~(0xffffffffu >> rem);
+                above_prev = rem >= 32 ? (above & 1u) : above_prev;
+                // phase 2: side tests for this lane's straddling edges only
+                const double4 *er = E + e0 + c0;
+                while (strad != 0) {
+                    const int j = __builtin_clz(strad);
+                    strad ^= 0x80000000u >> j;
+                    const double4 rec = er[j];
+                    const double t1 = xu - rec.x;
+                    const double t2 = yu - rec.y;
+                    const double sv = t1 * rec.z + t2 * rec.w;
+                    par ^= __builtin_amdgcn_ballot_w64(sv <= 0.0);
+                }
+            }
+            const int64_t i = p0 + u * 256 + tid;
+            if (i < n)
+                inside[i] = (uint8_t)((par >> lane) & 1u);
+        }
+        return;
     }
-    if (valid)
-        inside[i] = (uint8_t)par;
+
+    // fallback: groups of lanes sharing a polygon, ring streamed through scalar loads
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = p0 + u * 256 + tid;
+        const int qv = ((uint32_t)q[u] < (uint64_t)n_polys) ? q[u] : 0;
+        uint64_t todo = __builtin_amdgcn_ballot_w64(i < n);
+        uint64_t par = 0;
+        while (todo) {
+            const int leader = __builtin_ctzll(todo);
+            const int qu = __builtin_amdgcn_readlane(qv, leader);
+            int64_t b = offsets[qu], e = offsets[qu + 1];
+            clamp_ring(b, e, nv);
+            const uint64_t member = todo & __builtin_amdgcn_ballot_w64(qv == qu);
+            par |= ring_parity_uniform(x[u], y[u], vx, vy, b, e) & member;
+            todo &= ~member;
+        }
+        if (i < n)
+            inside[i] = (uint8_t)((par >> lane) & 1u);
+    }
 }
 
 // ---------------------------------------------------------------- validation
@@ -203,17 +465,65 @@ int launch_per_pair(const Problem &p, hipStream_t stream)
     return PIP_OK;
 }
 
-int launch_segmented(const Problem &p, hipStream_t stream)
+template <int U>
+static int launch_segmented_u(const Problem &p, hipStream_t stream, int block)
 {
-    const dim3 grid(grid_for(p.n_points, 256)), block(256);
+    const int64_t per_block = (int64_t)block * U;
+    const dim3 grid(grid_for(p.n_points, (int)per_block)), blk(block);
     if (p.point_poly)
-        hipLaunchKernelGGL(k_segmented_fp64<true>, grid, block, 0, stream, p.px, p.py, p.n_points, p.offsets,
+        hipLaunchKernelGGL((k_segmented_fp64<true, U>), grid, blk, 0, stream, p.px, p.py, p.n_points, p.offsets,
                            p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside);
     else
-        hipLaunchKernelGGL(k_segmented_fp64<false>, grid, block, 0, stream, p.px, p.py, p.n_points, p.offsets,
-                           p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside);
+        hipLaunchKernelGGL((k_segmented_fp64<false, U>), grid, blk, 0, stream, p.px, p.py, p.n_points,
+                           p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside);
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
+}
+
+int launch_segmented(const Problem &p, hipStream_t stream, int pairs_per_lane, int block)
+{
+    if (block != 64 && block != 128 && block != 256)
+        block = 256;
+    switch (pairs_per_lane) {
+    case 1: return launch_segmented_u<1>(p, stream, block);
+    case 2: return launch_segmented_u<2>(p, stream, block);
+    case 8: return launch_segmented_u<8>(p, stream, block);
+    default: return launch_segmented_u<4>(p, stream, block);
+    }
+}
+
+static size_t staged_smem_bytes(int max_edges, int max_rings)
+{
+    const size_t t = (((size_t)(max_rings + 1) * 4 + 15) & ~(size_t)15);
+    const size_t yb = ((((size_t)max_edges + max_rings + 64) * 8 + 31) & ~(size_t)31);
+    return t + yb + (size_t)max_edges * 32;
+}
+
+template <int U>
+static int launch_staged_u(const Problem &p, hipStream_t stream, int max_edges)
+{
+    const int64_t per_block = 256LL * U;
+    const int max_rings = 256 * U < 128 ? 256 * U : 128;
+    const size_t shmem = staged_smem_bytes(max_edges, max_rings);
+    hipLaunchKernelGGL((k_staged_fp64<U>), dim3(grid_for(p.n_points, (int)per_block)), dim3(256), shmem, stream,
+                       p.px, p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly,
+                       p.inside, max_edges, max_rings);
+    PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
+
+int launch_staged(const Problem &p, hipStream_t stream, int pairs_per_lane, int lds_slots)
+{
+    // lds_slots = edges a workgroup can stage (40 bytes each in LDS)
+    if (lds_slots <= 0)
+        lds_slots = 256;
+    if (lds_slots > 2048)
+        lds_slots = 2048;
+    switch (pairs_per_lane) {
+    case 1: return launch_staged_u<1>(p, stream, lds_slots);
+    case 4: return launch_staged_u<4>(p, stream, lds_slots);
+    default: return launch_staged_u<2>(p, stream, lds_slots);
+    }
 }
 
 int launch_validate(const Problem &p, unsigned *flags, hipStream_t stream)

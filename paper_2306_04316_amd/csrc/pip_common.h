@@ -54,7 +54,8 @@ int validate_on_device(const Problem &p, DeviceInfo *dev, hipStream_t stream);
 
 // ---------------------------------------------------------------- kernel launchers (exact binary64)
 int launch_per_pair(const Problem &p, hipStream_t stream);
-int launch_segmented(const Problem &p, hipStream_t stream);
+int launch_segmented(const Problem &p, hipStream_t stream, int pairs_per_lane, int block);
+int launch_staged(const Problem &p, hipStream_t stream, int pairs_per_lane, int lds_slots);
 int launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t stream);
 int launch_validate(const Problem &p, unsigned *flags, hipStream_t stream);
 

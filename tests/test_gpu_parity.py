@@ -15,7 +15,7 @@ from paper_2306_04316_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = ["per_pair", "segmented"]
+KERNELS = ["per_pair", "segmented", "staged"]
 
 
 @pytest.fixture(scope="module")
@@ -69,11 +69,11 @@ def test_stress_small(P, kernel):
 
 
 def test_batched_full(P):
-    check(P, W.batched(), "segmented", "batched full")
+    check(P, W.batched(), "staged", "batched full")
 
 
 def test_stress_full(P):
-    check(P, W.stress(), "segmented", "stress full")
+    check(P, W.stress(), "staged", "stress full")
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
