@@ -109,9 +109,53 @@ typedef struct {
     int32_t validate;       /* 1: check the data on the device first (synchronises) */
     int32_t pairs_per_lane; /* tuning, segmented kernel: pairs per lane (1, 2, 4, 8); 0 = default */
     int32_t block;          /* tuning: threads per workgroup (64, 128, 256); 0 = default */
-    int32_t lds_slots;      /* tuning, staged kernel: LDS vertex slots per workgroup
-                               (16 bytes each, at most 8192); 0 = default */
+    int32_t lds_slots;      /* tuning, staged kernel: edges a workgroup can stage in
+                               LDS (40 bytes each exact, 20 filtered; at most 2048);
+                               0 = default */
+    int32_t persistent;     /* plans: 1 = a resident grid pulls work items from an
+                               atomic queue, 0 = one workgroup per item,
+                               -1 = automatic */
+    int32_t order;          /* plans: 1 = items heaviest first (estimated edges x
+                               pairs), 0 = natural order, -1 = automatic */
+    int32_t use_graph;      /* plans: 1 = capture the step sequence in a HIP graph */
+    int32_t tune;           /* plans: 0 = no tuning; n > 0 = time the candidate
+                               configurations on the plan's data at creation (n
+                               timed runs each, n = 1 means 5) and keep the fastest */
+    int32_t force_recheck;  /* filtered mode, for testing: re-run every pair in
+                               binary64 (results are unchanged) */
+    float bound_scale;      /* filtered mode, for testing only: multiplies the proven
+                               error bound; 1 is the only value that guarantees
+                               bit-exact results (0 disables the bound) */
+    const char *tune_cache; /* plans: tuning cache file; NULL = environment variable
+                               PIP_TUNE_CACHE, else no cache */
 } pip_options;
+
+/* Configuration a plan runs with (after automatic choices and tuning). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t mode;
+    int32_t kernel;
+    int32_t pairs_per_lane;
+    int32_t lds_slots;
+    int32_t persistent;
+    int32_t order;
+    int32_t use_graph;      /* 1 if executions are graph launches */
+    int32_t grid;           /* workgroups of the main kernel */
+    int32_t n_items;        /* work items (256 * pairs_per_lane pairs each) */
+    int32_t tuned;          /* 0 = defaults/options, 1 = autotuned now, 2 = from the cache */
+    float tune_ms;          /* tuned step time (ms), when tuned */
+} pip_plan_config;
+
+/* Figures of a plan's last execution (see pip_plan_stats). */
+typedef struct {
+    uint64_t pairs;             /* pairs the plan classifies */
+    uint64_t rechecked_pairs;   /* pairs re-run in binary64 (filtered mode) */
+    float ms_prep;              /* device time: counter resets and item ordering */
+    float ms_main;              /* device time: main kernel */
+    float ms_recheck;           /* device time: binary64 recheck (filtered mode) */
+} pip_stats;
+
+typedef struct pip_plan pip_plan;
 
 /* Fills *opts with the defaults (exact binary64, automatic kernel, no validation). */
 PIP_API void pip_options_init(pip_options *opts);
@@ -127,12 +171,49 @@ PIP_API const char *pip_last_error(void);
  * (defaults).  n_points == 0 is a no-op.  Only PIP_MODE_EXACT_FP64 is
  * accepted here (the filtered mode needs a plan's workspace).  Allocates
  * nothing on the device.  Asynchronous on `stream` unless opts->validate.
+ * The plan-only options (persistent, order, use_graph, tune, tune_cache) are
+ * ignored here.
  */
 PIP_API int pip_classify(const double *px, const double *py, int64_t n_points,
                  const int64_t *offsets, int64_t n_polys,
                  const double *vx, const double *vy, int64_t n_vertices,
                  const int32_t *point_poly, uint8_t *inside,
                  const pip_options *opts, void *stream);
+
+/*
+ * Plans: prepare a repeatable classification of fixed device buffers (the
+ * arguments are those of pip_classify).  The plan owns a device workspace
+ * (allocated here, released by pip_plan_destroy: a few bytes per pair) and,
+ * with use_graph, a HIP graph of its step sequence:
+ *   counter resets -> work-item ordering -> main kernel -> binary64 recheck
+ * so that pip_plan_execute is one graph launch.  Both modes are accepted;
+ * the filtered mode (PIP_MODE_FILTERED_FP32) evaluates in binary32 with a
+ * proven error bound and re-runs undecided pairs in binary64, with the same
+ * bits as the exact mode.  With tune, creation times candidate
+ * configurations on the given data (this runs the classification several
+ * times on `stream` and waits for it).  The plan reads the buffers' contents
+ * at each execution, so new data in the same buffers needs no new plan; new
+ * buffer addresses do.  A plan belongs to the device current at creation.
+ * Executions of one plan must not overlap (they share its workspace).
+ */
+PIP_API int pip_plan_create(pip_plan **out,
+                    const double *px, const double *py, int64_t n_points,
+                    const int64_t *offsets, int64_t n_polys,
+                    const double *vx, const double *vy, int64_t n_vertices,
+                    const int32_t *point_poly, uint8_t *inside,
+                    const pip_options *opts, void *stream);
+
+/* Enqueue one execution on `stream` (asynchronous). */
+PIP_API int pip_plan_execute(pip_plan *plan, void *stream);
+
+/* Waits for the plan's last execution and reports its figures. */
+PIP_API int pip_plan_stats(pip_plan *plan, pip_stats *stats);
+
+/* The configuration the plan runs with. */
+PIP_API int pip_plan_get_config(const pip_plan *plan, pip_plan_config *cfg);
+
+/* Waits for the device, then releases the plan's workspace and graph. NULL is a no-op. */
+PIP_API int pip_plan_destroy(pip_plan *plan);
 
 /*
  * Diagnostic: copy nbytes (a multiple of 16) from src to dst with a plain

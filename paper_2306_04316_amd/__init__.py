@@ -17,7 +17,7 @@ import ctypes
 from . import _lib
 from ._lib import PipError  # noqa: F401
 
-__all__ = ["classify", "PipError", "abi_version", "probe_copy", "to_device"]
+__all__ = ["classify", "Plan", "PipError", "abi_version", "probe_copy", "to_device"]
 
 
 def _require(t, dtype, name, numel=None):
@@ -45,7 +45,9 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block=0, lds_slots=0) -> _lib.pip_options:
+def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block=0, lds_slots=0,
+            persistent=-1, order=-1, use_graph=True, tune=0, force_recheck=False, bound_scale=1.0,
+            tune_cache=None) -> _lib.pip_options:
     o = _lib.pip_options()
     _lib.load().pip_options_init(ctypes.byref(o))
     o.mode = _lib.MODES[mode] if isinstance(mode, str) else int(mode)
@@ -54,14 +56,18 @@ def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block
     o.pairs_per_lane = int(pairs_per_lane)
     o.block = int(block)
     o.lds_slots = int(lds_slots)
+    o.persistent = int(persistent)
+    o.order = int(order)
+    o.use_graph = 1 if use_graph else 0
+    o.tune = int(tune)
+    o.force_recheck = 1 if force_recheck else 0
+    o.bound_scale = float(bound_scale)
+    o.tune_cache = tune_cache.encode() if tune_cache else None
     return o
 
 
-def classify(px, py, offsets, vx, vy, point_poly=None, *, kernel="auto", validate=False, out=None,
-             stream=None, pairs_per_lane=0, block=0, lds_slots=0):
-    """inside[i] for point i against polygon point_poly[i] (or polygon 0)."""
+def _check_inputs(px, py, offsets, vx, vy, point_poly, out):
     import torch
-    lib = _lib.load()
     n = px.numel()
     _require(px, torch.float64, "px")
     _require(py, torch.float64, "py", n)
@@ -74,6 +80,68 @@ def classify(px, py, offsets, vx, vy, point_poly=None, *, kernel="auto", validat
         out = torch.empty(n, dtype=torch.uint8, device=px.device)
     else:
         _require(out, torch.uint8, "out", n)
+    return out
+
+
+class Plan:
+    """A prepared classification of fixed device tensors (pip_plan_* in the C ABI).
+
+    plan = Plan(px, py, offsets, vx, vy, point_poly, mode="filtered", tune=1)
+    plan.execute()          # enqueue on the current stream; result in plan.out
+    plan.stats()            # waits; figures of the last execution
+    The tensors must stay alive (and at the same addresses) while the plan exists.
+    """
+
+    def __init__(self, px, py, offsets, vx, vy, point_poly=None, *, out=None, stream=None, **opts):
+        import torch
+        self._lib = _lib.load()
+        self.out = _check_inputs(px, py, offsets, vx, vy, point_poly, out)
+        self._keep = (px, py, offsets, vx, vy, point_poly, self.out)
+        self._opts = options(**opts)
+        self.device = px.device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(px.device):
+            rc = self._lib.pip_plan_create(ctypes.byref(h), _ptr(px), _ptr(py), px.numel(), _ptr(offsets),
+                                           offsets.numel() - 1, _ptr(vx), _ptr(vy), vx.numel(), _ptr(point_poly),
+                                           _ptr(self.out), ctypes.byref(self._opts), _stream_handle(stream))
+        _lib.check(rc)
+        self._h = h
+
+    def execute(self, stream=None):
+        import torch
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.pip_plan_execute(self._h, _stream_handle(stream)))
+        return self.out
+
+    def stats(self) -> dict:
+        st = _lib.pip_stats()
+        _lib.check(self._lib.pip_plan_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _lib.pip_stats._fields_}
+
+    def config(self) -> dict:
+        c = _lib.pip_plan_config()
+        _lib.check(self._lib.pip_plan_get_config(self._h, ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in _lib.pip_plan_config._fields_ if f != "struct_size"}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.check(self._lib.pip_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def classify(px, py, offsets, vx, vy, point_poly=None, *, kernel="auto", validate=False, out=None,
+             stream=None, pairs_per_lane=0, block=0, lds_slots=0):
+    """inside[i] for point i against polygon point_poly[i] (or polygon 0)."""
+    import torch
+    lib = _lib.load()
+    n = px.numel()
+    out = _check_inputs(px, py, offsets, vx, vy, point_poly, out)
     o = options("exact", kernel, validate, pairs_per_lane, block, lds_slots)
     with torch.cuda.device(px.device):
         rc = lib.pip_classify(_ptr(px), _ptr(py), n, _ptr(offsets), offsets.numel() - 1, _ptr(vx), _ptr(vy),

@@ -24,7 +24,21 @@ class PipError(RuntimeError):
 class pip_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("mode", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("pairs_per_lane", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("lds_slots", ctypes.c_int32)]
+                ("lds_slots", ctypes.c_int32), ("persistent", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("tune", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
+                ("bound_scale", ctypes.c_float), ("tune_cache", ctypes.c_char_p)]
+
+
+class pip_plan_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("mode", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("pairs_per_lane", ctypes.c_int32), ("lds_slots", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("n_items", ctypes.c_int32), ("tuned", ctypes.c_int32), ("tune_ms", ctypes.c_float)]
+
+
+class pip_stats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_uint64), ("rechecked_pairs", ctypes.c_uint64), ("ms_prep", ctypes.c_float),
+                ("ms_main", ctypes.c_float), ("ms_recheck", ctypes.c_float)]
 
 
 _VP = ctypes.c_void_p
@@ -37,6 +51,12 @@ _SIGS = {
     "pip_classify": (ctypes.c_int, [_VP, _VP, _I64, _VP, _I64, _VP, _VP, _I64, _VP, _VP,
                                     ctypes.POINTER(pip_options), _VP]),
     "pip_probe_copy": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
+    "pip_plan_create": (ctypes.c_int, [ctypes.POINTER(_VP), _VP, _VP, _I64, _VP, _I64, _VP, _VP, _I64, _VP, _VP,
+                                       ctypes.POINTER(pip_options), _VP]),
+    "pip_plan_execute": (ctypes.c_int, [_VP, _VP]),
+    "pip_plan_stats": (ctypes.c_int, [_VP, ctypes.POINTER(pip_stats)]),
+    "pip_plan_get_config": (ctypes.c_int, [_VP, ctypes.POINTER(pip_plan_config)]),
+    "pip_plan_destroy": (ctypes.c_int, [_VP]),
 }
 
 _lib = None

@@ -46,6 +46,7 @@ int current_device(DeviceInfo **out)
         d->device = dev;
         d->cu_count = prop.multiProcessorCount;
         d->gfx950 = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        d->lds_per_block = prop.sharedMemPerBlock > 1024 ? prop.sharedMemPerBlock - 1024 : prop.sharedMemPerBlock;
         void *sym = nullptr;
         hipError_t e = hipGetSymbolAddress(&sym, HIP_SYMBOL(g_validate_word));
         if (e != hipSuccess) {
@@ -59,6 +60,16 @@ int current_device(DeviceInfo **out)
         return fail(PIP_ENOTSUP, "device %d is not gfx950", dev);
     *out = g_devs[dev];
     return PIP_OK;
+}
+
+int clamp_lds_slots(int lds_slots, bool filtered, int pairs_per_lane, const DeviceInfo *dev)
+{
+    lds_slots = lds_slots < 16 ? 16 : (lds_slots > 2048 ? 2048 : lds_slots);
+    const int rings = staged_max_rings(pairs_per_lane);
+    while (lds_slots > 16 && (filtered ? filtered_smem_bytes(lds_slots, rings) : staged_smem_bytes(lds_slots, rings)) >
+                                 dev->lds_per_block)
+        lds_slots /= 2;
+    return lds_slots;
 }
 
 int check_host_args(const Problem &p)
@@ -108,6 +119,13 @@ void pip_options_init(pip_options *opts)
     opts->mode = PIP_MODE_EXACT_FP64;
     opts->kernel = PIP_KERNEL_AUTO;
     opts->validate = 0;
+    opts->persistent = -1;
+    opts->order = -1;
+    opts->use_graph = 1;
+    opts->tune = 0;
+    opts->force_recheck = 0;
+    opts->bound_scale = 1.0f;
+    opts->tune_cache = NULL;
 }
 
 int pip_abi_version(void) { return PIP_ABI_VERSION; }
@@ -144,7 +162,8 @@ int pip_classify(const double *px, const double *py, int64_t n_points, const int
         return launch_per_pair(p, s);
     if (o.kernel == PIP_KERNEL_SEGMENTED)
         return launch_segmented(p, s, o.pairs_per_lane, o.block);
-    return launch_staged(p, s, o.pairs_per_lane, o.lds_slots);
+    const int ppl = o.pairs_per_lane > 0 ? o.pairs_per_lane : 4;
+    return launch_staged(p, s, ppl, clamp_lds_slots(o.lds_slots > 0 ? o.lds_slots : 256, false, ppl, dev));
 }
 
 int pip_probe_copy(void *dst, const void *src, int64_t nbytes, void *stream)

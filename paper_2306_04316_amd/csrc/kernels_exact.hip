@@ -1,59 +1,15 @@
-// Exact binary64 kernels for the constraint-1 ray-casting test.
-//
-// Per edge (a, b) of a ring and point p (paper, Method section, constraint 1;
-// Algorithm 1, with the half-open straddle reading):
-//   straddle  : (a_y > p_y) != (b_y > p_y)                 comparisons only, exact
-//   normal    : n = (b_y - a_y, a_x - b_x), negated when n_x < 0
-//   side      : s = (p_x - a_x) * n_x + (p_y - a_y) * n_y  each op rounded (no FMA)
-//   crossing  : s <= 0
-// Parity of the crossing count gives the inside bit.
-//
-// The negation of n is never materialised: with round-to-nearest-even,
-// fl(t * (-d)) = -fl(t * d) and fl(-u - v) = -fl(u + v), so the side value with
-// the negated normal is exactly -s' where s' uses the unnegated normal.  Under
-// the straddle condition n_x < 0 holds exactly when a is the endpoint above the
-// ray, so the crossing test becomes (b above ? s' <= 0 : s' >= 0).  Both tests
-// treat +0 and -0 alike, so the bit is the same as the literal rule's.
+// Exact binary64 kernels for the constraint-1 ray-casting test (paper,
+// Method section, constraint 1, and Algorithm 1, half-open straddle reading):
+// the plain per-pair baseline, the wave-segmented kernel, and the staged
+// kernel with rings in LDS.  The per-edge arithmetic is in ring_walk.h.
 //
 // This translation unit must be compiled with -ffp-contract=off.
 
 #include "pip_common.h"
+#include "ring_walk.h"
 
 namespace pip {
 namespace {
-
-// Clamp a ring's [b, e) to the vertex array so no access leaves it, and to
-// at most INT32_MAX vertices per ring.
-__device__ __forceinline__ void clamp_ring(int64_t &b, int64_t &e, int64_t nv)
-{
-    e = e < 0 ? 0 : (e > nv ? nv : e);
-    b = b < 0 ? 0 : (b > e ? e : b);
-    e = (e - b > INT32_MAX) ? b + INT32_MAX : e;
-}
-
-// Make a value the compiler can prove wave-uniform (it is, by construction).
-__device__ __forceinline__ int64_t uniform64(int64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// Crossing-parity contribution of edge (a, b) for point (x, y).
-__device__ __forceinline__ unsigned edge_cross(double x, double y, double ax, double ay, bool a_above,
-                                               double bx, double by, bool b_above)
-{
-    unsigned c = 0;
-    if (a_above != b_above) {
-        const double nx = by - ay;
-        const double ny = ax - bx;
-        const double t1 = x - ax;
-        const double t2 = y - ay;
-        const double s = t1 * nx + t2 * ny;
-        c = b_above ? (s <= 0.0) : (s >= 0.0);
-    }
-    return c;
-}
 
 // ---------------------------------------------------------------- plain per-pair baseline
 // One lane per pair.  Each lane walks its own polygon's ring with ordinary
@@ -99,63 +55,6 @@ __global__ __launch_bounds__(256) void k_per_pair_fp64(
 // batch, shared by all of them), then the next group goes.  With pairs sorted
 // by polygon a row sees one or two groups.
 
-// One edge step in lane-mask form, for a whole wavefront at once.  Every lane
-// runs it (uniform control flow); bit l of each mask belongs to lane l.
-//   ca/cb : lanes whose point is below a / b (a_y > p_y, b_y > p_y)
-//   st    : straddling lanes (exactly one endpoint above the ray)
-// The crossing test is (b above ? s' <= 0 : s' >= 0) with the unnegated normal
-// (see the note at the top of this file).  Returns the lanes whose crossing
-// count the edge increments; updates ca to cb.
-__device__ __forceinline__ uint64_t edge_step_mask(double x, double y, double ax, double ay, double bx, double by,
-                                                   uint64_t &ca)
-{
-    const uint64_t cb = __builtin_amdgcn_ballot_w64(by > y);
-    const uint64_t st = ca ^ cb;
-    const double nx = by - ay;
-    const double ny = ax - bx;
-    const double t1 = x - ax;
-    const double t2 = y - ay;
-    const double s = t1 * nx + t2 * ny;
-    const uint64_t le = __builtin_amdgcn_ballot_w64(s <= 0.0);
-    const uint64_t ge = __builtin_amdgcn_ballot_w64(s >= 0.0);
-    ca = cb;
-    return st & ((cb & le) | (~cb & ge));
-}
-
-// Walk ring [b, e) (wave-uniform, streamed through scalar loads) for every
-// lane's point; returns the lanes with an odd crossing count.  Must be called
-// with the whole wavefront active.
-__device__ __forceinline__ uint64_t ring_parity_uniform(double x, double y, const double *__restrict__ vx,
-                                                        const double *__restrict__ vy, int64_t b, int64_t e)
-{
-    // ring-relative 32-bit indices keep the loop control in scalar ALU
-    // instructions (gfx9 has no 64-bit scalar ordered compare)
-    const int k = (int)(e - b);
-    const double *__restrict__ rx = vx + b;
-    const double *__restrict__ ry = vy + b;
-    uint64_t par = 0;
-    if (k <= 0)
-        return 0;
-    double ax = rx[k - 1], ay = ry[k - 1];     // closing edge v_{k-1} -> v_0 first
-    uint64_t ca = __builtin_amdgcn_ballot_w64(ay > y);
-    for (int j0 = 0; j0 < k; j0 += 8) {
-        double bxs[8], bys[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int j = (j0 + t < k) ? j0 + t : k - 1;   // clamped: repeats v_{k-1}, a zero-length edge
-            bxs[t] = rx[j];
-            bys[t] = ry[j];
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            par ^= edge_step_mask(x, y, ax, ay, bxs[t], bys[t], ca);
-            ax = bxs[t];
-            ay = bys[t];
-        }
-    }
-    return par;
-}
-
 template <bool HAS_INDEX, int U>
 __global__ __launch_bounds__(256) void k_segmented_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
@@ -196,7 +95,7 @@ __global__ __launch_bounds__(256) void k_segmented_fp64(
             int64_t b = offsets[qu], e = offsets[qu + 1];
             clamp_ring(b, e, nv);
             const uint64_t member = todo & __builtin_amdgcn_ballot_w64(q[u] == qu);
-            par |= ring_parity_uniform(x[u], y[u], vx, vy, b, e) & member;
+            par |= ring_parity_compact_uniform(x[u], y[u], (member >> lane) & 1u, vx, vy, b, e) & member;
             todo &= ~member;
         }
         if (valid)
@@ -229,22 +128,21 @@ struct StageLayout {
     int e_off;   // double4 E[n_edges]
 };
 
+// Classify the 256*U pairs starting at p0 (one workgroup, 256 threads).
+// smem: dynamic LDS of staged_smem_bytes(max_edges, max_rings) bytes.
 template <int U>
-__global__ __launch_bounds__(256) void k_staged_fp64(
-    const double *__restrict__ px, const double *__restrict__ py, int64_t n,
+__device__ __forceinline__ void staged_item_fp64(
+    int64_t p0, const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys,
     const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
-    const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings)
+    const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
+    unsigned char *smem, int *s_kmax)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_kmax;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
-    const int64_t p0 = (int64_t)blockIdx.x * (256 * U);
     const int ypad = 64;
     const int y_alloc = max_edges + max_rings + ypad;
-
     double x[U], y[U];
     int q[U];
 #pragma unroll
@@ -288,7 +186,7 @@ __global__ __launch_bounds__(256) void k_staged_fp64(
 
     if (staged) {
         if (tid == 0)
-            s_kmax = 0;
+            *s_kmax = 0;
         for (int r = tid; r <= nr; r += 256) {
             int64_t o = offsets[qf + r];
             o = o < vb ? vb : (o > ve ? ve : o);
@@ -321,12 +219,12 @@ __global__ __launch_bounds__(256) void k_staged_fp64(
             }
         }
         if (lane == 0)
-            atomicMax(&s_kmax, kmax_local);
+            atomicMax(s_kmax, kmax_local);
         const int ytot = (int)(ve - vb) + nr;
         if (tid < ypad)
             Y[ytot + tid] = 0.0;
         __syncthreads();
-        const int kmax_b = s_kmax;
+        const int kmax_b = *s_kmax;
 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -336,6 +234,7 @@ __global__ __launch_bounds__(256) void k_staged_fp64(
             k = k < 0 ? 0 : k;
             const int yb = e0 + r;
             const double xu = x[u], yu = y[u];
+            const double yq = yu + 0.0;
             uint64_t par = 0;
             // anchor: above bit of v_{k-1}
             uint32_t above_prev = (k > 0 && Y[yb] > yu) ? 1u : 0u;
@@ -356,7 +255,7 @@ __global__ __launch_bounds__(256) void k_staged_fp64(
                         break;
 #pragma unroll
                     for (int tt = 0; tt < 4; ++tt)
-                        above = (above << 1) | (yr[t + tt] > yu ? 1u : 0u);
+                        above = shift_in_above(above, yq, yr[t + tt]);
                 }
                 above = t < 32 ? above << (32 - t) : above;
                 uint32_t strad = above ^ ((above >> 1) | (above_prev << 31));
@@ -384,23 +283,42 @@ __global__ __launch_bounds__(256) void k_staged_fp64(
     }
 
     // fallback: groups of lanes sharing a polygon, ring streamed through scalar loads
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t i = p0 + u * 256 + tid;
-        const int qv = ((uint32_t)q[u] < (uint64_t)n_polys) ? q[u] : 0;
-        uint64_t todo = __builtin_amdgcn_ballot_w64(i < n);
-        uint64_t par = 0;
-        while (todo) {
-            const int leader = __builtin_ctzll(todo);
-            const int qu = __builtin_amdgcn_readlane(qv, leader);
-            int64_t b = offsets[qu], e = offsets[qu + 1];
-            clamp_ring(b, e, nv);
-            const uint64_t member = todo & __builtin_amdgcn_ballot_w64(qv == qu);
-            par |= ring_parity_uniform(x[u], y[u], vx, vy, b, e) & member;
-            todo &= ~member;
-        }
-        if (i < n)
-            inside[i] = (uint8_t)((par >> lane) & 1u);
+    group_walk_rows<U>(p0, x, y, q, n, offsets, n_polys, vx, vy, nv, inside);
+}
+
+// Batched form.  With a queue, a grid sized to the resident capacity pulls
+// items (blocks of 256*U pairs) from an atomic counter in the order given by
+// `order` (heaviest first; NULL = natural order) until the list is exhausted.
+// Without a queue, workgroup b takes item order[b] (or b).
+template <int U>
+__global__ __launch_bounds__(256) void k_staged_batched_fp64(
+    const double *__restrict__ px, const double *__restrict__ py, int64_t n,
+    const int64_t *__restrict__ offsets, int64_t n_polys,
+    const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
+    const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
+    const int32_t *__restrict__ order, int n_items, unsigned *queue)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_kmax;
+    __shared__ int s_item;
+    if (!queue) {
+        const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
+        staged_item_fp64<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly,
+                            inside, max_edges, max_rings, smem, &s_kmax);
+        return;
+    }
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items)
+            break;
+        const int item = order ? order[it] : it;
+        staged_item_fp64<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly,
+                            inside, max_edges, max_rings, smem, &s_kmax);
+        __syncthreads();
     }
 }
 
@@ -492,38 +410,69 @@ int launch_segmented(const Problem &p, hipStream_t stream, int pairs_per_lane, i
     }
 }
 
-static size_t staged_smem_bytes(int max_edges, int max_rings)
+size_t staged_smem_bytes(int max_edges, int max_rings)
 {
     const size_t t = (((size_t)(max_rings + 1) * 4 + 15) & ~(size_t)15);
     const size_t yb = ((((size_t)max_edges + max_rings + 64) * 8 + 31) & ~(size_t)31);
     return t + yb + (size_t)max_edges * 32;
 }
 
-template <int U>
-static int launch_staged_u(const Problem &p, hipStream_t stream, int max_edges)
+int staged_max_rings(int pairs_per_lane)
 {
-    const int64_t per_block = 256LL * U;
-    const int max_rings = 256 * U < 128 ? 256 * U : 128;
+    const int u = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
+    return 256 * u < 128 ? 256 * u : 128;
+}
+
+int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_lane, int max_edges,
+                          const int32_t *order, int n_items, unsigned *queue, int grid)
+{
+    const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
+    const int max_rings = staged_max_rings(U);
     const size_t shmem = staged_smem_bytes(max_edges, max_rings);
-    hipLaunchKernelGGL((k_staged_fp64<U>), dim3(grid_for(p.n_points, (int)per_block)), dim3(256), shmem, stream,
-                       p.px, p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly,
-                       p.inside, max_edges, max_rings);
+    if (!queue)
+        grid = n_items;
+    if (grid <= 0)
+        return PIP_OK;
+#define PIP_LAUNCH_S(UU)                                                                                         \
+    hipLaunchKernelGGL((k_staged_batched_fp64<UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,            \
+                       p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside,        \
+                       max_edges, max_rings, order, n_items, queue)
+    if (U == 1)
+        PIP_LAUNCH_S(1);
+    else if (U == 4)
+        PIP_LAUNCH_S(4);
+    else
+        PIP_LAUNCH_S(2);
+#undef PIP_LAUNCH_S
     PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
+
+int staged_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu)
+{
+    const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
+    const size_t shmem = staged_smem_bytes(max_edges, staged_max_rings(U));
+    int nb = 0;
+    hipError_t e;
+    if (U == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<1>, 256, shmem);
+    else if (U == 4)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<4>, 256, shmem);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<2>, 256, shmem);
+    if (e != hipSuccess)
+        return fail(PIP_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
+    *blocks_per_cu = nb < 1 ? 1 : nb;
     return PIP_OK;
 }
 
 int launch_staged(const Problem &p, hipStream_t stream, int pairs_per_lane, int lds_slots)
 {
-    // lds_slots = edges a workgroup can stage (40 bytes each in LDS)
-    if (lds_slots <= 0)
-        lds_slots = 256;
-    if (lds_slots > 2048)
-        lds_slots = 2048;
-    switch (pairs_per_lane) {
-    case 1: return launch_staged_u<1>(p, stream, lds_slots);
-    case 4: return launch_staged_u<4>(p, stream, lds_slots);
-    default: return launch_staged_u<2>(p, stream, lds_slots);
-    }
+    // lds_slots = edges a workgroup can stage (40 bytes each in LDS), already
+    // clamped to the device's LDS per workgroup
+    const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
+    const int n_items = (int)((p.n_points + 256 * U - 1) / (256 * U));
+    return launch_staged_batched(p, stream, U, lds_slots, nullptr, n_items, nullptr, 0);
 }
 
 int launch_validate(const Problem &p, unsigned *flags, hipStream_t stream)

@@ -1,0 +1,438 @@
+// Binary32 filtered evaluation with a proven error bound, plus the binary64
+// recheck of the pairs the filter cannot decide.
+//
+// Per workgroup item (256*U consecutive pairs, sorted by polygon) the rings
+// are staged in LDS re-centred on their bounding-box centre c:
+//   YF : fl32(fl64(y_j - c_y)) per vertex (straddle pass)
+//   EF : (XI, YI, NX, NY) = fl32 of fl64(a - c) and of the rule's binary64
+//        normal (negated when its x part is negative), per edge
+// and per ring: c (binary64), M_ring = an upper bound of |v - c| over the
+// ring (rounded up to binary32), and an eligibility flag.
+//
+// For a pair, P = fl32(fl64(p - c)).  Straddle: rounding is monotone, so a
+// strict binary32 order between P_y and a vertex's YF implies the same
+// strict binary64 order between p_y and y_v; equal values are undecided.
+// Side: S = fl32(fl32(P_x - XI) * NX + fl32(P_y - YI) * NY).  With M >= every
+// re-centred coordinate of the pair (point and ring) and u = 2^-24,
+//   |S - E| <= 10.03 u M (|NX| + |NY|) + 4 eta (|NX| + |NY| + 1),
+// where E = t1 n_x + t2 n_y is the exact value on the binary64 inputs and
+// normals and eta = 2^-126 covers flushed subnormals; the binary64 value the
+// rule computes differs from E by at most 6.02 * 2^-53 M (|n_x| + |n_y|).
+// Hence |S| > B = 12 u M (|NX| + |NY|) + 4 eta (|NX| + |NY| + 1) guarantees
+// that the rule's binary64 side value is nonzero with the sign of S (the 12
+// also covers the rounding of B itself and of M).  The bound needs every
+// nonzero |n| component in [2^-60, 2^60] and |p - c|, |v - c| <= 2^60 (no
+// binary32 overflow or underflow of normals); rings or points outside that
+// range are not filtered.  A pair with any undecided straddle or side test
+// is appended to a list and re-run in binary64 in the rule's order.
+//
+// This translation unit must be compiled with -ffp-contract=off: the bound
+// assumes separately rounded binary32 products and sums.
+
+#include "pip_common.h"
+#include "ring_walk.h"
+
+namespace pip {
+namespace {
+
+constexpr float kBoundK = 12.0f * 5.9604644775390625e-8f;   // 12 * 2^-24
+constexpr float kEta4 = 4.0f * 1.1754943508222875e-38f;       // 4 * 2^-126
+constexpr double kLim = 1.152921504606846976e18;              // 2^60
+constexpr double kTiny = 8.673617379884035e-19;               // 2^-60
+
+__device__ __forceinline__ bool normal_ok(double v)
+{
+    const double a = fabs(v);
+    return a == 0.0 || (a >= kTiny && a <= kLim);
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Append the lanes in `mask` (their pair indices i) to the recheck list.
+__device__ __forceinline__ void append_recheck(uint64_t mask, int64_t i, int32_t *list, unsigned *count)
+{
+    const int lane = threadIdx.x & 63;
+    if (mask == 0)
+        return;
+    unsigned base = 0;
+    const int leader = __builtin_ctzll(mask);
+    if (lane == leader)
+        base = atomicAdd(count, (unsigned)__builtin_popcountll(mask));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if ((mask >> lane) & 1u) {
+        const unsigned below = (unsigned)__builtin_popcountll(mask & ((1ull << lane) - 1ull));
+        list[base + below] = (int32_t)i;
+    }
+}
+
+}  // namespace
+
+size_t filtered_smem_bytes(int max_edges, int max_rings)
+{
+    // T int[max_rings+1] | ring table 32 B per ring | YF float[max_edges+max_rings+64] | EF float4[max_edges]
+    size_t o = (((size_t)(max_rings + 1) * 4 + 15) & ~(size_t)15);
+    o += (size_t)max_rings * 32;
+    o += ((((size_t)max_edges + max_rings + 64) * 4 + 15) & ~(size_t)15);
+    o += (size_t)max_edges * 16;
+    return o;
+}
+
+namespace {
+
+struct RingInfo {
+    double cx, cy;
+    float m;        // bound on |v - c| (rounded up), or -1 when the ring is not filterable
+    int pad[3];
+};
+
+template <int U>
+__device__ __forceinline__ void filtered_item(
+    int64_t p0, const double *__restrict__ px, const double *__restrict__ py, int64_t n,
+    const int64_t *__restrict__ offsets, int64_t n_polys,
+    const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
+    const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
+    float bound_scale, int force_recheck, int32_t *__restrict__ recheck, unsigned *recheck_count,
+    unsigned char *smem)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int ypad = 64;
+    const int y_alloc = max_edges + max_rings + ypad;
+
+    double x[U], y[U];
+    int q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = p0 + u * 256 + tid;
+        x[u] = 0.0;
+        y[u] = 0.0;
+        q[u] = -1;
+        if (i < n) {
+            x[u] = px[i];
+            y[u] = py[i];
+            q[u] = point_poly ? point_poly[i] : 0;
+        }
+    }
+    const int64_t plast = (p0 + 256 * U < n ? p0 + 256 * U : n) - 1;
+    int qf = 0, ql = 0;
+    if (point_poly) {
+        qf = point_poly[p0];
+        ql = point_poly[plast];
+    }
+    const bool range_ok = (uint32_t)qf < (uint64_t)n_polys && (uint32_t)ql < (uint64_t)n_polys && qf <= ql;
+    int64_t vb = 0, ve = 0;
+    if (range_ok) {
+        vb = offsets[qf];
+        ve = offsets[ql + 1];
+        clamp_ring(vb, ve, nv);
+    }
+    const int nr = ql - qf + 1;
+    bool mine_ok = true;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        mine_ok = mine_ok && (q[u] < 0 || (q[u] >= qf && q[u] <= ql));
+    const bool staged = __syncthreads_and(range_ok && ve - vb <= max_edges && nr <= max_rings && mine_ok);
+
+    if (!staged) {
+        // Rings too large for the workgroup's LDS (or unsorted pairs): these
+        // pairs take the exact binary64 wave-uniform walk instead.
+        group_walk_rows<U>(p0, x, y, q, n, offsets, n_polys, vx, vy, nv, inside);
+        return;
+    }
+
+    int *T = (int *)smem;
+    size_t o = (((size_t)(max_rings + 1) * 4 + 15) & ~(size_t)15);
+    RingInfo *R = (RingInfo *)(smem + o);
+    o += (size_t)max_rings * 32;
+    float *YF = (float *)(smem + o);
+    o += ((((size_t)max_edges + max_rings + 64) * 4 + 15) & ~(size_t)15);
+    float4 *EF = (float4 *)(smem + o);
+
+    for (int r = tid; r <= nr; r += 256) {
+        int64_t ov = offsets[qf + r];
+        ov = ov < vb ? vb : (ov > ve ? ve : ov);
+        T[r] = (int)(ov - vb);
+    }
+    __syncthreads();
+    int kmax_local = 0;
+    for (int r = wid; r < nr; r += 4) {
+        const int e0 = T[r];
+        int e1 = T[r + 1];
+        e1 = e1 < e0 ? e0 : e1;
+        const int k = e1 - e0;
+        kmax_local = k > kmax_local ? k : kmax_local;
+        const double *__restrict__ rx = vx + vb + e0;
+        const double *__restrict__ ry = vy + vb + e0;
+        // bounding box -> centre, radius
+        double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+        bool ok = true;
+        for (int j = lane; j < k; j += 64) {
+            const double a = rx[j], b = ry[j];
+            xmn = fmin(xmn, a);
+            xmx = fmax(xmx, a);
+            ymn = fmin(ymn, b);
+            ymx = fmax(ymx, b);
+        }
+        xmn = wave_min(xmn);
+        xmx = wave_max(xmx);
+        ymn = wave_min(ymn);
+        ymx = wave_max(ymx);
+        const double cx = k > 0 ? 0.5 * xmn + 0.5 * xmx : 0.0;
+        const double cy = k > 0 ? 0.5 * ymn + 0.5 * ymx : 0.0;
+        const double m = k > 0 ? fmax(fmax(fabs(xmn - cx), fabs(xmx - cx)), fmax(fabs(ymn - cy), fabs(ymx - cy)))
+                               : 0.0;
+        const int yb = e0 + r;
+        for (int j = lane; j < k; j += 64) {
+            const int jp = j == 0 ? k - 1 : j - 1;
+            const double ax = rx[jp], ay = ry[jp], bx = rx[j], by = ry[j];
+            double nx = by - ay;
+            double ny = ax - bx;
+            if (nx < 0.0) {
+                nx = -nx;
+                ny = -ny;
+            }
+            ok = ok && normal_ok(nx) && normal_ok(ny);
+            EF[e0 + j] = make_float4((float)(ax - cx), (float)(ay - cy), (float)nx, (float)ny);
+            const float yv = (float)(by - cy);
+            YF[yb + 1 + j] = yv;
+            if (j == k - 1)
+                YF[yb] = yv;
+        }
+        const bool ring_ok = __builtin_amdgcn_ballot_w64(!ok) == 0 && k > 0 && m <= kLim;
+        if (lane == 0) {
+            RingInfo ri;
+            ri.cx = cx;
+            ri.cy = cy;
+            ri.m = ring_ok ? __double2float_ru(m) : -1.0f;
+            R[r] = ri;
+        }
+    }
+    const int ytot = (int)(ve - vb) + nr;
+    if (tid < ypad)
+        YF[ytot + tid] = 0.0f;
+    // block max of ring sizes (loop bound of the straddle pass)
+    __shared__ int s_kmax;
+    if (tid == 0)
+        s_kmax = 0;
+    __syncthreads();
+    if (lane == 0)
+        atomicMax(&s_kmax, kmax_local);
+    __syncthreads();
+    const int kmax_b = s_kmax;
+
+    const float ks = kBoundK * bound_scale;
+    const float eta = kEta4 * bound_scale;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = p0 + u * 256 + tid;
+        const int r = (q[u] < 0 ? qf : q[u]) - qf;
+        const int e0 = T[r];
+        int k = T[r + 1] - e0;
+        k = k < 0 ? 0 : k;
+        const int yb = e0 + r;
+        const RingInfo ri = R[r];
+        const double xr = x[u] - ri.cx, yr = y[u] - ri.cy;
+        const float PX = (float)xr, PY = (float)yr;
+        bool amb = ri.m < 0.0f || !(fabs(xr) <= kLim) || !(fabs(yr) <= kLim) || force_recheck;
+        const float mp = fmaxf(ri.m, fmaxf(fabsf(PX), fabsf(PY)));
+        const float kmt = ks * mp + eta;
+        const float PYq = PY + 0.0f;
+        uint64_t par = 0;
+        float zmin = k > 0 ? fabsf(PYq - YF[yb]) : 1.0f;
+        uint32_t above_prev = (k > 0 && (__float_as_uint(PYq - YF[yb]) >> 31)) ? 1u : 0u;
+        for (int c0 = 0; c0 < kmax_b; c0 += 32) {
+            if (__builtin_amdgcn_ballot_w64(k > c0) == 0)
+                break;
+            uint32_t above = 0;
+            const int ybase = yb + 1 + c0;
+            const float *yp = YF + (ybase < y_alloc - 32 ? ybase : y_alloc - 32);
+            int t = 0;
+            for (; t < 32; t += 4) {
+                if (__builtin_amdgcn_ballot_w64(k > c0 + t) == 0)
+                    break;
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                    const float d = PYq - yp[t + tt];
+                    const bool inside_ring = c0 + t + tt < k;
+                    zmin = inside_ring ? fminf(zmin, fabsf(d)) : zmin;
+                    above = __builtin_amdgcn_alignbit(above, __float_as_uint(d), 31);
+                }
+            }
+            above = t < 32 ? above << (32 - t) : above;
+            uint32_t strad = above ^ ((above >> 1) | (above_prev << 31));
+            const int rem = k - c0;
+            if (rem < 32)
+                strad &= rem <= 0 ? 0u : ~(0xffffffffu >> rem);
+            above_prev = rem >= 32 ? (above & 1u) : above_prev;
+            const float4 *er = EF + e0 + c0;
+            while (strad != 0) {
+                const int j = __builtin_clz(strad);
+                strad ^= 0x80000000u >> j;
+                const float4 rec = er[j];
+                const float t1 = PX - rec.x;
+                const float t2 = PY - rec.y;
+                const float p1 = t1 * rec.z;
+                const float p2 = t2 * rec.w;
+                const float sv = p1 + p2;
+                const float nsum = fabsf(rec.z) + fabsf(rec.w);
+                const float bnd = kmt * nsum + eta;
+                amb = amb || !(fabsf(sv) > bnd);
+                par ^= __builtin_amdgcn_ballot_w64(sv <= 0.0f);
+            }
+        }
+        amb = amb || zmin == 0.0f;
+        const bool valid = i < n;
+        const uint64_t ambm = __builtin_amdgcn_ballot_w64(valid && amb);
+        if (valid && !amb)
+            inside[i] = (uint8_t)((par >> lane) & 1u);
+        append_recheck(ambm, i, recheck, recheck_count);
+    }
+}
+
+template <int U>
+__global__ __launch_bounds__(256) void k_filtered_fp32(
+    const double *__restrict__ px, const double *__restrict__ py, int64_t n,
+    const int64_t *__restrict__ offsets, int64_t n_polys,
+    const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
+    const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
+    float bound_scale, int force_recheck, int32_t *__restrict__ recheck, unsigned *recheck_count,
+    const int32_t *__restrict__ order, int n_items, unsigned *queue)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item;
+    if (!queue) {
+        const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
+        filtered_item<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside,
+                         max_edges, max_rings, bound_scale, force_recheck, recheck, recheck_count, smem);
+        return;
+    }
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items)
+            break;
+        const int item = order ? order[it] : it;
+        filtered_item<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside,
+                         max_edges, max_rings, bound_scale, force_recheck, recheck, recheck_count, smem);
+        __syncthreads();
+    }
+}
+
+// Binary64 recheck, in the rule's operation order, of the listed pairs.  A
+// fixed grid strides over the list; its length is read on the device, so the
+// launch does not depend on it (graph-safe).
+__global__ __launch_bounds__(256) void k_recheck_fp64(
+    const double *__restrict__ px, const double *__restrict__ py,
+    const int64_t *__restrict__ offsets, int64_t n_polys,
+    const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
+    const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside,
+    const int32_t *__restrict__ list, const unsigned *__restrict__ count, int64_t cap)
+{
+    int64_t m = (int64_t)*count;
+    m = m < cap ? m : cap;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = list[t];
+        int64_t qq = point_poly ? (int64_t)point_poly[i] : 0;
+        qq = ((uint64_t)qq < (uint64_t)n_polys) ? qq : 0;
+        int64_t b = offsets[qq], e = offsets[qq + 1];
+        clamp_ring(b, e, nv);
+        const double x = px[i], y = py[i];
+        unsigned par = 0;
+        if (e > b) {
+            double ax = vx[e - 1], ay = vy[e - 1];
+            for (int64_t j = b; j < e; ++j) {
+                const double bx = vx[j], by = vy[j];
+                if ((ay > y) != (by > y)) {
+                    double nx = by - ay;
+                    double ny = ax - bx;
+                    if (nx < 0.0) {
+                        nx = -nx;
+                        ny = -ny;
+                    }
+                    const double t1 = x - ax;
+                    const double t2 = y - ay;
+                    const double s = t1 * nx + t2 * ny;
+                    par ^= (s <= 0.0) ? 1u : 0u;
+                }
+                ax = bx;
+                ay = by;
+            }
+        }
+        inside[i] = (uint8_t)par;
+    }
+}
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+int launch_filtered(const Problem &p, hipStream_t stream, int pairs_per_lane, int max_edges, float bound_scale,
+                    int force_recheck, int32_t *recheck, unsigned *recheck_count, const int32_t *order,
+                    int n_items, unsigned *queue, int grid)
+{
+    const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
+    const int max_rings = 256 * U < 128 ? 256 * U : 128;
+    const size_t shmem = filtered_smem_bytes(max_edges, max_rings);
+    if (!queue)
+        grid = n_items;
+    if (grid <= 0)
+        return PIP_OK;
+#define PIP_LAUNCH_F(UU)                                                                                         \
+    hipLaunchKernelGGL((k_filtered_fp32<UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py, p.n_points,     \
+                       p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside, max_edges,         \
+                       max_rings, bound_scale, force_recheck, recheck, recheck_count, order, n_items, queue)
+    if (U == 1)
+        PIP_LAUNCH_F(1);
+    else if (U == 4)
+        PIP_LAUNCH_F(4);
+    else
+        PIP_LAUNCH_F(2);
+#undef PIP_LAUNCH_F
+    PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
+
+int filtered_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu)
+{
+    const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
+    const int max_rings = 256 * U < 128 ? 256 * U : 128;
+    const size_t shmem = filtered_smem_bytes(max_edges, max_rings);
+    int nb = 0;
+    hipError_t e;
+    if (U == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_filtered_fp32<1>, 256, shmem);
+    else if (U == 4)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_filtered_fp32<4>, 256, shmem);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_filtered_fp32<2>, 256, shmem);
+    if (e != hipSuccess)
+        return fail(PIP_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
+    *blocks_per_cu = nb < 1 ? 1 : nb;
+    return PIP_OK;
+}
+
+int launch_recheck(const Problem &p, hipStream_t stream, const int32_t *list, const unsigned *count, int grid)
+{
+    hipLaunchKernelGGL(k_recheck_fp64, dim3(grid), dim3(256), 0, stream, p.px, p.py, p.offsets, p.n_polys, p.vx,
+                       p.vy, p.n_vertices, p.point_poly, p.inside, list, count, (int64_t)p.n_points);
+    PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
+
+}  // namespace pip

@@ -32,7 +32,10 @@ struct DeviceInfo {
     int cu_count = 0;
     bool gfx950 = false;
     unsigned *validate_flags = nullptr;   // address of the __device__ flag word
+    size_t lds_per_block = 0;             // largest dynamic LDS a workgroup may request
 };
+// Largest edge budget (lds_slots) whose staging fits the device's LDS per workgroup.
+int clamp_lds_slots(int lds_slots, bool filtered, int pairs_per_lane, const DeviceInfo *dev);
 // Info for the current device (cached per device); PIP_ENOTSUP if not gfx950.
 int current_device(DeviceInfo **out);
 
@@ -56,6 +59,24 @@ int validate_on_device(const Problem &p, DeviceInfo *dev, hipStream_t stream);
 int launch_per_pair(const Problem &p, hipStream_t stream);
 int launch_segmented(const Problem &p, hipStream_t stream, int pairs_per_lane, int block);
 int launch_staged(const Problem &p, hipStream_t stream, int pairs_per_lane, int lds_slots);
+size_t staged_smem_bytes(int max_edges, int max_rings);
+int staged_max_rings(int pairs_per_lane);
+int staged_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu);
+int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_lane, int max_edges,
+                          const int32_t *order, int n_items, unsigned *queue, int grid);
+
+// ---------------------------------------------------------------- filtered binary32 path
+size_t filtered_smem_bytes(int max_edges, int max_rings);
+int filtered_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu);
+int launch_filtered(const Problem &p, hipStream_t stream, int pairs_per_lane, int max_edges, float bound_scale,
+                    int force_recheck, int32_t *recheck, unsigned *recheck_count, const int32_t *order,
+                    int n_items, unsigned *queue, int grid);
+int launch_recheck(const Problem &p, hipStream_t stream, const int32_t *list, const unsigned *count, int grid);
+
+// ---------------------------------------------------------------- preparation
+int launch_fill(unsigned *p, int n, unsigned v, hipStream_t stream);
+int launch_item_order(const Problem &p, hipStream_t stream, int item_pairs, int n_items, uint8_t *bucket,
+                      unsigned *counters, int32_t *order);
 int launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t stream);
 int launch_validate(const Problem &p, unsigned *flags, hipStream_t stream);
 

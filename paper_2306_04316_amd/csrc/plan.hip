@@ -1,0 +1,462 @@
+// Plans: a prepared, repeatable classification of fixed device buffers.
+//
+// A plan owns its workspace (one device allocation, made at creation and
+// released at destruction) and, by default, a HIP graph of its step sequence:
+//   counters reset -> item order (heaviest first) -> main kernel -> recheck
+// so an execution is a single graph launch.  The main kernel is chosen by the
+// options, optionally by timing candidate configurations on the plan's own
+// data (the autotuner below), with results kept in a small text cache.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "pip_common.h"
+
+struct pip_plan {
+    pip::Problem p;
+    pip_options o;               // as requested
+    pip_plan_config cfg;         // as resolved (after tuning)
+    int device = -1;
+    int cu_count = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    unsigned *counters = nullptr;   // [0,64) ordering, [64] queue, [65] recheck count
+    uint8_t *bucket = nullptr;
+    int32_t *order = nullptr;
+    int32_t *recheck = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool executed = false;
+};
+
+namespace pip {
+namespace {
+
+constexpr int kQueue = 64;
+constexpr int kRecheckCount = 65;
+constexpr int kCounters = 68;
+
+int item_pairs_of(const pip_plan_config &c) { return 256 * c.pairs_per_lane; }
+
+bool staged_kind(const pip_plan_config &c)
+{
+    return c.mode == PIP_MODE_FILTERED_FP32 || c.kernel == PIP_KERNEL_STAGED || c.kernel == PIP_KERNEL_AUTO;
+}
+
+int resolve_grid(pip_plan *pl, pip_plan_config &c)
+{
+    DeviceInfo *dev = nullptr;
+    PIP_TRY(current_device(&dev));
+    c.lds_slots = clamp_lds_slots(c.lds_slots, c.mode == PIP_MODE_FILTERED_FP32, c.pairs_per_lane, dev);
+    c.n_items = (int)((pl->p.n_points + item_pairs_of(c) - 1) / item_pairs_of(c));
+    if (!staged_kind(c) || !c.persistent) {
+        c.grid = c.n_items;
+        return PIP_OK;
+    }
+    int nb = 1;
+    if (c.mode == PIP_MODE_FILTERED_FP32)
+        PIP_TRY(filtered_occupancy(c.pairs_per_lane, c.lds_slots, &nb));
+    else
+        PIP_TRY(staged_occupancy(c.pairs_per_lane, c.lds_slots, &nb));
+    const int64_t g = (int64_t)nb * pl->cu_count;
+    c.grid = (int)std::min<int64_t>(g, c.n_items);
+    return PIP_OK;
+}
+
+// Enqueue one execution of the plan's step sequence with configuration c.
+int enqueue(pip_plan *pl, const pip_plan_config &c, hipStream_t s, bool capturing)
+{
+    auto rec = [&](int k) -> int {
+        hipError_t e = capturing ? hipEventRecordWithFlags(pl->ev[k], s, hipEventRecordExternal)
+                                 : hipEventRecord(pl->ev[k], s);
+        if (e != hipSuccess)
+            return fail(PIP_EHIP, "hipEventRecord failed: %s", hipGetErrorString(e));
+        return PIP_OK;
+    };
+    const Problem &p = pl->p;
+    PIP_TRY(rec(0));
+    if (p.n_points > 0) {
+        const bool staged = staged_kind(c);
+        PIP_TRY(launch_fill(pl->counters + kQueue, kCounters - kQueue, 0u, s));
+        const bool lpt = staged && c.order == 1 && p.point_poly;
+        if (lpt)
+            PIP_TRY(launch_item_order(p, s, item_pairs_of(c), c.n_items, pl->bucket, pl->counters, pl->order));
+        PIP_TRY(rec(1));
+        unsigned *queue = c.persistent ? pl->counters + kQueue : nullptr;
+        const int32_t *order = lpt ? pl->order : nullptr;
+        if (c.mode == PIP_MODE_FILTERED_FP32) {
+            PIP_TRY(launch_filtered(p, s, c.pairs_per_lane, c.lds_slots, pl->o.bound_scale, pl->o.force_recheck,
+                                    pl->recheck, pl->counters + kRecheckCount, order, c.n_items, queue, c.grid));
+        } else if (c.kernel == PIP_KERNEL_PER_PAIR) {
+            PIP_TRY(launch_per_pair(p, s));
+        } else if (c.kernel == PIP_KERNEL_SEGMENTED) {
+            PIP_TRY(launch_segmented(p, s, c.pairs_per_lane, 256));
+        } else {
+            PIP_TRY(launch_staged_batched(p, s, c.pairs_per_lane, c.lds_slots, order, c.n_items, queue, c.grid));
+        }
+        PIP_TRY(rec(2));
+        if (c.mode == PIP_MODE_FILTERED_FP32)
+            PIP_TRY(launch_recheck(p, s, pl->recheck, pl->counters + kRecheckCount, pl->cu_count * 8));
+    } else {
+        PIP_TRY(rec(1));
+        PIP_TRY(rec(2));
+    }
+    PIP_TRY(rec(3));
+    return PIP_OK;
+}
+
+void drop_graph(pip_plan *pl)
+{
+    if (pl->exec)
+        (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph)
+        (void)hipGraphDestroy(pl->graph);
+    pl->exec = nullptr;
+    pl->graph = nullptr;
+}
+
+int build_graph(pip_plan *pl)
+{
+    drop_graph(pl);
+    hipStream_t cs = nullptr;
+    PIP_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int rc = PIP_OK;
+    if (e != hipSuccess) {
+        rc = fail(PIP_EHIP, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+    } else {
+        rc = enqueue(pl, pl->cfg, cs, true);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (rc == PIP_OK && e != hipSuccess)
+            rc = fail(PIP_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        if (rc == PIP_OK) {
+            pl->graph = g;
+            e = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess)
+                rc = fail(PIP_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != PIP_OK)
+        drop_graph(pl);
+    return rc;
+}
+
+// ---------------------------------------------------------------- tuning cache
+std::string tune_key(const pip_plan *pl)
+{
+    auto lg = [](int64_t v) {
+        int b = 0;
+        while (v > 1) {
+            v >>= 1;
+            ++b;
+        }
+        return b;
+    };
+    char buf[160];
+    snprintf(buf, sizeof buf, "gfx950:m%d:k%d:n%d:p%d:v%d:i%d", pl->o.mode, pl->o.kernel, lg(pl->p.n_points),
+             lg(pl->p.n_polys), lg(pl->p.n_vertices), pl->p.point_poly ? 1 : 0);
+    return buf;
+}
+
+const char *cache_path(const pip_plan *pl)
+{
+    if (pl->o.tune_cache && pl->o.tune_cache[0])
+        return pl->o.tune_cache;
+    const char *e = getenv("PIP_TUNE_CACHE");
+    return (e && e[0]) ? e : nullptr;
+}
+
+// Cache lines: "<key> <pairs_per_lane> <lds_slots> <persistent> <order> <ms>"
+bool cache_lookup(const pip_plan *pl, pip_plan_config &c)
+{
+    const char *path = cache_path(pl);
+    if (!path)
+        return false;
+    FILE *f = fopen(path, "r");
+    if (!f)
+        return false;
+    const std::string key = tune_key(pl);
+    char k[200];
+    int u, l, pe, od;
+    float ms;
+    bool found = false;
+    while (fscanf(f, "%199s %d %d %d %d %f", k, &u, &l, &pe, &od, &ms) == 6) {
+        const bool sane = (u == 1 || u == 2 || u == 4) && l >= 16 && l <= 2048 && (pe == 0 || pe == 1) &&
+                          (od == 0 || od == 1);
+        if (key == k && sane) {
+            c.pairs_per_lane = u;
+            c.lds_slots = l;
+            c.persistent = pe;
+            c.order = od;
+            c.tune_ms = ms;
+            found = true;   // the last matching line wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const pip_plan *pl, const pip_plan_config &c)
+{
+    const char *path = cache_path(pl);
+    if (!path)
+        return;
+    FILE *f = fopen(path, "a");
+    if (!f)
+        return;
+    fprintf(f, "%s %d %d %d %d %.6f\n", tune_key(pl).c_str(), c.pairs_per_lane, c.lds_slots, c.persistent, c.order,
+            c.tune_ms);
+    fclose(f);
+}
+
+// Time one candidate: median device time (ms) of the whole step sequence over
+// `reps` eager executions on stream s (after two untimed ones).
+int time_candidate(pip_plan *pl, pip_plan_config &c, hipStream_t s, int reps, float *ms_out)
+{
+    PIP_TRY(resolve_grid(pl, c));
+    std::vector<float> t;
+    for (int r = 0; r < reps + 2; ++r) {
+        PIP_TRY(enqueue(pl, c, s, false));
+        PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
+        float a = 0.f;
+        PIP_HIP_TRY(hipEventElapsedTime(&a, pl->ev[0], pl->ev[3]));
+        if (r >= 2)
+            t.push_back(a);
+    }
+    std::sort(t.begin(), t.end());
+    *ms_out = t[t.size() / 2];
+    return PIP_OK;
+}
+
+int autotune(pip_plan *pl, hipStream_t s)
+{
+    pip_plan_config best = pl->cfg;
+    float best_ms = 1e30f;
+    const int reps = pl->o.tune > 1 ? pl->o.tune : 5;
+    std::vector<pip_plan_config> cands;
+    const int lds_opts[] = {128, 256, 512, 1024};
+    const int ppl_opts[] = {1, 2, 4};
+    for (int u : ppl_opts)
+        for (int l : lds_opts)
+            for (int pe = 0; pe <= 1; ++pe)
+                for (int od = 0; od <= (pl->p.point_poly ? 1 : 0); ++od) {
+                    pip_plan_config c = pl->cfg;
+                    c.pairs_per_lane = u;
+                    c.lds_slots = l;
+                    c.persistent = pe;
+                    c.order = od;
+                    cands.push_back(c);
+                }
+    for (auto &c : cands) {
+        float ms = 0.f;
+        PIP_TRY(time_candidate(pl, c, s, reps, &ms));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    best.tuned = 1;
+    best.tune_ms = best_ms;
+    PIP_TRY(resolve_grid(pl, best));
+    pl->cfg = best;
+    cache_store(pl, best);
+    return PIP_OK;
+}
+
+int check_options(const pip_options *opts, pip_options &o)
+{
+    pip_options_init(&o);
+    if (opts) {
+        if (opts->struct_size != sizeof(pip_options))
+            return fail(PIP_EINVAL, "pip_options.struct_size=%u, expected %zu", opts->struct_size,
+                        sizeof(pip_options));
+        o = *opts;
+    }
+    if (o.mode != PIP_MODE_EXACT_FP64 && o.mode != PIP_MODE_FILTERED_FP32)
+        return fail(PIP_EINVAL, "unknown mode %d", o.mode);
+    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_STAGED)
+        return fail(PIP_EINVAL, "unknown kernel %d", o.kernel);
+    if (o.mode == PIP_MODE_FILTERED_FP32 && (o.kernel == PIP_KERNEL_PER_PAIR || o.kernel == PIP_KERNEL_SEGMENTED))
+        return fail(PIP_EINVAL, "the filtered mode runs on the staged kernel only");
+    if (!(o.bound_scale >= 0.0f))
+        return fail(PIP_EINVAL, "bound_scale must be >= 0");
+    return PIP_OK;
+}
+
+}  // namespace
+}  // namespace pip
+
+using namespace pip;
+
+extern "C" {
+
+int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t n_points, const int64_t *offsets,
+                    int64_t n_polys, const double *vx, const double *vy, int64_t n_vertices,
+                    const int32_t *point_poly, uint8_t *inside, const pip_options *opts, void *stream)
+{
+    clear_error();
+    if (!out)
+        return fail(PIP_EINVAL, "out is NULL");
+    *out = nullptr;
+    pip_options o;
+    PIP_TRY(check_options(opts, o));
+    Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
+    PIP_TRY(check_host_args(p));
+    DeviceInfo *dev = nullptr;
+    PIP_TRY(current_device(&dev));
+    hipStream_t s = (hipStream_t)stream;
+    if (o.validate)
+        PIP_TRY(validate_on_device(p, dev, s));
+
+    pip_plan *pl = new pip_plan;
+    pl->p = p;
+    pl->o = o;
+    pl->device = dev->device;
+    pl->cu_count = dev->cu_count;
+    pip_plan_config &c = pl->cfg;
+    memset(&c, 0, sizeof c);
+    c.struct_size = sizeof c;
+    c.mode = o.mode;
+    c.kernel = o.kernel == PIP_KERNEL_AUTO ? PIP_KERNEL_STAGED : o.kernel;
+    c.pairs_per_lane = o.pairs_per_lane > 0 ? o.pairs_per_lane : 4;
+    c.lds_slots = o.lds_slots > 0 ? std::min(o.lds_slots, 2048) : 256;
+    c.persistent = o.persistent >= 0 ? (o.persistent ? 1 : 0) : (point_poly ? 1 : 0);
+    c.order = o.order >= 0 ? (o.order ? 1 : 0) : (point_poly ? 1 : 0);
+    c.use_graph = o.use_graph ? 1 : 0;
+    if (c.pairs_per_lane != 1 && c.pairs_per_lane != 2 && c.pairs_per_lane != 4)
+        c.pairs_per_lane = 4;
+
+    int rc = PIP_OK;
+    // workspace: counters | bucket[n_items max] | order[n_items max] | recheck[n_points]
+    const int64_t max_items = (n_points + 255) / 256 + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_cnt = take(kCounters * sizeof(unsigned));
+    const size_t o_bkt = take((size_t)max_items);
+    const size_t o_ord = take((size_t)max_items * sizeof(int32_t));
+    const size_t o_rck = take(o.mode == PIP_MODE_FILTERED_FP32 ? (size_t)std::max<int64_t>(n_points, 1) * 4 : 0);
+    pl->ws_bytes = off;
+    hipError_t e = hipMalloc(&pl->ws, pl->ws_bytes);
+    if (e != hipSuccess) {
+        delete pl;
+        (void)hipGetLastError();
+        return fail(PIP_ENOMEM, "plan workspace of %zu bytes: %s", off, hipGetErrorString(e));
+    }
+    unsigned char *w = (unsigned char *)pl->ws;
+    pl->counters = (unsigned *)(w + o_cnt);
+    pl->bucket = w + o_bkt;
+    pl->order = (int32_t *)(w + o_ord);
+    pl->recheck = o.mode == PIP_MODE_FILTERED_FP32 ? (int32_t *)(w + o_rck) : nullptr;
+    for (int k = 0; k < 4 && rc == PIP_OK; ++k) {
+        e = hipEventCreate(&pl->ev[k]);
+        if (e != hipSuccess)
+            rc = fail(PIP_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+    }
+    if (rc == PIP_OK)
+        rc = launch_fill(pl->counters, kCounters, 0u, s);
+    if (rc == PIP_OK && staged_kind(c) && n_points > 0) {
+        pip_plan_config cached = c;
+        if (cache_lookup(pl, cached)) {
+            c = cached;
+            c.tuned = 2;
+        } else if (o.tune) {
+            rc = autotune(pl, s);
+        }
+    }
+    if (rc == PIP_OK)
+        rc = resolve_grid(pl, c);
+    if (rc == PIP_OK && c.use_graph) {
+        if (build_graph(pl) != PIP_OK) {
+            c.use_graph = 0;   // capture unsupported here: run the same sequence eagerly
+            clear_error();
+            (void)hipGetLastError();
+        }
+    }
+    if (rc != PIP_OK) {
+        pip_plan_destroy(pl);
+        return rc;
+    }
+    *out = pl;
+    return PIP_OK;
+}
+
+int pip_plan_execute(pip_plan *pl, void *stream)
+{
+    clear_error();
+    if (!pl)
+        return fail(PIP_EINVAL, "plan is NULL");
+    int dev = -1;
+    PIP_HIP_TRY(hipGetDevice(&dev));
+    if (dev != pl->device)
+        return fail(PIP_EINVAL, "plan belongs to device %d, current device is %d", pl->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+    if (pl->exec) {
+        PIP_HIP_TRY(hipGraphLaunch(pl->exec, s));
+    } else {
+        PIP_TRY(enqueue(pl, pl->cfg, s, false));
+    }
+    pl->executed = true;
+    return PIP_OK;
+}
+
+int pip_plan_stats(pip_plan *pl, pip_stats *st)
+{
+    clear_error();
+    if (!pl || !st)
+        return fail(PIP_EINVAL, "NULL argument");
+    memset(st, 0, sizeof *st);
+    st->pairs = (uint64_t)pl->p.n_points;
+    if (!pl->executed)
+        return PIP_OK;
+    PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
+    PIP_HIP_TRY(hipEventElapsedTime(&st->ms_prep, pl->ev[0], pl->ev[1]));
+    PIP_HIP_TRY(hipEventElapsedTime(&st->ms_main, pl->ev[1], pl->ev[2]));
+    PIP_HIP_TRY(hipEventElapsedTime(&st->ms_recheck, pl->ev[2], pl->ev[3]));
+    if (pl->recheck) {
+        unsigned cnt = 0;
+        PIP_HIP_TRY(hipMemcpy(&cnt, pl->counters + kRecheckCount, sizeof cnt, hipMemcpyDeviceToHost));
+        st->rechecked_pairs = cnt;
+    }
+    return PIP_OK;
+}
+
+int pip_plan_get_config(const pip_plan *pl, pip_plan_config *cfg)
+{
+    clear_error();
+    if (!pl || !cfg)
+        return fail(PIP_EINVAL, "NULL argument");
+    *cfg = pl->cfg;
+    return PIP_OK;
+}
+
+int pip_plan_destroy(pip_plan *pl)
+{
+    clear_error();
+    if (!pl)
+        return PIP_OK;
+    drop_graph(pl);
+    for (auto &e : pl->ev)
+        if (e)
+            (void)hipEventDestroy(e);
+    if (pl->ws) {
+        (void)hipDeviceSynchronize();   // no enqueued execution may still use the workspace
+        (void)hipFree(pl->ws);
+    }
+    delete pl;
+    return PIP_OK;
+}
+
+}  // extern "C"

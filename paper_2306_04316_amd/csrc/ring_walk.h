@@ -1,0 +1,203 @@
+// Device helpers shared by the exact and the filtered kernels: the rule's
+// per-edge step in binary64 (paper, Method section, constraint 1, and
+// Algorithm 1, half-open straddle reading), in per-lane and lane-mask forms,
+// and the wave-uniform ring walks.  Include only from .hip files compiled
+// with -ffp-contract=off.
+//
+// The negation of the normal is never materialised in the per-lane and mask
+// steps: with round-to-nearest-even, fl(t * (-d)) = -fl(t * d) and
+// fl(-u - v) = -fl(u + v), so the side value with the negated normal is
+// exactly -s' where s' uses the unnegated normal.  Under the straddle
+// condition n_x < 0 holds exactly when a is the endpoint above the ray, so the
+// crossing test becomes (b above ? s' <= 0 : s' >= 0).  Both tests treat +0
+// and -0 alike, so the bit is the same as the literal rule's.
+#pragma once
+
+#include "pip_common.h"
+
+namespace pip {
+namespace {
+
+// Clamp a ring's [b, e) to the vertex array so no access leaves it, and to
+// at most INT32_MAX vertices per ring.
+__device__ __forceinline__ void clamp_ring(int64_t &b, int64_t &e, int64_t nv)
+{
+    e = e < 0 ? 0 : (e > nv ? nv : e);
+    b = b < 0 ? 0 : (b > e ? e : b);
+    e = (e - b > INT32_MAX) ? b + INT32_MAX : e;
+}
+
+// Crossing-parity contribution of edge (a, b) for point (x, y).
+__device__ __forceinline__ unsigned edge_cross(double x, double y, double ax, double ay, bool a_above,
+                                               double bx, double by, bool b_above)
+{
+    unsigned c = 0;
+    if (a_above != b_above) {
+        const double nx = by - ay;
+        const double ny = ax - bx;
+        const double t1 = x - ax;
+        const double t2 = y - ay;
+        const double s = t1 * nx + t2 * ny;
+        c = b_above ? (s <= 0.0) : (s >= 0.0);
+    }
+    return c;
+}
+
+// Shift the "vertex above the ray" bit of y_v into the low end of word w.
+// y_v > p_y  <=>  fl(p_y - y_v) < 0: the difference of two binary64 values is
+// zero only when they are equal (gradual underflow) and otherwise has the
+// exact sign, so its sign bit is the comparison -- provided p_y carries no
+// negative zero (p_y = -0, y_v = +0 would give -0).  Callers pass
+// yq = p_y + 0.0, which maps -0 to +0 and leaves every other value alone.
+// One add and one funnel shift, and no condition-mask hazards.
+__device__ __forceinline__ uint32_t shift_in_above(uint32_t w, double yq, double yv)
+{
+    const double d = yq - yv;
+    const uint32_t hi = (uint32_t)(__double_as_longlong(d) >> 32);
+    return __builtin_amdgcn_alignbit(w, hi, 31);
+}
+
+// One edge step in lane-mask form, for a whole wavefront at once.  Every lane
+// runs it (uniform control flow); bit l of each mask belongs to lane l.
+//   ca/cb : lanes whose point is below a / b (a_y > p_y, b_y > p_y)
+//   st    : straddling lanes (exactly one endpoint above the ray)
+// The crossing test is (b above ? s' <= 0 : s' >= 0) with the unnegated normal
+// (see the note at the top of this file).  Returns the lanes whose crossing
+// count the edge increments; updates ca to cb.
+__device__ __forceinline__ uint64_t edge_step_mask(double x, double y, double ax, double ay, double bx, double by,
+                                                   uint64_t &ca)
+{
+    const uint64_t cb = __builtin_amdgcn_ballot_w64(by > y);
+    const uint64_t st = ca ^ cb;
+    const double nx = by - ay;
+    const double ny = ax - bx;
+    const double t1 = x - ax;
+    const double t2 = y - ay;
+    const double s = t1 * nx + t2 * ny;
+    const uint64_t le = __builtin_amdgcn_ballot_w64(s <= 0.0);
+    const uint64_t ge = __builtin_amdgcn_ballot_w64(s >= 0.0);
+    ca = cb;
+    return st & ((cb & le) | (~cb & ge));
+}
+
+// Walk ring [b, e) (wave-uniform, streamed through scalar loads) for every
+// lane's point; returns the lanes with an odd crossing count.  Must be called
+// with the whole wavefront active.
+__device__ __forceinline__ uint64_t ring_parity_uniform(double x, double y, const double *__restrict__ vx,
+                                                        const double *__restrict__ vy, int64_t b, int64_t e)
+{
+    // ring-relative 32-bit indices keep the loop control in scalar ALU
+    // instructions (gfx9 has no 64-bit scalar ordered compare)
+    const int k = (int)(e - b);
+    const double *__restrict__ rx = vx + b;
+    const double *__restrict__ ry = vy + b;
+    uint64_t par = 0;
+    if (k <= 0)
+        return 0;
+    double ax = rx[k - 1], ay = ry[k - 1];     // closing edge v_{k-1} -> v_0 first
+    uint64_t ca = __builtin_amdgcn_ballot_w64(ay > y);
+    for (int j0 = 0; j0 < k; j0 += 8) {
+        double bxs[8], bys[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int j = (j0 + t < k) ? j0 + t : k - 1;   // clamped: repeats v_{k-1}, a zero-length edge
+            bxs[t] = rx[j];
+            bys[t] = ry[j];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            par ^= edge_step_mask(x, y, ax, ay, bxs[t], bys[t], ca);
+            ax = bxs[t];
+            ay = bys[t];
+        }
+    }
+    return par;
+}
+
+// The same parity with compacted side tests: the ring's y values stream
+// through scalar loads into each lane's 32-bit "above" words (two vector
+// instructions per vertex), then each lane evaluates the side value only for
+// its own straddling edges, fetching those two vertices itself.
+__device__ __forceinline__ uint64_t ring_parity_compact_uniform(double x, double y, bool member,
+                                                                const double *__restrict__ vx,
+                                                                const double *__restrict__ vy, int64_t b,
+                                                                int64_t e)
+{
+    const int k = (int)(e - b);
+    const double *__restrict__ rx = vx + b;
+    const double *__restrict__ ry = vy + b;
+    uint64_t par = 0;
+    if (k <= 0)
+        return 0;
+    const double yq = y + 0.0;
+    uint32_t prev = shift_in_above(0u, yq, ry[k - 1]);
+    for (int c0 = 0; c0 < k; c0 += 32) {
+        const int m = k - c0 < 32 ? k - c0 : 32;
+        uint32_t above = 0;
+        if (m == 32) {
+#pragma unroll
+            for (int t = 0; t < 32; ++t)
+                above = shift_in_above(above, yq, ry[c0 + t]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 32; ++t)
+                above = shift_in_above(above, yq, ry[c0 + (t < m ? t : m - 1)]);
+        }
+        uint32_t strad = above ^ ((above >> 1) | (prev << 31));
+        if (m < 32)
+            strad &= ~(0xffffffffu >> m);
+        prev = (above >> (32 - m)) & 1u;
+        strad = member ? strad : 0u;
+        while (strad != 0) {
+            const int j = __builtin_clz(strad);
+            strad ^= 0x80000000u >> j;
+            const int jb = c0 + j;
+            const int ja = jb == 0 ? k - 1 : jb - 1;
+            const double ax = rx[ja], ay = ry[ja], bx = rx[jb], by = ry[jb];
+            const bool b_above = (above >> (31 - j)) & 1u;
+            const double nx = by - ay;
+            const double ny = ax - bx;
+            const double t1 = x - ax;
+            const double t2 = y - ay;
+            const double s = t1 * nx + t2 * ny;
+            par ^= __builtin_amdgcn_ballot_w64(b_above ? (s <= 0.0) : (s >= 0.0));
+        }
+    }
+    return par;
+}
+
+
+// Rows u of a workgroup item whose rings were not staged: lanes that share a
+// polygon run together (leader = first unfinished lane), each group walking
+// its ring wave-uniformly with compacted side tests.
+template <int U>
+__device__ __forceinline__ void group_walk_rows(int64_t p0, const double (&x)[U], const double (&y)[U],
+                                                const int (&q)[U], int64_t n, const int64_t *__restrict__ offsets,
+                                                int64_t n_polys, const double *__restrict__ vx,
+                                                const double *__restrict__ vy, int64_t nv,
+                                                uint8_t *__restrict__ inside)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = p0 + u * 256 + tid;
+        const int qv = ((uint32_t)q[u] < (uint64_t)n_polys) ? q[u] : 0;
+        uint64_t todo = __builtin_amdgcn_ballot_w64(i < n);
+        uint64_t par = 0;
+        while (todo) {
+            const int leader = __builtin_ctzll(todo);
+            const int qu = __builtin_amdgcn_readlane(qv, leader);
+            int64_t b = offsets[qu], e = offsets[qu + 1];
+            clamp_ring(b, e, nv);
+            const uint64_t member = todo & __builtin_amdgcn_ballot_w64(qv == qu);
+            par |= ring_parity_compact_uniform(x[u], y[u], (member >> lane) & 1u, vx, vy, b, e) & member;
+            todo &= ~member;
+        }
+        if (i < n)
+            inside[i] = (uint8_t)((par >> lane) & 1u);
+    }
+}
+
+}  // namespace
+}  // namespace pip

@@ -1,0 +1,196 @@
+"""GPU parity of plans (pip_plan_*): exact and binary32-filtered modes, work
+ordering, persistent queues, graph replays and the autotuner -- every mask
+compared bit for bit with the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_same_mask, note, to_dev
+from paper_2306_04316_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2306_04316_amd as P
+    return P
+
+
+def plan_run(P, w, **opts):
+    import torch
+    d = to_dev(w)
+    pl = P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], **opts)
+    pl.execute()
+    torch.cuda.synchronize()
+    got = pl.out.cpu().numpy()
+    st = pl.stats()
+    cfg = pl.config()
+    pl.close()
+    return got, st, cfg
+
+
+def check_plan(P, w, what, **opts):
+    note(f"plan {what} {opts} N={w.n_points} P={w.n_polys} V={w.n_vertices}")
+    got, st, cfg = plan_run(P, w, **opts)
+    want = oracle.classify_workload(w)
+    assert_same_mask(got, want, f"plan {what} {opts}", w.px, w.py, w.point_poly)
+    return st, cfg
+
+
+SMALL = {
+    "star": lambda: W.star(),
+    "footprints": lambda: W.footprints(scale=0.0123),
+    "batched": lambda: W.batched(scale=0.01),
+    "stress": lambda: W.stress(scale=0.02),
+    "fractal": lambda: W.fractal(scale=0.001, n_vertices=20_000),
+}
+
+
+@pytest.mark.parametrize("mode", ["exact", "filtered"])
+@pytest.mark.parametrize("name", list(SMALL))
+def test_plan_small(P, mode, name):
+    st, cfg = check_plan(P, SMALL[name](), name, mode=mode)
+    assert cfg["use_graph"] == 1
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("mode", ["exact", "filtered"])
+def test_plan_scheduling_variants(P, persistent, order, mode):
+    check_plan(P, W.batched(scale=0.01), "batched", mode=mode, persistent=persistent, order=order)
+
+
+@pytest.mark.parametrize("ppl", [1, 2, 4])
+@pytest.mark.parametrize("lds", [64, 256, 2048])
+def test_plan_tiles(P, ppl, lds):
+    check_plan(P, W.stress(scale=0.005), "stress", mode="filtered", pairs_per_lane=ppl, lds_slots=lds)
+    check_plan(P, W.stress(scale=0.005), "stress", mode="exact", pairs_per_lane=ppl, lds_slots=lds)
+
+
+def test_filtered_recheck_fraction(P):
+    w = W.stress(scale=0.02)
+    st, _ = check_plan(P, w, "stress", mode="filtered")
+    frac = st["rechecked_pairs"] / w.n_points
+    note(f"stress recheck fraction {frac:.4f}")
+    # the special classes (on vertices, level with a horizontal edge, within 1e-9 m) are 3%
+    assert 0.01 < frac < 0.2
+
+
+def test_filtered_force_recheck(P):
+    w = W.batched(scale=0.01)
+    st, _ = check_plan(P, w, "batched", mode="filtered", force_recheck=True)
+    assert st["rechecked_pairs"] >= 0.99 * w.n_points
+
+
+def test_filtered_negative_control(P):
+    """With the error bound switched off (bound_scale=0) the binary32 filter alone
+    must get some stress pairs wrong: the recheck is load-bearing."""
+    import torch
+    w = W.stress(scale=0.02)
+    note("negative control: filtered with bound_scale=0")
+    got, st, _ = plan_run(P, w, mode="filtered", bound_scale=0.0)
+    want = oracle.classify_workload(w)
+    nbad = int(np.count_nonzero(got != want))
+    assert nbad > 0, "the unbounded binary32 filter matched the oracle everywhere"
+    note(f"negative control mismatches: {nbad}")
+
+
+@pytest.mark.parametrize("mode", ["exact", "filtered"])
+def test_graph_replays(P, mode):
+    """Several replays of one captured graph, with eager work between them."""
+    import torch
+    w = W.stress(scale=0.01)
+    want = oracle.classify_workload(w)
+    d = to_dev(w)
+    pl = P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], mode=mode)
+    assert pl.config()["use_graph"] == 1
+    for r in range(4):
+        note(f"graph replay {r} mode={mode}")
+        pl.out.fill_(7)
+        tmp = torch.ones(1 << 20, device="cuda").cumsum(0)   # unrelated eager work
+        pl.execute()
+        torch.cuda.synchronize()
+        assert_same_mask(pl.out.cpu().numpy(), want, f"replay {r}")
+        assert tmp[-1].item() == float(1 << 20)
+    pl.close()
+
+
+def test_plan_sees_new_data_in_same_buffers(P):
+    import torch
+    w1 = W.footprints(scale=0.01, seed=1)
+    d = to_dev(w1)
+    pl = P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], mode="filtered")
+    pl.execute()
+    torch.cuda.synchronize()
+    assert_same_mask(pl.out.cpu().numpy(), oracle.classify_workload(w1), "first data")
+    # new points, same polygons, same buffers
+    rng = np.random.default_rng(5)
+    w1.px = w1.px + rng.uniform(-1e-4, 1e-4, w1.n_points)
+    d["px"].copy_(torch.from_numpy(w1.px))
+    pl.execute()
+    torch.cuda.synchronize()
+    assert_same_mask(pl.out.cpu().numpy(), oracle.classify_workload(w1), "second data")
+    pl.close()
+
+
+def test_plan_eager_mode(P):
+    check_plan(P, W.batched(scale=0.005), "batched", mode="filtered", use_graph=False)
+    check_plan(P, W.batched(scale=0.005), "batched", mode="exact", use_graph=False)
+
+
+def test_plan_baseline_kernels(P):
+    check_plan(P, W.footprints(scale=0.01), "footprints", kernel="per_pair")
+    check_plan(P, W.footprints(scale=0.01), "footprints", kernel="segmented")
+
+
+def test_plan_unsorted_pairs(P):
+    w = W.footprints(scale=0.01)
+    s = W.subsample(w, np.random.default_rng(3).permutation(w.n_points))
+    for mode in ("exact", "filtered"):
+        check_plan(P, s, "shuffled", mode=mode)
+
+
+def test_plan_empty(P):
+    import torch
+    w = W.footprints(scale=0.001)
+    d = to_dev(w)
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    pl = P.Plan(e, e, d["offsets"], d["vx"], d["vy"], torch.empty(0, dtype=torch.int32, device="cuda"),
+                mode="filtered")
+    pl.execute()
+    torch.cuda.synchronize()
+    assert pl.stats()["pairs"] == 0
+    pl.close()
+
+
+def test_autotune_and_cache(P, tmp_path):
+    cache = str(tmp_path / "tune.txt")
+    w = W.batched(scale=0.005)
+    st, cfg = check_plan(P, w, "batched", mode="exact", tune=1, tune_cache=cache)
+    assert cfg["tuned"] == 1 and cfg["tune_ms"] > 0
+    text = open(cache).read().split()
+    assert len(text) == 6
+    st, cfg2 = check_plan(P, w, "batched", mode="exact", tune=1, tune_cache=cache)
+    assert cfg2["tuned"] == 2
+    for k in ("pairs_per_lane", "lds_slots", "persistent", "order"):
+        assert cfg2[k] == cfg[k]
+
+
+@pytest.mark.parametrize("mode", ["exact", "filtered"])
+def test_plan_full_batched(P, mode):
+    check_plan(P, W.batched(), "batched full", mode=mode)
+
+
+@pytest.mark.parametrize("mode", ["exact", "filtered"])
+def test_plan_full_stress(P, mode):
+    st, _ = check_plan(P, W.stress(), "stress full", mode=mode)
+    if mode == "filtered":
+        note(f"stress full rechecked pairs {st['rechecked_pairs']}")
+
+
+@pytest.mark.parametrize("mode", ["exact", "filtered"])
+def test_plan_full_footprints(P, mode):
+    check_plan(P, W.footprints(), "footprints full", mode=mode)
