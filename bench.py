@@ -1,20 +1,28 @@
 """Throughput of the ray-casting point-in-polygon hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--config 2] [--mode exact] [--kernel auto]
+    python bench.py [--steps K] [--warmup W] [--config 2] [--mode exact|filtered] [--no-tune]
 
-A step classifies one full batch of the workload (default: the footprint
-workload, 100,000 building-footprint polygons and 10M point->polygon pairs)
-through the C ABI.  Inputs are resident in HBM before timing starts; the
-batch rotates over several device copies so that no step reads data the
-previous step left in the on-chip caches.  Prints one JSON line with
-throughput (point-edge tests/s, points/s), the dominant kernel's roofline
-fraction (kernel time from HIP events recorded on the launch stream), the
-bit-exact parity verdict against the CPU oracle, and the oracle's own speed
-on this host's cores.
+One step is one full pass of the hot path over one batch of the workload
+(default: the footprint workload, 100,000 building-footprint polygons and 10M
+point->polygon pairs) through a plan of the C ABI: counter resets and
+heaviest-first work ordering, the main kernel, and (filtered mode) the binary64
+recheck, launched as one HIP graph.  Inputs are resident in HBM before timing
+starts; the steps rotate over four device copies of the batch (one plan each) so
+that no step reads data the previous step left in the caches (the copies total
+more than the 256 MB last-level cache).
+
+Prints one JSON line: throughput (point-edge tests/s as `value`, points/s), the
+dominant kernel's HBM roofline fraction with its duration taken from HIP events
+recorded around it on the launch stream during the timed steps, the bit-exact
+parity verdict against the CPU oracle, the same path in the other arithmetic
+mode and the plain per-pair baseline kernel for comparison, and the oracle's own
+speed on this host's cores.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -38,9 +46,20 @@ WORKLOAD_TEXT = {
     5: "stress: batched topology in metres (offset 5e6, 5-50 m), 3% of points on/near edges and vertices",
 }
 
-# Traffic measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE) for the dominant kernel at the
-# default workload, scaled by the calibration copy; None until counters exist for the current kernel.
-PROFILED_TRAFFIC = {}
+# HBM traffic of the main kernel per launch, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
+# of this benchmark (bytes, after scaling by the counters' reading of a copy kernel of known size).
+# Keyed by (config, mode, kernel-source digest): an entry stops applying as soon as the kernel
+# sources change, and the benchmark then reports traffic as null.
+PROFILED_TRAFFIC: dict = {}
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2306_04316_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
 
 
 def parse():
@@ -50,12 +69,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", default="exact", choices=["exact"])
+    ap.add_argument("--mode", default="exact", choices=["exact", "filtered"])
     ap.add_argument("--kernel", default="auto", choices=["auto", "per_pair", "segmented", "staged"])
     ap.add_argument("--pairs-per-lane", type=int, default=0)
-    ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--lds-slots", type=int, default=0)
+    ap.add_argument("--persistent", type=int, default=-1)
+    ap.add_argument("--order", type=int, default=-1)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip autotuning at plan creation")
     ap.add_argument("--copies", type=int, default=4, help="device copies the steps rotate over")
+    ap.add_argument("--compare-steps", type=int, default=10,
+                    help="steps for the other-mode and per-pair comparison runs (0 = skip them)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle timing budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -74,19 +98,28 @@ def host_threads() -> int:
     return max(1, n)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, budget_s: float):
-    """Time the oracle as it stands on this host's cores over whole passes of a bounded sample."""
+    """The oracle as it stands, on this host's cores, over whole passes of a bounded sample."""
     import oracle
+    from paper_2306_04316_amd import workloads as W
     th = host_threads()
     n = w.n_points
-    # size a sample that takes about budget_s: probe with a small slice first
     probe_n = min(n, 20_000)
     t0 = time.perf_counter()
-    idx = np.arange(probe_n)
-    from paper_2306_04316_amd import workloads as W
-    oracle.classify_workload(W.subsample(w, idx), nthreads=th)
+    oracle.classify_workload(W.subsample(w, np.arange(probe_n)), nthreads=th)
     dt = max(time.perf_counter() - t0, 1e-6)
-    want = int(min(n, max(probe_n, probe_n * budget_s / dt)))
+    want = int(min(n, max(probe_n, probe_n * 0.5 * budget_s / dt)))
     if want >= n:
         s, label = w, f"the full workload ({n} pairs)"
     else:
@@ -101,28 +134,58 @@ def cpu_baseline(w, budget_s: float):
         if el >= 0.5 * budget_s:
             break
     per = el / reps
-    tests = s.n_tests
-    return {"value": tests / per, "unit": "tests/s", "points_per_s": s.n_points / per, "cores": th,
-            "kind": "oracle", "sample": f"{label}, {reps} pass(es), {per:.3f} s per pass",
+    return {"value": s.n_tests / per, "unit": "tests/s", "points_per_s": s.n_points / per, "cores": th,
+            "kind": "oracle", "sample": f"{label}, {reps} pass(es), {per:.4f} s per pass",
             "cpu_model": cpu_model()}
 
 
-def cpu_model() -> str:
-    try:
-        with open("/proc/cpuinfo") as f:
-            for ln in f:
-                if ln.startswith("model name"):
-                    return ln.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
+class Runner:
+    """Plans over rotating device copies of one workload; times every step with HIP events
+    recorded on the launch stream just before and after the plan's (graph) launch."""
+
+    def __init__(self, P, copies, plan_opts):
+        self.plans = [P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], out=d["out"],
+                             **plan_opts) for d in copies]
+        self.timed = bool(plan_opts.get("timing"))
+
+    def run(self, steps, warmup):
+        import torch
+        n = len(self.plans)
+        for i in range(warmup):
+            self.plans[i % n].execute()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        phase = []
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        start.record()
+        for i in range(steps):
+            if self.timed and i >= n:
+                # before this plan runs again, read the phase events of its previous execution
+                # (enqueued n steps ago; waits for that execution only, n - 1 steps stay queued)
+                phase.append(self.plans[i % n].timing())
+            ev[i][0].record()
+            self.plans[i % n].execute()
+            ev[i][1].record()
+        stop.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if self.timed:
+            for i in range(max(0, steps - n), steps):
+                phase.append(self.plans[i % n].timing())
+        step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+        return start.elapsed_time(stop) / steps, step_ms, (np.array(phase) if phase else None), wall
+
+    def close(self):
+        for p in self.plans:
+            p.close()
 
 
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
-                                   "(the pairs are independent: the multi-GPU split is a partition "
+                                   "(the pairs are independent: a multi-GPU split is a partition "
                                    "of polygons with their points, with no exchange)"}), flush=True)
         sys.exit(2)
     import torch
@@ -146,70 +209,82 @@ def main():
     w = W.make(a.config, seed=a.seed)
     t_gen = time.perf_counter() - t_gen
     copies = []
-    for c in range(max(1, a.copies)):
+    for _ in range(max(1, a.copies)):
         d = P.to_device(w, dev)
         d["out"] = torch.empty(w.n_points, dtype=torch.uint8, device=dev)
         copies.append(d)
     torch.cuda.synchronize()
 
-    def step(i, ev=None):
-        d = copies[i % len(copies)]
-        if ev is not None:
-            ev[0].record()
-        P.classify(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], kernel=a.kernel,
-                   out=d["out"], pairs_per_lane=a.pairs_per_lane, block=a.block, lds_slots=a.lds_slots)
-        if ev is not None:
-            ev[1].record()
+    def plan_opts(mode, kernel):
+        return dict(mode=mode, kernel=kernel, pairs_per_lane=a.pairs_per_lane, lds_slots=a.lds_slots,
+                    persistent=a.persistent, order=a.order, use_graph=not a.no_graph,
+                    tune=0 if (a.no_tune or kernel in ("per_pair", "segmented")) else 1)
 
-    for i in range(a.warmup):
-        step(i)
-    torch.cuda.synchronize()
-
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record()
-    for i in range(a.steps):
-        step(a.warmup + i, evs[i])
-    stop.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = start.elapsed_time(stop)
-    kern_ms = [e0.elapsed_time(e1) for (e0, e1) in evs]
-    ms_per_step = gpu_ms / a.steps
-
-    T = w.n_tests
-    N = w.n_points
-    value = T / (ms_per_step * 1e-3)
-    kern_avg = float(np.mean(kern_ms))
+    T, N = w.n_tests, w.n_points
+    runner = Runner(P, copies, plan_opts(a.mode, a.kernel))
+    cfg = runner.plans[0].config()
+    ms_per_step, step_ms, _, wall = runner.run(a.steps, a.warmup)
+    runner.close()
+    # Phase breakdown from eager executions with events between the phases (same plan options,
+    # not graph-launched); when the graph holds the main kernel alone, the per-step events of the
+    # timed region above bracket exactly that kernel.
+    rt = Runner(P, copies, dict(plan_opts(a.mode, a.kernel), timing=True, tune=0,
+                                pairs_per_lane=cfg["pairs_per_lane"], lds_slots=cfg["lds_slots"],
+                                persistent=cfg["persistent"], order=cfg["order"]))
+    _, _, phase, _ = rt.run(max(8, min(a.steps, 20)), 2)
+    rt.close()
+    single_kernel = (a.mode == "exact" and not cfg["persistent"] and not cfg["order"])
+    main_ms = float(np.mean(step_ms)) if single_kernel else float(np.mean(phase[:, 1]))
+    main_src = ("HIP events around each graph launch in the timed region (the graph holds only the main kernel)"
+                if single_kernel else "HIP events around the main kernel in eager timed executions")
     alg_bytes = w.nbytes_algorithmic()
-    achieved = alg_bytes / (kern_avg * 1e-3) / 1e9
+    achieved = alg_bytes / (main_ms * 1e-3) / 1e9
+    last = copies[(a.warmup + a.steps - 1) % len(copies)]["out"]
 
     parity = "not checked"
+    want = None
     if not a.no_parity:
         import oracle
-        got = copies[(a.warmup + a.steps - 1) % len(copies)]["out"].cpu().numpy()
-        if w.n_tests <= 5_000_000_000:
+        got = last.cpu().numpy()
+        if T <= 5_000_000_000:
             want = oracle.classify_workload(w, nthreads=host_threads())
             nbad = int(np.count_nonzero(got != want))
             parity = "bit-exact (all pairs)" if nbad == 0 else f"MISMATCH in {nbad} pairs"
         else:
-            rng = np.random.default_rng(1)
-            idx = np.sort(rng.choice(N, 2000, replace=False))
-            want = oracle.classify_workload(W.subsample(w, idx), nthreads=host_threads())
-            nbad = int(np.count_nonzero(got[idx] != want))
-            parity = (f"bit-exact (2000 sampled pairs)" if nbad == 0
+            idx = np.sort(np.random.default_rng(1).choice(N, 2000, replace=False))
+            ws = oracle.classify_workload(W.subsample(w, idx), nthreads=host_threads())
+            nbad = int(np.count_nonzero(got[idx] != ws))
+            parity = ("bit-exact (2000 sampled pairs)" if nbad == 0
                       else f"MISMATCH in {nbad} of 2000 sampled pairs")
 
-    cpu = None
-    if not a.no_cpu_baseline:
-        cpu = cpu_baseline(w, a.cpu_seconds)
+    compare = {}
+    if a.compare_steps > 0:
+        other = "filtered" if a.mode == "exact" else "exact"
+        for label, opts in (("mode_" + other, plan_opts(other, "auto")),
+                            ("per_pair_baseline", plan_opts("exact", "per_pair"))):
+            r = Runner(P, copies, dict(opts, timing=True))
+            st = r.plans[0]
+            ms, _, ph, _ = r.run(a.compare_steps, 2)
+            entry = {"ms_per_step_eager": ms, "main_kernel_ms": float(np.mean(ph[:, 1])),
+                     "prep_ms": float(np.mean(ph[:, 0])), "config": st.config()}
+            if opts["mode"] == "filtered":
+                s = st.stats()
+                entry["recheck_fraction"] = s["rechecked_pairs"] / max(1, N)
+                entry["recheck_ms"] = float(np.mean(ph[:, 2]))
+            if want is not None:
+                got = copies[(2 + a.compare_steps - 1) % len(copies)]["out"].cpu().numpy()
+                entry["parity"] = "bit-exact" if np.array_equal(got, want) else "MISMATCH"
+            r.close()
+            compare[label] = entry
+        compare["main_kernel_speedup_vs_per_pair"] = compare["per_pair_baseline"]["main_kernel_ms"] / main_ms
 
-    traffic = PROFILED_TRAFFIC.get((a.config, a.mode, a.kernel))
+    cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
+
+    digest = kernel_digest()
+    traffic = PROFILED_TRAFFIC.get((a.config, a.mode, digest))
     rec = {
         "metric": METRIC,
-        "value": value,
+        "value": T / (ms_per_step * 1e-3),
         "unit": "tests/s",
         "points_per_s": N / (ms_per_step * 1e-3),
         "n_gpus": 1,
@@ -219,16 +294,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if a.mode == "exact" else "f32+f64",
         "data": "synthetic",
         "parity": parity,
-        "config": {"workload": WORKLOAD_TEXT[a.config], "config_id": a.config, "seed": a.seed,
-                   "pairs": N, "polygons": w.n_polys, "vertices": w.n_vertices, "tests": T,
-                   "mode": a.mode, "kernel": a.kernel, "device_copies": len(copies)},
+        "config": {"workload": WORKLOAD_TEXT[a.config], "config_id": a.config, "seed": a.seed, "pairs": N,
+                   "polygons": w.n_polys, "vertices": w.n_vertices, "tests": T, "mode": a.mode,
+                   "plan": cfg, "device_copies": len(copies)},
+        "phases_ms_eager": {"prep": float(np.mean(phase[:, 0])), "main": float(np.mean(phase[:, 1])),
+                            "recheck": float(np.mean(phase[:, 2]))},
+        "step_ms_events": {"mean": float(np.mean(step_ms)), "min": float(np.min(step_ms))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "main classification kernel", "kernel_ms": kern_avg,
-                     "alg_bytes_per_launch": alg_bytes},
+                     "kernel": "main classification kernel", "kernel_ms": main_ms, "kernel_ms_source": main_src,
+                     "alg_bytes_per_launch": alg_bytes, "kernel_digest": digest},
+        "compare": compare,
         "cpu_baseline": cpu,
         "wall_s_timed": wall,
         "gen_s": t_gen,

@@ -117,7 +117,8 @@ typedef struct {
                                -1 = automatic */
     int32_t order;          /* plans: 1 = items heaviest first (estimated edges x
                                pairs), 0 = natural order, -1 = automatic */
-    int32_t use_graph;      /* plans: 1 = capture the step sequence in a HIP graph */
+    int32_t use_graph;      /* plans: 1 = capture the step sequence in a HIP graph
+                               (ignored with timing = 1) */
     int32_t tune;           /* plans: 0 = no tuning; n > 0 = time the candidate
                                configurations on the plan's data at creation (n
                                timed runs each, n = 1 means 5) and keep the fastest */
@@ -128,6 +129,9 @@ typedef struct {
                                bit-exact results (0 disables the bound) */
     const char *tune_cache; /* plans: tuning cache file; NULL = environment variable
                                PIP_TUNE_CACHE, else no cache */
+    int32_t timing;         /* plans: 1 = record device-time events between the
+                               phases of every execution (executions then run
+                               eagerly, not as a graph) */
 } pip_options;
 
 /* Configuration a plan runs with (after automatic choices and tuning). */
@@ -206,8 +210,17 @@ PIP_API int pip_plan_create(pip_plan **out,
 /* Enqueue one execution on `stream` (asynchronous). */
 PIP_API int pip_plan_execute(pip_plan *plan, void *stream);
 
-/* Waits for the plan's last execution and reports its figures. */
+/* Waits for the plan's last execution and reports its figures (the phase
+ * times only when the plan was created with timing = 1). */
 PIP_API int pip_plan_stats(pip_plan *plan, pip_stats *stats);
+
+/*
+ * Device time (ms) of the last execution's phases: preparation, main
+ * kernel, recheck.  Needs a plan created with timing = 1 (PIP_ENOTSUP
+ * otherwise).  Waits only for that execution's end (not for the stream),
+ * so it can be called while later work is still queued.
+ */
+PIP_API int pip_plan_timing(pip_plan *plan, float *ms_prep, float *ms_main, float *ms_recheck);
 
 /* The configuration the plan runs with. */
 PIP_API int pip_plan_get_config(const pip_plan *plan, pip_plan_config *cfg);

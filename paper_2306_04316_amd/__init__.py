@@ -47,7 +47,7 @@ def _stream_handle(stream):
 
 def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block=0, lds_slots=0,
             persistent=-1, order=-1, use_graph=True, tune=0, force_recheck=False, bound_scale=1.0,
-            tune_cache=None) -> _lib.pip_options:
+            tune_cache=None, timing=False) -> _lib.pip_options:
     o = _lib.pip_options()
     _lib.load().pip_options_init(ctypes.byref(o))
     o.mode = _lib.MODES[mode] if isinstance(mode, str) else int(mode)
@@ -63,6 +63,7 @@ def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block
     o.force_recheck = 1 if force_recheck else 0
     o.bound_scale = float(bound_scale)
     o.tune_cache = tune_cache.encode() if tune_cache else None
+    o.timing = 1 if timing else 0
     return o
 
 
@@ -117,6 +118,12 @@ class Plan:
         st = _lib.pip_stats()
         _lib.check(self._lib.pip_plan_stats(self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in _lib.pip_stats._fields_}
+
+    def timing(self):
+        """(ms_prep, ms_main, ms_recheck) of the last execution; waits for that execution only."""
+        a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        _lib.check(self._lib.pip_plan_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def config(self) -> dict:
         c = _lib.pip_plan_config()

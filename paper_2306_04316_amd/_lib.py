@@ -26,7 +26,7 @@ class pip_options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("pairs_per_lane", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("lds_slots", ctypes.c_int32), ("persistent", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("tune", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
-                ("bound_scale", ctypes.c_float), ("tune_cache", ctypes.c_char_p)]
+                ("bound_scale", ctypes.c_float), ("tune_cache", ctypes.c_char_p), ("timing", ctypes.c_int32)]
 
 
 class pip_plan_config(ctypes.Structure):
@@ -55,6 +55,8 @@ _SIGS = {
                                        ctypes.POINTER(pip_options), _VP]),
     "pip_plan_execute": (ctypes.c_int, [_VP, _VP]),
     "pip_plan_stats": (ctypes.c_int, [_VP, ctypes.POINTER(pip_stats)]),
+    "pip_plan_timing": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                       ctypes.POINTER(ctypes.c_float)]),
     "pip_plan_get_config": (ctypes.c_int, [_VP, ctypes.POINTER(pip_plan_config)]),
     "pip_plan_destroy": (ctypes.c_int, [_VP]),
 }

@@ -1,6 +1,7 @@
 // C ABI entry points: argument checks, device checks, kernel selection.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -31,6 +32,22 @@ int fail(int code, const char *fmt, ...)
 }
 
 void clear_error() { g_err[0] = '\0'; }
+
+void log_msg(const char *fmt, ...)
+{
+    static const bool on = [] {
+        const char *e = getenv("PIP_LOG");
+        return e && e[0] && e[0] != '0';
+    }();
+    if (!on)
+        return;
+    va_list ap;
+    va_start(ap, fmt);
+    fputs("[pip] ", stderr);
+    vfprintf(stderr, fmt, ap);
+    fputc('\n', stderr);
+    va_end(ap);
+}
 
 int current_device(DeviceInfo **out)
 {
@@ -126,6 +143,7 @@ void pip_options_init(pip_options *opts)
     opts->force_recheck = 0;
     opts->bound_scale = 1.0f;
     opts->tune_cache = NULL;
+    opts->timing = 0;
 }
 
 int pip_abi_version(void) { return PIP_ABI_VERSION; }

@@ -11,6 +11,8 @@ namespace pip {
 // ---------------------------------------------------------------- errors
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
+// Diagnostics to stderr when the environment variable PIP_LOG is set (and not "0").
+void log_msg(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 
 #define PIP_HIP_TRY(expr)                                                              \
     do {                                                                               \

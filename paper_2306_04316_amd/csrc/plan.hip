@@ -32,6 +32,7 @@ struct pip_plan {
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool executed = false;
+    bool timed = false;   // the last execution recorded the phase events
 };
 
 namespace pip {
@@ -68,45 +69,60 @@ int resolve_grid(pip_plan *pl, pip_plan_config &c)
     return PIP_OK;
 }
 
-// Enqueue one execution of the plan's step sequence with configuration c.
-int enqueue(pip_plan *pl, const pip_plan_config &c, hipStream_t s, bool capturing)
+// The step sequence, in three phases; eager executions record the plan's
+// events between them, graph executions get event-record nodes instead.
+enum Phase { kPrep = 0, kMain = 1, kRecheck = 2 };
+
+bool phase_empty(const pip_plan *pl, const pip_plan_config &c, int ph)
 {
-    auto rec = [&](int k) -> int {
-        hipError_t e = capturing ? hipEventRecordWithFlags(pl->ev[k], s, hipEventRecordExternal)
-                                 : hipEventRecord(pl->ev[k], s);
-        if (e != hipSuccess)
-            return fail(PIP_EHIP, "hipEventRecord failed: %s", hipGetErrorString(e));
-        return PIP_OK;
-    };
+    if (pl->p.n_points == 0)
+        return true;
+    if (ph == kPrep)   // counters (queue, recheck count) or the item order are needed
+        return !(staged_kind(c) && (c.persistent || c.mode == PIP_MODE_FILTERED_FP32 ||
+                                    (c.order == 1 && pl->p.point_poly)));
+    if (ph == kRecheck)
+        return c.mode != PIP_MODE_FILTERED_FP32;
+    return false;
+}
+
+int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
+{
     const Problem &p = pl->p;
-    PIP_TRY(rec(0));
-    if (p.n_points > 0) {
-        const bool staged = staged_kind(c);
+    if (phase_empty(pl, c, ph))
+        return PIP_OK;
+    const bool lpt = staged_kind(c) && c.order == 1 && p.point_poly;
+    if (ph == kPrep) {
         PIP_TRY(launch_fill(pl->counters + kQueue, kCounters - kQueue, 0u, s));
-        const bool lpt = staged && c.order == 1 && p.point_poly;
         if (lpt)
             PIP_TRY(launch_item_order(p, s, item_pairs_of(c), c.n_items, pl->bucket, pl->counters, pl->order));
-        PIP_TRY(rec(1));
+        return PIP_OK;
+    }
+    if (ph == kMain) {
         unsigned *queue = c.persistent ? pl->counters + kQueue : nullptr;
         const int32_t *order = lpt ? pl->order : nullptr;
-        if (c.mode == PIP_MODE_FILTERED_FP32) {
-            PIP_TRY(launch_filtered(p, s, c.pairs_per_lane, c.lds_slots, pl->o.bound_scale, pl->o.force_recheck,
-                                    pl->recheck, pl->counters + kRecheckCount, order, c.n_items, queue, c.grid));
-        } else if (c.kernel == PIP_KERNEL_PER_PAIR) {
-            PIP_TRY(launch_per_pair(p, s));
-        } else if (c.kernel == PIP_KERNEL_SEGMENTED) {
-            PIP_TRY(launch_segmented(p, s, c.pairs_per_lane, 256));
-        } else {
-            PIP_TRY(launch_staged_batched(p, s, c.pairs_per_lane, c.lds_slots, order, c.n_items, queue, c.grid));
-        }
-        PIP_TRY(rec(2));
         if (c.mode == PIP_MODE_FILTERED_FP32)
-            PIP_TRY(launch_recheck(p, s, pl->recheck, pl->counters + kRecheckCount, pl->cu_count * 8));
-    } else {
-        PIP_TRY(rec(1));
-        PIP_TRY(rec(2));
+            return launch_filtered(p, s, c.pairs_per_lane, c.lds_slots, pl->o.bound_scale, pl->o.force_recheck,
+                                   pl->recheck, pl->counters + kRecheckCount, order, c.n_items, queue, c.grid);
+        if (c.kernel == PIP_KERNEL_PER_PAIR)
+            return launch_per_pair(p, s);
+        if (c.kernel == PIP_KERNEL_SEGMENTED)
+            return launch_segmented(p, s, c.pairs_per_lane, 256);
+        return launch_staged_batched(p, s, c.pairs_per_lane, c.lds_slots, order, c.n_items, queue, c.grid);
     }
-    PIP_TRY(rec(3));
+    return launch_recheck(p, s, pl->recheck, pl->counters + kRecheckCount, pl->cu_count * 8);
+}
+
+// Enqueue one eager execution of the step sequence with configuration c,
+// with the plan's phase events when `timed`.
+int enqueue(pip_plan *pl, const pip_plan_config &c, hipStream_t s, bool timed)
+{
+    for (int ph = 0; ph < 3; ++ph) {
+        if (timed)
+            PIP_HIP_TRY(hipEventRecord(pl->ev[ph], s));
+        PIP_TRY(enqueue_phase(pl, c, s, ph));
+    }
+    if (timed)
+        PIP_HIP_TRY(hipEventRecord(pl->ev[3], s));
     return PIP_OK;
 }
 
@@ -120,28 +136,29 @@ void drop_graph(pip_plan *pl)
     pl->graph = nullptr;
 }
 
+// The graph: the whole step sequence captured from one stream, kernel nodes
+// only (event-record nodes would add several microseconds per execution;
+// phase timings come from eager executions with timing enabled).
 int build_graph(pip_plan *pl)
 {
     drop_graph(pl);
     hipStream_t cs = nullptr;
     PIP_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     int rc = PIP_OK;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
         rc = fail(PIP_EHIP, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
     } else {
-        rc = enqueue(pl, pl->cfg, cs, true);
+        rc = enqueue(pl, pl->cfg, cs, false);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cs, &g);
         if (rc == PIP_OK && e != hipSuccess)
             rc = fail(PIP_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        pl->graph = g;
         if (rc == PIP_OK) {
-            pl->graph = g;
             e = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0);
             if (e != hipSuccess)
                 rc = fail(PIP_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
-        } else if (g) {
-            (void)hipGraphDestroy(g);
         }
     }
     (void)hipStreamDestroy(cs);
@@ -225,7 +242,7 @@ int time_candidate(pip_plan *pl, pip_plan_config &c, hipStream_t s, int reps, fl
     PIP_TRY(resolve_grid(pl, c));
     std::vector<float> t;
     for (int r = 0; r < reps + 2; ++r) {
-        PIP_TRY(enqueue(pl, c, s, false));
+        PIP_TRY(enqueue(pl, c, s, true));
         PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
         float a = 0.f;
         PIP_HIP_TRY(hipEventElapsedTime(&a, pl->ev[0], pl->ev[3]));
@@ -331,7 +348,7 @@ int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t 
     c.lds_slots = o.lds_slots > 0 ? std::min(o.lds_slots, 2048) : 256;
     c.persistent = o.persistent >= 0 ? (o.persistent ? 1 : 0) : (point_poly ? 1 : 0);
     c.order = o.order >= 0 ? (o.order ? 1 : 0) : (point_poly ? 1 : 0);
-    c.use_graph = o.use_graph ? 1 : 0;
+    c.use_graph = (o.use_graph && !o.timing) ? 1 : 0;
     if (c.pairs_per_lane != 1 && c.pairs_per_lane != 2 && c.pairs_per_lane != 4)
         c.pairs_per_lane = 4;
 
@@ -381,6 +398,7 @@ int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t 
     if (rc == PIP_OK && c.use_graph) {
         if (build_graph(pl) != PIP_OK) {
             c.use_graph = 0;   // capture unsupported here: run the same sequence eagerly
+            log_msg("graph capture failed, running eagerly: %s", pip_last_error());
             clear_error();
             (void)hipGetLastError();
         }
@@ -405,8 +423,10 @@ int pip_plan_execute(pip_plan *pl, void *stream)
     hipStream_t s = (hipStream_t)stream;
     if (pl->exec) {
         PIP_HIP_TRY(hipGraphLaunch(pl->exec, s));
+        pl->timed = false;
     } else {
-        PIP_TRY(enqueue(pl, pl->cfg, s, false));
+        PIP_TRY(enqueue(pl, pl->cfg, s, pl->o.timing != 0));
+        pl->timed = pl->o.timing != 0;
     }
     pl->executed = true;
     return PIP_OK;
@@ -421,15 +441,34 @@ int pip_plan_stats(pip_plan *pl, pip_stats *st)
     st->pairs = (uint64_t)pl->p.n_points;
     if (!pl->executed)
         return PIP_OK;
-    PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
-    PIP_HIP_TRY(hipEventElapsedTime(&st->ms_prep, pl->ev[0], pl->ev[1]));
-    PIP_HIP_TRY(hipEventElapsedTime(&st->ms_main, pl->ev[1], pl->ev[2]));
-    PIP_HIP_TRY(hipEventElapsedTime(&st->ms_recheck, pl->ev[2], pl->ev[3]));
+    if (pl->timed) {
+        PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
+        PIP_HIP_TRY(hipEventElapsedTime(&st->ms_prep, pl->ev[0], pl->ev[1]));
+        PIP_HIP_TRY(hipEventElapsedTime(&st->ms_main, pl->ev[1], pl->ev[2]));
+        PIP_HIP_TRY(hipEventElapsedTime(&st->ms_recheck, pl->ev[2], pl->ev[3]));
+    }
     if (pl->recheck) {
         unsigned cnt = 0;
         PIP_HIP_TRY(hipMemcpy(&cnt, pl->counters + kRecheckCount, sizeof cnt, hipMemcpyDeviceToHost));
         st->rechecked_pairs = cnt;
     }
+    return PIP_OK;
+}
+
+int pip_plan_timing(pip_plan *pl, float *ms_prep, float *ms_main, float *ms_recheck)
+{
+    clear_error();
+    if (!pl || !ms_prep || !ms_main || !ms_recheck)
+        return fail(PIP_EINVAL, "NULL argument");
+    *ms_prep = *ms_main = *ms_recheck = 0.f;
+    if (!pl->executed)
+        return PIP_OK;
+    if (!pl->timed)
+        return fail(PIP_ENOTSUP, "the last execution was not timed (create the plan with timing = 1)");
+    PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
+    PIP_HIP_TRY(hipEventElapsedTime(ms_prep, pl->ev[0], pl->ev[1]));
+    PIP_HIP_TRY(hipEventElapsedTime(ms_main, pl->ev[1], pl->ev[2]));
+    PIP_HIP_TRY(hipEventElapsedTime(ms_recheck, pl->ev[2], pl->ev[3]));
     return PIP_OK;
 }
 
