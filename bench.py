@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", default="exact", choices=["exact", "filtered"])
-    ap.add_argument("--kernel", default="auto", choices=["auto", "per_pair", "segmented", "staged"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "per_pair", "segmented", "staged", "runs"])
     ap.add_argument("--pairs-per-lane", type=int, default=0)
     ap.add_argument("--lds-slots", type=int, default=0)
     ap.add_argument("--persistent", type=int, default=-1)
@@ -219,6 +219,7 @@ def main():
         return dict(mode=mode, kernel=kernel, pairs_per_lane=a.pairs_per_lane, lds_slots=a.lds_slots,
                     persistent=a.persistent, order=a.order, use_graph=not a.no_graph,
                     tune=0 if (a.no_tune or kernel in ("per_pair", "segmented")) else 1)
+
 
     T, N = w.n_tests, w.n_points
     runner = Runner(P, copies, plan_opts(a.mode, a.kernel))

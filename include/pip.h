@@ -99,7 +99,12 @@ typedef enum {
     /* one lane per pair; a workgroup copies the rings its (sorted) pairs
      * test into LDS once and every lane walks its own ring from there;
      * workgroups whose rings do not fit fall back to the segmented walk */
-    PIP_KERNEL_STAGED = 3
+    PIP_KERNEL_STAGED = 3,
+    /* one lane per pair; each wavefront splits its pairs into runs of equal
+     * polygon id (at most 64 pairs each) and walks each run's ring
+     * wave-uniformly: an exact straddle pass into per-lane bit words, then
+     * side values only for each lane's straddling edges */
+    PIP_KERNEL_RUNS = 4
 } pip_kernel;
 
 typedef struct {

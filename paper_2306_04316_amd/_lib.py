@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "PIP_OK", -1: "PIP_EINVAL", -2: "PIP_ERANGE", -3: "PIP_EDOM",
                 -5: "PIP_EHIP", -6: "PIP_ENOTSUP"}
 
 MODES = {"exact": 0, "fp64": 0, "filtered": 1, "fp32": 1}
-KERNELS = {"auto": 0, "per_pair": 1, "segmented": 2, "staged": 3}
+KERNELS = {"auto": 0, "per_pair": 1, "segmented": 2, "staged": 3, "runs": 4}
 
 
 class PipError(RuntimeError):

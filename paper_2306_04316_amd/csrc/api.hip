@@ -165,7 +165,7 @@ int pip_classify(const double *px, const double *py, int64_t n_points, const int
     }
     if (o.mode != PIP_MODE_EXACT_FP64)
         return fail(PIP_EINVAL, "pip_classify supports PIP_MODE_EXACT_FP64 only (mode=%d); use a plan", o.mode);
-    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_STAGED)
+    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_RUNS)
         return fail(PIP_EINVAL, "unknown kernel %d", o.kernel);
     Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
     PIP_TRY(check_host_args(p));
@@ -181,6 +181,10 @@ int pip_classify(const double *px, const double *py, int64_t n_points, const int
     if (o.kernel == PIP_KERNEL_SEGMENTED)
         return launch_segmented(p, s, o.pairs_per_lane, o.block);
     const int ppl = o.pairs_per_lane > 0 ? o.pairs_per_lane : 4;
+    if (o.kernel == PIP_KERNEL_RUNS || o.kernel == PIP_KERNEL_AUTO) {
+        const int u = ppl == 1 ? 1 : (ppl == 2 ? 2 : 4);
+        return launch_runs_batched(p, s, u, nullptr, (int)((n_points + 256 * u - 1) / (256 * u)), nullptr, 0);
+    }
     return launch_staged(p, s, ppl, clamp_lds_slots(o.lds_slots > 0 ? o.lds_slots : 256, false, ppl, dev));
 }
 

@@ -322,6 +322,102 @@ __global__ __launch_bounds__(256) void k_staged_batched_fp64(
     }
 }
 
+// ---------------------------------------------------------------- runs (polygon-aligned rows)
+// A workgroup item is 1024 consecutive pairs; wavefront w owns pairs
+// item + 64*U*w .. +64*U (row u in registers: pair + 64u + lane, coalesced
+// loads, all issued before any arithmetic).  The wavefront parks its points
+// and polygon ids in a private LDS region and walks them as runs: a run is at
+// most 64 consecutive pairs with the same polygon id (found with one ballot),
+// processed with the ring wave-uniform -- its y values stream through scalar
+// loads into each lane's straddle bits (two vector instructions per vertex),
+// then every lane evaluates the side value for its own straddling edges only.
+// A run has a single polygon, so no lane waits for another polygon's ring,
+// and the ring's size is the run's cost whatever it is (3 or 10^6 vertices).
+template <int U>
+__device__ __forceinline__ void runs_item_fp64(
+    int64_t p0, const double *__restrict__ px, const double *__restrict__ py, int64_t n,
+    const int64_t *__restrict__ offsets, int64_t n_polys,
+    const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
+    const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, unsigned char *smem)
+{
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    constexpr int WP = 64 * U;   // pairs per wavefront
+    const int64_t wbase = p0 + (int64_t)wid * WP;
+    double2 *P = (double2 *)smem + wid * WP;
+    int *Q = (int *)((double2 *)smem + 4 * WP) + wid * WP;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = wbase + u * 64 + lane;
+        double xv = 0.0, yv = 0.0;
+        int qv = 0;
+        if (i < n) {
+            xv = px[i];
+            yv = py[i];
+            if (point_poly) {
+                qv = point_poly[i];
+                qv = ((uint32_t)qv < (uint64_t)n_polys) ? qv : 0;
+            }
+        }
+        P[u * 64 + lane] = make_double2(xv, yv);
+        Q[u * 64 + lane] = qv;
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // wave-private LDS: own writes visible to own reads
+    __builtin_amdgcn_wave_barrier();
+    const int64_t left = n - wbase;
+    const int wn = left <= 0 ? 0 : (left < WP ? (int)left : WP);
+    int s = 0;
+    while (s < wn) {
+        const int qs = __builtin_amdgcn_readfirstlane(Q[s]);
+        const int j = s + lane;
+        const bool same = j < wn && Q[j < WP ? j : WP - 1] == qs;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(same);
+        const int cnt = (~m == 0) ? 64 : __builtin_ctzll(~m);
+        const bool member = lane < cnt;
+        const double2 pt = P[j < WP ? j : WP - 1];
+        int64_t b = offsets[qs], e = offsets[qs + 1];
+        clamp_ring(b, e, nv);
+        const uint64_t par = ring_parity_compact_uniform(pt.x, pt.y, member, vx, vy, b, e);
+        if (member)
+            inside[wbase + j] = (uint8_t)((par >> lane) & 1u);
+        s += cnt;
+    }
+}
+
+// LDS per workgroup: 4 wavefronts x 64*U pairs x (point 16 B + polygon id 4 B)
+inline size_t runs_lds_bytes(int pairs_per_lane) { return (size_t)4 * 64 * pairs_per_lane * (16 + 4); }
+
+template <int U>
+__global__ __launch_bounds__(256) void k_runs_batched_fp64(
+    const double *__restrict__ px, const double *__restrict__ py, int64_t n,
+    const int64_t *__restrict__ offsets, int64_t n_polys,
+    const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
+    const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside,
+    const int32_t *__restrict__ order, int n_items, unsigned *queue)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item;
+    if (!queue) {
+        const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
+        runs_item_fp64<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside,
+                          smem);
+        return;
+    }
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items)
+            break;
+        const int item = order ? order[it] : it;
+        runs_item_fp64<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside,
+                          smem);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- validation
 __global__ __launch_bounds__(256) void k_validate_points(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
@@ -460,6 +556,49 @@ int staged_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<4>, 256, shmem);
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<2>, 256, shmem);
+    if (e != hipSuccess)
+        return fail(PIP_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
+    *blocks_per_cu = nb < 1 ? 1 : nb;
+    return PIP_OK;
+}
+
+size_t runs_smem_bytes(int pairs_per_lane) { return runs_lds_bytes(pairs_per_lane); }
+
+int launch_runs_batched(const Problem &p, hipStream_t stream, int pairs_per_lane, const int32_t *order,
+                        int n_items, unsigned *queue, int grid)
+{
+    const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
+    const size_t shmem = runs_smem_bytes(U);
+    if (!queue)
+        grid = n_items;
+    if (grid <= 0)
+        return PIP_OK;
+#define PIP_LAUNCH_R(UU)                                                                                         \
+    hipLaunchKernelGGL((k_runs_batched_fp64<UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py, p.n_points,  \
+                       p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside, order, n_items, queue)
+    if (U == 1)
+        PIP_LAUNCH_R(1);
+    else if (U == 4)
+        PIP_LAUNCH_R(4);
+    else
+        PIP_LAUNCH_R(2);
+#undef PIP_LAUNCH_R
+    PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
+
+int runs_occupancy(int pairs_per_lane, int *blocks_per_cu)
+{
+    const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
+    const size_t shmem = runs_smem_bytes(U);
+    int nb = 0;
+    hipError_t e;
+    if (U == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_runs_batched_fp64<1>, 256, shmem);
+    else if (U == 4)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_runs_batched_fp64<4>, 256, shmem);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_runs_batched_fp64<2>, 256, shmem);
     if (e != hipSuccess)
         return fail(PIP_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
     *blocks_per_cu = nb < 1 ? 1 : nb;

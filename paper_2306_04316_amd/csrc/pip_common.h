@@ -62,6 +62,10 @@ int launch_per_pair(const Problem &p, hipStream_t stream);
 int launch_segmented(const Problem &p, hipStream_t stream, int pairs_per_lane, int block);
 int launch_staged(const Problem &p, hipStream_t stream, int pairs_per_lane, int lds_slots);
 size_t staged_smem_bytes(int max_edges, int max_rings);
+size_t runs_smem_bytes(int pairs_per_lane);
+int runs_occupancy(int pairs_per_lane, int *blocks_per_cu);
+int launch_runs_batched(const Problem &p, hipStream_t stream, int pairs_per_lane, const int32_t *order,
+                        int n_items, unsigned *queue, int grid);
 int staged_max_rings(int pairs_per_lane);
 int staged_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu);
 int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_lane, int max_edges,

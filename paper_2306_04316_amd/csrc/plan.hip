@@ -44,9 +44,12 @@ constexpr int kCounters = 68;
 
 int item_pairs_of(const pip_plan_config &c) { return 256 * c.pairs_per_lane; }
 
+// Kernels that take work items (runs of 256 * pairs_per_lane pairs) and so
+// support the persistent queue and the heaviest-first order.
 bool staged_kind(const pip_plan_config &c)
 {
-    return c.mode == PIP_MODE_FILTERED_FP32 || c.kernel == PIP_KERNEL_STAGED || c.kernel == PIP_KERNEL_AUTO;
+    return c.mode == PIP_MODE_FILTERED_FP32 || c.kernel == PIP_KERNEL_STAGED || c.kernel == PIP_KERNEL_RUNS ||
+           c.kernel == PIP_KERNEL_AUTO;
 }
 
 int resolve_grid(pip_plan *pl, pip_plan_config &c)
@@ -62,6 +65,8 @@ int resolve_grid(pip_plan *pl, pip_plan_config &c)
     int nb = 1;
     if (c.mode == PIP_MODE_FILTERED_FP32)
         PIP_TRY(filtered_occupancy(c.pairs_per_lane, c.lds_slots, &nb));
+    else if (c.kernel == PIP_KERNEL_RUNS)
+        PIP_TRY(runs_occupancy(c.pairs_per_lane, &nb));
     else
         PIP_TRY(staged_occupancy(c.pairs_per_lane, c.lds_slots, &nb));
     const int64_t g = (int64_t)nb * pl->cu_count;
@@ -107,6 +112,8 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
             return launch_per_pair(p, s);
         if (c.kernel == PIP_KERNEL_SEGMENTED)
             return launch_segmented(p, s, c.pairs_per_lane, 256);
+        if (c.kernel == PIP_KERNEL_RUNS)
+            return launch_runs_batched(p, s, c.pairs_per_lane, order, c.n_items, queue, c.grid);
         return launch_staged_batched(p, s, c.pairs_per_lane, c.lds_slots, order, c.n_items, queue, c.grid);
     }
     return launch_recheck(p, s, pl->recheck, pl->counters + kRecheckCount, pl->cu_count * 8);
@@ -192,7 +199,7 @@ const char *cache_path(const pip_plan *pl)
     return (e && e[0]) ? e : nullptr;
 }
 
-// Cache lines: "<key> <pairs_per_lane> <lds_slots> <persistent> <order> <ms>"
+// Cache lines: "<key> <kernel> <pairs_per_lane> <lds_slots> <persistent> <order> <use_graph> <ms>"
 bool cache_lookup(const pip_plan *pl, pip_plan_config &c)
 {
     const char *path = cache_path(pl);
@@ -203,17 +210,21 @@ bool cache_lookup(const pip_plan *pl, pip_plan_config &c)
         return false;
     const std::string key = tune_key(pl);
     char k[200];
-    int u, l, pe, od;
+    int kern, u, l, pe, od, gr;
     float ms;
     bool found = false;
-    while (fscanf(f, "%199s %d %d %d %d %f", k, &u, &l, &pe, &od, &ms) == 6) {
-        const bool sane = (u == 1 || u == 2 || u == 4) && l >= 16 && l <= 2048 && (pe == 0 || pe == 1) &&
-                          (od == 0 || od == 1);
+    while (fscanf(f, "%199s %d %d %d %d %d %d %f", k, &kern, &u, &l, &pe, &od, &gr, &ms) == 8) {
+        const bool sane = (kern == PIP_KERNEL_STAGED || kern == PIP_KERNEL_RUNS) && (u == 1 || u == 2 || u == 4) &&
+                          l >= 16 && l <= 2048 && (pe == 0 || pe == 1) && (od == 0 || od == 1) &&
+                          (gr == 0 || gr == 1) &&
+                          !(pl->o.mode == PIP_MODE_FILTERED_FP32 && kern != PIP_KERNEL_STAGED);
         if (key == k && sane) {
+            c.kernel = kern;
             c.pairs_per_lane = u;
             c.lds_slots = l;
             c.persistent = pe;
             c.order = od;
+            c.use_graph = gr && pl->o.use_graph && !pl->o.timing;
             c.tune_ms = ms;
             found = true;   // the last matching line wins
         }
@@ -230,8 +241,8 @@ void cache_store(const pip_plan *pl, const pip_plan_config &c)
     FILE *f = fopen(path, "a");
     if (!f)
         return;
-    fprintf(f, "%s %d %d %d %d %.6f\n", tune_key(pl).c_str(), c.pairs_per_lane, c.lds_slots, c.persistent, c.order,
-            c.tune_ms);
+    fprintf(f, "%s %d %d %d %d %d %d %.6f\n", tune_key(pl).c_str(), c.kernel, c.pairs_per_lane, c.lds_slots,
+            c.persistent, c.order, c.use_graph, c.tune_ms);
     fclose(f);
 }
 
@@ -254,6 +265,39 @@ int time_candidate(pip_plan *pl, pip_plan_config &c, hipStream_t s, int reps, fl
     return PIP_OK;
 }
 
+// Mean wall time per launch (ms) of `reps` back-to-back executions of the
+// plan as configured now (graph launches if it has a graph), between two
+// events on stream s.
+int time_launches(pip_plan *pl, hipStream_t s, int reps, float *ms_out)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    PIP_HIP_TRY(hipEventCreate(&a));
+    int rc = PIP_OK;
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess)
+        rc = fail(PIP_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+    for (int r = 0; r < 2 && rc == PIP_OK; ++r)
+        rc = pl->exec ? (hipGraphLaunch(pl->exec, s) == hipSuccess ? PIP_OK : fail(PIP_EHIP, "graph launch"))
+                      : enqueue(pl, pl->cfg, s, false);
+    if (rc == PIP_OK && hipEventRecord(a, s) != hipSuccess)
+        rc = fail(PIP_EHIP, "hipEventRecord failed");
+    for (int r = 0; r < reps && rc == PIP_OK; ++r)
+        rc = pl->exec ? (hipGraphLaunch(pl->exec, s) == hipSuccess ? PIP_OK : fail(PIP_EHIP, "graph launch"))
+                      : enqueue(pl, pl->cfg, s, false);
+    if (rc == PIP_OK && hipEventRecord(b, s) != hipSuccess)
+        rc = fail(PIP_EHIP, "hipEventRecord failed");
+    if (rc == PIP_OK && hipEventSynchronize(b) != hipSuccess)
+        rc = fail(PIP_EHIP, "hipEventSynchronize failed");
+    float ms = 0.f;
+    if (rc == PIP_OK && hipEventElapsedTime(&ms, a, b) != hipSuccess)
+        rc = fail(PIP_EHIP, "hipEventElapsedTime failed");
+    *ms_out = ms / (reps > 0 ? reps : 1);
+    (void)hipEventDestroy(a);
+    if (b)
+        (void)hipEventDestroy(b);
+    return rc;
+}
+
 int autotune(pip_plan *pl, hipStream_t s)
 {
     pip_plan_config best = pl->cfg;
@@ -262,17 +306,29 @@ int autotune(pip_plan *pl, hipStream_t s)
     std::vector<pip_plan_config> cands;
     const int lds_opts[] = {128, 256, 512, 1024};
     const int ppl_opts[] = {1, 2, 4};
-    for (int u : ppl_opts)
-        for (int l : lds_opts)
-            for (int pe = 0; pe <= 1; ++pe)
-                for (int od = 0; od <= (pl->p.point_poly ? 1 : 0); ++od) {
-                    pip_plan_config c = pl->cfg;
-                    c.pairs_per_lane = u;
-                    c.lds_slots = l;
-                    c.persistent = pe;
-                    c.order = od;
-                    cands.push_back(c);
-                }
+    std::vector<int> kernels;
+    if (pl->o.mode == PIP_MODE_FILTERED_FP32 || pl->o.kernel == PIP_KERNEL_STAGED)
+        kernels = {PIP_KERNEL_STAGED};
+    else if (pl->o.kernel == PIP_KERNEL_RUNS)
+        kernels = {PIP_KERNEL_RUNS};
+    else
+        kernels = {PIP_KERNEL_STAGED, PIP_KERNEL_RUNS};
+    for (int kern : kernels)
+        for (int u : ppl_opts)
+            for (int l : lds_opts) {
+                if (kern == PIP_KERNEL_RUNS && l != lds_opts[0])
+                    continue;   // the runs kernel stages nothing
+                for (int pe = 0; pe <= 1; ++pe)
+                    for (int od = 0; od <= (pl->p.point_poly ? 1 : 0); ++od) {
+                        pip_plan_config c = pl->cfg;
+                        c.kernel = kern;
+                        c.pairs_per_lane = u;
+                        c.lds_slots = l;
+                        c.persistent = pe;
+                        c.order = od;
+                        cands.push_back(c);
+                    }
+            }
     for (auto &c : cands) {
         float ms = 0.f;
         PIP_TRY(time_candidate(pl, c, s, reps, &ms));
@@ -285,7 +341,24 @@ int autotune(pip_plan *pl, hipStream_t s)
     best.tune_ms = best_ms;
     PIP_TRY(resolve_grid(pl, best));
     pl->cfg = best;
-    cache_store(pl, best);
+    // graph or eager launches: whichever issues the chosen sequence faster
+    if (pl->o.use_graph && !pl->o.timing) {
+        float eager = 0.f, graph = 0.f;
+        pl->cfg.use_graph = 0;
+        drop_graph(pl);
+        PIP_TRY(time_launches(pl, s, 4 * reps, &eager));
+        if (build_graph(pl) == PIP_OK) {
+            PIP_TRY(time_launches(pl, s, 4 * reps, &graph));
+            pl->cfg.use_graph = graph < eager ? 1 : 0;
+        } else {
+            clear_error();
+        }
+        drop_graph(pl);
+        log_msg("tuned: kernel %d ppl %d lds %d persistent %d order %d: %.4f ms/step eager, %.4f graph",
+                pl->cfg.kernel, pl->cfg.pairs_per_lane, pl->cfg.lds_slots, pl->cfg.persistent, pl->cfg.order, eager,
+                graph);
+    }
+    cache_store(pl, pl->cfg);
     return PIP_OK;
 }
 
@@ -300,7 +373,7 @@ int check_options(const pip_options *opts, pip_options &o)
     }
     if (o.mode != PIP_MODE_EXACT_FP64 && o.mode != PIP_MODE_FILTERED_FP32)
         return fail(PIP_EINVAL, "unknown mode %d", o.mode);
-    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_STAGED)
+    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_RUNS)
         return fail(PIP_EINVAL, "unknown kernel %d", o.kernel);
     if (o.mode == PIP_MODE_FILTERED_FP32 && (o.kernel == PIP_KERNEL_PER_PAIR || o.kernel == PIP_KERNEL_SEGMENTED))
         return fail(PIP_EINVAL, "the filtered mode runs on the staged kernel only");
@@ -343,7 +416,18 @@ int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t 
     memset(&c, 0, sizeof c);
     c.struct_size = sizeof c;
     c.mode = o.mode;
-    c.kernel = o.kernel == PIP_KERNEL_AUTO ? PIP_KERNEL_STAGED : o.kernel;
+    c.kernel = o.kernel;
+    if (o.kernel == PIP_KERNEL_AUTO) {
+        // rings shared by every pair of a large single polygon stream best through
+        // scalar loads; batched small rings best through LDS
+        c.kernel = PIP_KERNEL_STAGED;
+        if (o.mode == PIP_MODE_EXACT_FP64 && !point_poly && n_points > 0) {
+            int64_t o2[2] = {0, 0};
+            if (hipMemcpy(o2, offsets, sizeof o2, hipMemcpyDeviceToHost) == hipSuccess && o2[1] - o2[0] > 512)
+                c.kernel = PIP_KERNEL_RUNS;
+            (void)hipGetLastError();
+        }
+    }
     c.pairs_per_lane = o.pairs_per_lane > 0 ? o.pairs_per_lane : 4;
     c.lds_slots = o.lds_slots > 0 ? std::min(o.lds_slots, 2048) : 256;
     c.persistent = o.persistent >= 0 ? (o.persistent ? 1 : 0) : (point_poly ? 1 : 0);

@@ -139,9 +139,15 @@ __device__ __forceinline__ uint64_t ring_parity_compact_uniform(double x, double
             for (int t = 0; t < 32; ++t)
                 above = shift_in_above(above, yq, ry[c0 + t]);
         } else {
+            // partial chunk: batches of 8 (clamped to the ring's last vertex,
+            // whose extra bits are masked below), then left-align
+            int t = 0;
+            for (; t < m; t += 8) {
 #pragma unroll
-            for (int t = 0; t < 32; ++t)
-                above = shift_in_above(above, yq, ry[c0 + (t < m ? t : m - 1)]);
+                for (int tt = 0; tt < 8; ++tt)
+                    above = shift_in_above(above, yq, ry[c0 + (t + tt < m ? t + tt : m - 1)]);
+            }
+            above <<= (32 - t);
         }
         uint32_t strad = above ^ ((above >> 1) | (prev << 31));
         if (m < 32)

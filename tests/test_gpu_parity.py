@@ -15,7 +15,7 @@ from paper_2306_04316_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = ["per_pair", "segmented", "staged"]
+KERNELS = ["per_pair", "segmented", "staged", "runs"]
 
 
 @pytest.fixture(scope="module")
@@ -85,7 +85,7 @@ def test_fractal_full_sampled(P):
     import torch
     w = W.fractal()
     note(f"fractal full sampled N={w.n_points} V={w.n_vertices}")
-    got = run(P, w, "segmented")
+    got = run(P, w, "runs")
     rng = np.random.default_rng(11)
     idx = np.sort(rng.choice(w.n_points, 1500, replace=False))
     s = W.subsample(w, idx)

@@ -56,6 +56,12 @@ def test_plan_small(P, mode, name):
     assert cfg["use_graph"] == 1
 
 
+@pytest.mark.parametrize("mode", ["exact", "filtered"])
+@pytest.mark.parametrize("name", ["star", "batched", "fractal"])
+def test_plan_small_tuned(P, mode, name):
+    check_plan(P, SMALL[name](), name, mode=mode, tune=1)
+
+
 @pytest.mark.parametrize("persistent", [0, 1])
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("mode", ["exact", "filtered"])
@@ -148,6 +154,17 @@ def test_plan_baseline_kernels(P):
     check_plan(P, W.footprints(scale=0.01), "footprints", kernel="segmented")
 
 
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_plan_runs_kernel(P, name, persistent):
+    check_plan(P, SMALL[name](), name, kernel="runs", persistent=persistent)
+
+
+@pytest.mark.parametrize("ppl", [1, 2, 4])
+def test_plan_runs_tiles(P, ppl):
+    check_plan(P, W.stress(scale=0.01), "stress", kernel="runs", pairs_per_lane=ppl)
+
+
 def test_plan_unsorted_pairs(P):
     w = W.footprints(scale=0.01)
     s = W.subsample(w, np.random.default_rng(3).permutation(w.n_points))
@@ -174,10 +191,10 @@ def test_autotune_and_cache(P, tmp_path):
     st, cfg = check_plan(P, w, "batched", mode="exact", tune=1, tune_cache=cache)
     assert cfg["tuned"] == 1 and cfg["tune_ms"] > 0
     text = open(cache).read().split()
-    assert len(text) == 6
+    assert len(text) == 8
     st, cfg2 = check_plan(P, w, "batched", mode="exact", tune=1, tune_cache=cache)
     assert cfg2["tuned"] == 2
-    for k in ("pairs_per_lane", "lds_slots", "persistent", "order"):
+    for k in ("kernel", "pairs_per_lane", "lds_slots", "persistent", "order", "use_graph"):
         assert cfg2[k] == cfg[k]
 
 
