@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--persistent", type=int, default=-1)
     ap.add_argument("--order", type=int, default=-1)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--index", action="store_true",
+                    help="one polygon: y-indexed path (edges skipped by y-range tree, points in y order)")
     ap.add_argument("--no-tune", action="store_true", help="skip autotuning at plan creation")
     ap.add_argument("--copies", type=int, default=4, help="device copies the steps rotate over")
     ap.add_argument("--compare-steps", type=int, default=10,
@@ -181,6 +183,11 @@ class Runner:
             p.close()
 
 
+def progress(msg: str) -> None:
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -215,28 +222,32 @@ def main():
         copies.append(d)
     torch.cuda.synchronize()
 
-    def plan_opts(mode, kernel):
+    def plan_opts(mode, kernel, index=False):
         return dict(mode=mode, kernel=kernel, pairs_per_lane=a.pairs_per_lane, lds_slots=a.lds_slots,
-                    persistent=a.persistent, order=a.order, use_graph=not a.no_graph,
-                    tune=0 if (a.no_tune or kernel in ("per_pair", "segmented")) else 1)
+                    persistent=a.persistent, order=a.order, use_graph=not a.no_graph, index=index,
+                    tune=0 if (a.no_tune or index or kernel in ("per_pair", "segmented")) else 1)
 
 
     T, N = w.n_tests, w.n_points
-    runner = Runner(P, copies, plan_opts(a.mode, a.kernel))
+    progress(f"workload {a.config}: N={N} P={w.n_polys} V={w.n_vertices}; creating plans"
+             + ("" if a.no_tune or a.index else " (autotuning)"))
+    runner = Runner(P, copies, plan_opts(a.mode, a.kernel, a.index))
+    progress(f"plan config {runner.plans[0].config()}; timed run of {a.steps} steps")
     cfg = runner.plans[0].config()
     ms_per_step, step_ms, _, wall = runner.run(a.steps, a.warmup)
     runner.close()
     # Phase breakdown from eager executions with events between the phases (same plan options,
     # not graph-launched); when the graph holds the main kernel alone, the per-step events of the
     # timed region above bracket exactly that kernel.
-    rt = Runner(P, copies, dict(plan_opts(a.mode, a.kernel), timing=True, tune=0,
+    progress("phase timing run")
+    rt = Runner(P, copies, dict(plan_opts(a.mode, a.kernel, a.index), timing=True, tune=0,
                                 pairs_per_lane=cfg["pairs_per_lane"], lds_slots=cfg["lds_slots"],
                                 persistent=cfg["persistent"], order=cfg["order"]))
     _, _, phase, _ = rt.run(max(8, min(a.steps, 20)), 2)
     rt.close()
-    single_kernel = (a.mode == "exact" and not cfg["persistent"] and not cfg["order"])
+    single_kernel = (a.mode == "exact" and not cfg["persistent"] and not cfg["order"] and not cfg["index"])
     main_ms = float(np.mean(step_ms)) if single_kernel else float(np.mean(phase[:, 1]))
-    main_src = ("HIP events around each graph launch in the timed region (the graph holds only the main kernel)"
+    main_src = ("HIP events around each plan launch in the timed region (the step is the main kernel alone)"
                 if single_kernel else "HIP events around the main kernel in eager timed executions")
     alg_bytes = w.nbytes_algorithmic()
     achieved = alg_bytes / (main_ms * 1e-3) / 1e9
@@ -245,6 +256,7 @@ def main():
     parity = "not checked"
     want = None
     if not a.no_parity:
+        progress("parity against the oracle")
         import oracle
         got = last.cpu().numpy()
         if T <= 5_000_000_000:
@@ -261,8 +273,11 @@ def main():
     compare = {}
     if a.compare_steps > 0:
         other = "filtered" if a.mode == "exact" else "exact"
-        for label, opts in (("mode_" + other, plan_opts(other, "auto")),
-                            ("per_pair_baseline", plan_opts("exact", "per_pair"))):
+        runs = [("mode_" + other, plan_opts(other, "auto")), ("per_pair_baseline", plan_opts("exact", "per_pair"))]
+        if a.index:
+            runs = [("unindexed", plan_opts("exact", "auto"))]
+        for label, opts in runs:
+            progress(f"comparison run: {label}")
             r = Runner(P, copies, dict(opts, timing=True))
             st = r.plans[0]
             ms, _, ph, _ = r.run(a.compare_steps, 2)
@@ -277,8 +292,13 @@ def main():
                 entry["parity"] = "bit-exact" if np.array_equal(got, want) else "MISMATCH"
             r.close()
             compare[label] = entry
-        compare["main_kernel_speedup_vs_per_pair"] = compare["per_pair_baseline"]["main_kernel_ms"] / main_ms
+        if "per_pair_baseline" in compare:
+            compare["main_kernel_speedup_vs_per_pair"] = compare["per_pair_baseline"]["main_kernel_ms"] / main_ms
+        if "unindexed" in compare:
+            compare["speedup_vs_unindexed"] = compare["unindexed"]["main_kernel_ms"] / main_ms
 
+    if not a.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
 
     digest = kernel_digest()

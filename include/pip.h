@@ -137,6 +137,11 @@ typedef struct {
     int32_t timing;         /* plans: 1 = record device-time events between the
                                phases of every execution (executions then run
                                eagerly, not as a graph) */
+    int32_t index;          /* plans, exact mode, one polygon (point_poly NULL):
+                               1 = build a y-range tree over the ring's edges and
+                               visit the points in y order, so whole groups of
+                               edges are skipped by comparisons (same bits; work
+                               no longer proportional to every edge) */
 } pip_options;
 
 /* Configuration a plan runs with (after automatic choices and tuning). */
@@ -153,6 +158,7 @@ typedef struct {
     int32_t n_items;        /* work items (256 * pairs_per_lane pairs each) */
     int32_t tuned;          /* 0 = defaults/options, 1 = autotuned now, 2 = from the cache */
     float tune_ms;          /* tuned step time (ms), when tuned */
+    int32_t index;          /* 1 if the plan runs the y-indexed path */
 } pip_plan_config;
 
 /* Figures of a plan's last execution (see pip_plan_stats). */

@@ -47,7 +47,7 @@ def _stream_handle(stream):
 
 def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block=0, lds_slots=0,
             persistent=-1, order=-1, use_graph=True, tune=0, force_recheck=False, bound_scale=1.0,
-            tune_cache=None, timing=False) -> _lib.pip_options:
+            tune_cache=None, timing=False, index=False) -> _lib.pip_options:
     o = _lib.pip_options()
     _lib.load().pip_options_init(ctypes.byref(o))
     o.mode = _lib.MODES[mode] if isinstance(mode, str) else int(mode)
@@ -64,6 +64,7 @@ def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block
     o.bound_scale = float(bound_scale)
     o.tune_cache = tune_cache.encode() if tune_cache else None
     o.timing = 1 if timing else 0
+    o.index = 1 if index else 0
     return o
 
 

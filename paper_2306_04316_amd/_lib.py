@@ -26,14 +26,16 @@ class pip_options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("pairs_per_lane", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("lds_slots", ctypes.c_int32), ("persistent", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("tune", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
-                ("bound_scale", ctypes.c_float), ("tune_cache", ctypes.c_char_p), ("timing", ctypes.c_int32)]
+                ("bound_scale", ctypes.c_float), ("tune_cache", ctypes.c_char_p), ("timing", ctypes.c_int32),
+                ("index", ctypes.c_int32)]
 
 
 class pip_plan_config(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("mode", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("pairs_per_lane", ctypes.c_int32), ("lds_slots", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("n_items", ctypes.c_int32), ("tuned", ctypes.c_int32), ("tune_ms", ctypes.c_float)]
+                ("n_items", ctypes.c_int32), ("tuned", ctypes.c_int32), ("tune_ms", ctypes.c_float),
+                ("index", ctypes.c_int32)]
 
 
 class pip_stats(ctypes.Structure):

@@ -144,6 +144,7 @@ void pip_options_init(pip_options *opts)
     opts->bound_scale = 1.0f;
     opts->tune_cache = NULL;
     opts->timing = 0;
+    opts->index = 0;
 }
 
 int pip_abi_version(void) { return PIP_ABI_VERSION; }

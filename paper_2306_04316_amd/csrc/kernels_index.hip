@@ -1,0 +1,266 @@
+// y-index for one large polygon tested by many points (beyond the paper's
+// O(n)-per-point sweep; the results are the rule's bits, unchanged).
+//
+// The ring's edges are grouped into a three-level tree of y ranges: a level-0
+// node covers 32 consecutive edges, a level-1 node 32 level-0 nodes, a
+// level-2 node 32 level-1 nodes.  A node's range [lo, hi] spans every endpoint
+// of its edges, so a point with p_y < lo (every endpoint above the ray) or
+// p_y >= hi (every endpoint at or below it) has no straddling edge in the node
+// -- a decision taken by comparisons only, hence exact -- and the above bit of
+// the node's last vertex is simply (p_y < lo).  The points are reordered by a
+// counting sort on a y bucket, so that the 64 points of a wavefront share a
+// narrow y band and whole subtrees are skipped by every lane together; a node
+// that some lane's band meets is descended, down to level-0 chunks walked
+// exactly as in the unindexed kernel.
+
+#include "pip_common.h"
+#include "ring_walk.h"
+
+namespace pip {
+namespace {
+
+constexpr int kYBuckets = 65536;
+
+// Level-0 bounds: node c covers edges 32c .. 32c+31, endpoints v_{32c-1} .. v_{32c+31}.
+__global__ __launch_bounds__(256) void k_bounds_l0(const double *__restrict__ ry, int k, double2 *__restrict__ b0,
+                                                   int n0)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n0)
+        return;
+    double lo = INFINITY, hi = -INFINITY;
+    const int j0 = 32 * c - 1;
+    const int j1 = 32 * c + 31 < k - 1 ? 32 * c + 31 : k - 1;
+    for (int j = j0; j <= j1; ++j) {
+        const double v = ry[j < 0 ? k - 1 : j];
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+    }
+    b0[c] = make_double2(lo, hi);
+}
+
+// Next level: node c covers input nodes 32c .. 32c+31.
+__global__ __launch_bounds__(256) void k_bounds_up(const double2 *__restrict__ in, int n_in,
+                                                   double2 *__restrict__ out, int n_out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_out)
+        return;
+    double lo = INFINITY, hi = -INFINITY;
+    const int i1 = 32 * c + 32 < n_in ? 32 * c + 32 : n_in;
+    for (int i = 32 * c; i < i1; ++i) {
+        lo = fmin(lo, in[i].x);
+        hi = fmax(hi, in[i].y);
+    }
+    out[c] = make_double2(lo, hi);
+}
+
+// Whole-ring range: one workgroup reduces the top level.
+__global__ __launch_bounds__(256) void k_bounds_root(const double2 *__restrict__ in, int n_in,
+                                                     double2 *__restrict__ root)
+{
+    __shared__ double slo[256], shi[256];
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = threadIdx.x; i < n_in; i += 256) {
+        lo = fmin(lo, in[i].x);
+        hi = fmax(hi, in[i].y);
+    }
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + o]);
+            shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *root = make_double2(slo[0], shi[0]);
+}
+
+__device__ __forceinline__ int ybucket(double y, double lo, double scale)
+{
+    const double f = (y - lo) * scale;
+    return !(f >= 0.0) ? 0 : (f >= (double)(kYBuckets - 1) ? kYBuckets - 1 : (int)f);
+}
+
+__global__ __launch_bounds__(256) void k_yhist(const double *__restrict__ py, int64_t n,
+                                               const double2 *__restrict__ root, unsigned *__restrict__ hist)
+{
+    const double lo = root->x, hi = root->y;
+    const double scale = hi > lo ? (double)kYBuckets / (hi - lo) : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&hist[ybucket(py[i], lo, scale)], 1u);
+}
+
+// Exclusive scan of the bucket counts (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_yscan(const unsigned *__restrict__ hist, unsigned *__restrict__ base)
+{
+    __shared__ unsigned part[1024];
+    constexpr int per = kYBuckets / 1024;
+    const int t = threadIdx.x;
+    unsigned s = 0;
+    for (int i = 0; i < per; ++i)
+        s += hist[t * per + i];
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const unsigned v = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned run = part[t] - s;
+    for (int i = 0; i < per; ++i) {
+        base[t * per + i] = run;
+        run += hist[t * per + i];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_yscatter(const double *__restrict__ px, const double *__restrict__ py,
+                                                  int64_t n, const double2 *__restrict__ root,
+                                                  const unsigned *__restrict__ base, unsigned *__restrict__ cursor,
+                                                  double2 *__restrict__ spt, int32_t *__restrict__ sidx)
+{
+    const double lo = root->x, hi = root->y;
+    const double scale = hi > lo ? (double)kYBuckets / (hi - lo) : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double y = py[i];
+        const int b = ybucket(y, lo, scale);
+        const unsigned pos = base[b] + atomicAdd(&cursor[b], 1u);
+        spt[pos] = make_double2(px[i], y);
+        sidx[pos] = (int32_t)i;
+    }
+}
+
+struct Tree {
+    const double2 *b0, *b1, *b2;
+    int n0, n1, n2;
+};
+
+// Lanes whose point lies in [lo, hi) may have straddling edges in the node.
+__device__ __forceinline__ bool node_hit(double y, double2 bnd, uint32_t &prev)
+{
+    const bool below = y < bnd.x;
+    const bool in = !below && y < bnd.y;
+    const bool any = __builtin_amdgcn_ballot_w64(in) != 0;
+    if (!any)
+        prev = below ? 1u : 0u;
+    return any;
+}
+
+// Rows of 64 y-ordered points against the one ring, walked through the tree.
+__global__ __launch_bounds__(256) void k_runs_indexed_fp64(const double2 *__restrict__ spt,
+                                                           const int32_t *__restrict__ sidx, int64_t n,
+                                                           const double *__restrict__ rx,
+                                                           const double *__restrict__ ry, int k, Tree tr,
+                                                           uint8_t *__restrict__ inside)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool member = i < n;
+    double2 p = make_double2(0.0, 0.0);
+    int32_t idx = 0;
+    if (member) {
+        p = spt[i];
+        idx = sidx[i];
+    }
+    uint64_t par = 0;
+    if (k > 0) {
+        const double yq = p.y + 0.0;
+        uint32_t prev = shift_in_above(0u, yq, ry[k - 1]);
+        for (int g2 = 0; g2 < tr.n2; ++g2) {
+            if (!node_hit(p.y, tr.b2[g2], prev))
+                continue;
+            const int g1e = 32 * g2 + 32 < tr.n1 ? 32 * g2 + 32 : tr.n1;
+            for (int g1 = 32 * g2; g1 < g1e; ++g1) {
+                if (!node_hit(p.y, tr.b1[g1], prev))
+                    continue;
+                const int ce = 32 * g1 + 32 < tr.n0 ? 32 * g1 + 32 : tr.n0;
+                for (int c = 32 * g1; c < ce; ++c) {
+                    if (!node_hit(p.y, tr.b0[c], prev))
+                        continue;
+                    par ^= chunk_parity_uniform(p.x, p.y, yq, member, rx, ry, k, 32 * c, prev);
+                }
+            }
+        }
+    }
+    if (member)
+        inside[idx] = (uint8_t)((par >> lane) & 1u);
+}
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+IndexLayout index_layout(int64_t n_points, int64_t k)
+{
+    IndexLayout L;
+    L.n0 = (int)((k + 31) / 32);
+    L.n1 = (L.n0 + 31) / 32;
+    L.n2 = (L.n1 + 31) / 32;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        const size_t at = o;
+        o = (o + b + 255) & ~(size_t)255;
+        return at;
+    };
+    L.o_b0 = take((size_t)(L.n0 > 0 ? L.n0 : 1) * 16);
+    L.o_b1 = take((size_t)(L.n1 > 0 ? L.n1 : 1) * 16);
+    L.o_b2 = take((size_t)(L.n2 > 0 ? L.n2 : 1) * 16);
+    L.o_root = take(16);
+    L.o_hist = take((size_t)kYBuckets * 4);
+    L.o_cursor = take((size_t)kYBuckets * 4);
+    L.o_base = take((size_t)kYBuckets * 4);
+    L.o_spt = take((size_t)(n_points > 0 ? n_points : 1) * 16);
+    L.o_sidx = take((size_t)(n_points > 0 ? n_points : 1) * 4);
+    L.bytes = o;
+    return L;
+}
+
+int launch_index_prep(const Problem &p, hipStream_t s, const IndexLayout &L, unsigned char *ws)
+{
+    // one polygon: its ring is the whole vertex array (offsets = {0, n_vertices})
+    const int k = (int)p.n_vertices;
+    double2 *b0 = (double2 *)(ws + L.o_b0), *b1 = (double2 *)(ws + L.o_b1), *b2 = (double2 *)(ws + L.o_b2);
+    double2 *root = (double2 *)(ws + L.o_root);
+    unsigned *hist = (unsigned *)(ws + L.o_hist), *cursor = (unsigned *)(ws + L.o_cursor);
+    unsigned *base = (unsigned *)(ws + L.o_base);
+    if (k <= 0 || p.n_points <= 0)
+        return PIP_OK;
+    hipLaunchKernelGGL(k_bounds_l0, dim3(grid_for(L.n0, 256)), dim3(256), 0, s, p.vy, k, b0, L.n0);
+    hipLaunchKernelGGL(k_bounds_up, dim3(grid_for(L.n1, 256)), dim3(256), 0, s, b0, L.n0, b1, L.n1);
+    hipLaunchKernelGGL(k_bounds_up, dim3(grid_for(L.n2, 256)), dim3(256), 0, s, b1, L.n1, b2, L.n2);
+    hipLaunchKernelGGL(k_bounds_root, dim3(1), dim3(256), 0, s, b2, L.n2, root);
+    PIP_TRY(launch_fill(hist, kYBuckets, 0u, s));
+    PIP_TRY(launch_fill(cursor, kYBuckets, 0u, s));
+    unsigned g = grid_for(p.n_points, 256);
+    g = g > 8192 ? 8192 : g;
+    hipLaunchKernelGGL(k_yhist, dim3(g), dim3(256), 0, s, p.py, p.n_points, root, hist);
+    hipLaunchKernelGGL(k_yscan, dim3(1), dim3(1024), 0, s, hist, base);
+    hipLaunchKernelGGL(k_yscatter, dim3(g), dim3(256), 0, s, p.px, p.py, p.n_points, root, base, cursor,
+                       (double2 *)(ws + L.o_spt), (int32_t *)(ws + L.o_sidx));
+    PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
+
+int launch_runs_indexed(const Problem &p, hipStream_t s, const IndexLayout &L, unsigned char *ws)
+{
+    if (p.n_points <= 0)
+        return PIP_OK;
+    Tree tr;
+    tr.b0 = (const double2 *)(ws + L.o_b0);
+    tr.b1 = (const double2 *)(ws + L.o_b1);
+    tr.b2 = (const double2 *)(ws + L.o_b2);
+    tr.n0 = L.n0;
+    tr.n1 = L.n1;
+    tr.n2 = L.n2;
+    hipLaunchKernelGGL(k_runs_indexed_fp64, dim3(grid_for(p.n_points, 256)), dim3(256), 0, s,
+                       (const double2 *)(ws + L.o_spt), (const int32_t *)(ws + L.o_sidx), p.n_points, p.vx, p.vy,
+                       (int)p.n_vertices, tr, p.inside);
+    PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
+
+}  // namespace pip

@@ -79,6 +79,16 @@ int launch_filtered(const Problem &p, hipStream_t stream, int pairs_per_lane, in
                     int n_items, unsigned *queue, int grid);
 int launch_recheck(const Problem &p, hipStream_t stream, const int32_t *list, const unsigned *count, int grid);
 
+// ---------------------------------------------------------------- y-index for one large ring
+struct IndexLayout {
+    int n0 = 0, n1 = 0, n2 = 0;   // tree nodes per level
+    size_t o_b0 = 0, o_b1 = 0, o_b2 = 0, o_root = 0, o_hist = 0, o_cursor = 0, o_base = 0, o_spt = 0, o_sidx = 0;
+    size_t bytes = 0;             // workspace bytes
+};
+IndexLayout index_layout(int64_t n_points, int64_t k);
+int launch_index_prep(const Problem &p, hipStream_t s, const IndexLayout &L, unsigned char *ws);
+int launch_runs_indexed(const Problem &p, hipStream_t s, const IndexLayout &L, unsigned char *ws);
+
 // ---------------------------------------------------------------- preparation
 int launch_fill(unsigned *p, int n, unsigned v, hipStream_t stream);
 int launch_item_order(const Problem &p, hipStream_t stream, int item_pairs, int n_items, uint8_t *bucket,

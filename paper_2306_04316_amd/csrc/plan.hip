@@ -28,6 +28,8 @@ struct pip_plan {
     uint8_t *bucket = nullptr;
     int32_t *order = nullptr;
     int32_t *recheck = nullptr;
+    unsigned char *index_ws = nullptr;
+    pip::IndexLayout index;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -82,6 +84,8 @@ bool phase_empty(const pip_plan *pl, const pip_plan_config &c, int ph)
 {
     if (pl->p.n_points == 0)
         return true;
+    if (c.index)
+        return ph == kRecheck;
     if (ph == kPrep)   // counters (queue, recheck count) or the item order are needed
         return !(staged_kind(c) && (c.persistent || c.mode == PIP_MODE_FILTERED_FP32 ||
                                     (c.order == 1 && pl->p.point_poly)));
@@ -95,6 +99,9 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
     const Problem &p = pl->p;
     if (phase_empty(pl, c, ph))
         return PIP_OK;
+    if (c.index)
+        return ph == kPrep ? launch_index_prep(p, s, pl->index, pl->index_ws)
+                           : launch_runs_indexed(p, s, pl->index, pl->index_ws);
     const bool lpt = staged_kind(c) && c.order == 1 && p.point_poly;
     if (ph == kPrep) {
         PIP_TRY(launch_fill(pl->counters + kQueue, kCounters - kQueue, 0u, s));
@@ -247,18 +254,23 @@ void cache_store(const pip_plan *pl, const pip_plan_config &c)
 }
 
 // Time one candidate: median device time (ms) of the whole step sequence over
-// `reps` eager executions on stream s (after two untimed ones).
-int time_candidate(pip_plan *pl, pip_plan_config &c, hipStream_t s, int reps, float *ms_out)
+// up to `reps` eager executions on stream s (after one untimed execution).
+// A candidate whose first timed execution exceeds `cutoff` ms is abandoned
+// after it (its time is that execution's), and long steps get fewer reps.
+int time_candidate(pip_plan *pl, pip_plan_config &c, hipStream_t s, int reps, float cutoff, float *ms_out)
 {
     PIP_TRY(resolve_grid(pl, c));
     std::vector<float> t;
-    for (int r = 0; r < reps + 2; ++r) {
+    PIP_TRY(enqueue(pl, c, s, true));
+    PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
+    for (int r = 0; r < reps; ++r) {
         PIP_TRY(enqueue(pl, c, s, true));
         PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
         float a = 0.f;
         PIP_HIP_TRY(hipEventElapsedTime(&a, pl->ev[0], pl->ev[3]));
-        if (r >= 2)
-            t.push_back(a);
+        t.push_back(a);
+        if (r == 0 && (a > cutoff || a > 50.0f))
+            break;   // clearly worse than the best so far, or a long step: one timing is enough
     }
     std::sort(t.begin(), t.end());
     *ms_out = t[t.size() / 2];
@@ -329,13 +341,18 @@ int autotune(pip_plan *pl, hipStream_t s)
                         cands.push_back(c);
                     }
             }
+    // total budget: about 2 s of device time, or every candidate once for long steps
+    float spent = 0.f;
     for (auto &c : cands) {
         float ms = 0.f;
-        PIP_TRY(time_candidate(pl, c, s, reps, &ms));
+        PIP_TRY(time_candidate(pl, c, s, reps, 1.5f * best_ms, &ms));
+        spent += ms * (ms > 50.0f ? 2.f : (float)reps + 1.f);
         if (ms < best_ms) {
             best_ms = ms;
             best = c;
         }
+        if (spent > 2000.f && best_ms < 1e29f && best_ms > 20.0f)
+            break;
     }
     best.tuned = 1;
     best.tune_ms = best_ms;
@@ -379,6 +396,8 @@ int check_options(const pip_options *opts, pip_options &o)
         return fail(PIP_EINVAL, "the filtered mode runs on the staged kernel only");
     if (!(o.bound_scale >= 0.0f))
         return fail(PIP_EINVAL, "bound_scale must be >= 0");
+    if (o.index && o.mode != PIP_MODE_EXACT_FP64)
+        return fail(PIP_EINVAL, "the y-index runs in the exact mode only");
     return PIP_OK;
 }
 
@@ -449,6 +468,18 @@ int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t 
     const size_t o_bkt = take((size_t)max_items);
     const size_t o_ord = take((size_t)max_items * sizeof(int32_t));
     const size_t o_rck = take(o.mode == PIP_MODE_FILTERED_FP32 ? (size_t)std::max<int64_t>(n_points, 1) * 4 : 0);
+    if (o.index) {
+        if (point_poly) {
+            delete pl;
+            return fail(PIP_EINVAL, "the y-index needs one polygon (point_poly NULL)");
+        }
+        pl->index = index_layout(n_points, n_vertices);
+        c.index = 1;
+        c.kernel = PIP_KERNEL_RUNS;
+        c.persistent = 0;
+        c.order = 0;
+    }
+    const size_t o_idx = take(o.index ? pl->index.bytes : 0);
     pl->ws_bytes = off;
     hipError_t e = hipMalloc(&pl->ws, pl->ws_bytes);
     if (e != hipSuccess) {
@@ -461,6 +492,7 @@ int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t 
     pl->bucket = w + o_bkt;
     pl->order = (int32_t *)(w + o_ord);
     pl->recheck = o.mode == PIP_MODE_FILTERED_FP32 ? (int32_t *)(w + o_rck) : nullptr;
+    pl->index_ws = o.index ? w + o_idx : nullptr;
     for (int k = 0; k < 4 && rc == PIP_OK; ++k) {
         e = hipEventCreate(&pl->ev[k]);
         if (e != hipSuccess)
@@ -468,7 +500,7 @@ int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t 
     }
     if (rc == PIP_OK)
         rc = launch_fill(pl->counters, kCounters, 0u, s);
-    if (rc == PIP_OK && staged_kind(c) && n_points > 0) {
+    if (rc == PIP_OK && staged_kind(c) && n_points > 0 && !c.index) {
         pip_plan_config cached = c;
         if (cache_lookup(pl, cached)) {
             c = cached;

@@ -114,10 +114,61 @@ __device__ __forceinline__ uint64_t ring_parity_uniform(double x, double y, cons
     return par;
 }
 
-// The same parity with compacted side tests: the ring's y values stream
-// through scalar loads into each lane's 32-bit "above" words (two vector
-// instructions per vertex), then each lane evaluates the side value only for
-// its own straddling edges, fetching those two vertices itself.
+// One 32-edge chunk of a wave-uniform ring with compacted side tests: edges
+// c0 .. c0+m-1 (m <= 32), i.e. vertices v_{c0-1} -> v_{c0} onwards.  The ring's
+// y values stream through scalar loads into each lane's 32-bit "above" word
+// (two vector instructions per vertex); each member lane then evaluates the
+// side value only for its own straddling edges, fetching those two vertices
+// itself.  `prev` holds the above bit of v_{c0-1} on entry and of the chunk's
+// last vertex on exit.  Returns the lanes with an odd number of crossings in
+// the chunk.
+__device__ __forceinline__ uint64_t chunk_parity_uniform(double x, double y, double yq, bool member,
+                                                         const double *__restrict__ rx,
+                                                         const double *__restrict__ ry, int k, int c0,
+                                                         uint32_t &prev)
+{
+    const int m = k - c0 < 32 ? k - c0 : 32;
+    uint32_t above = 0;
+    if (m == 32) {
+#pragma unroll
+        for (int t = 0; t < 32; ++t)
+            above = shift_in_above(above, yq, ry[c0 + t]);
+    } else {
+        // partial chunk: batches of 8 (clamped to the ring's last vertex, whose
+        // extra bits are masked below), then left-align
+        int t = 0;
+        for (; t < m; t += 8) {
+#pragma unroll
+            for (int tt = 0; tt < 8; ++tt)
+                above = shift_in_above(above, yq, ry[c0 + (t + tt < m ? t + tt : m - 1)]);
+        }
+        above <<= (32 - t);
+    }
+    uint32_t strad = above ^ ((above >> 1) | (prev << 31));
+    if (m < 32)
+        strad &= ~(0xffffffffu >> m);
+    prev = (above >> (32 - m)) & 1u;
+    strad = member ? strad : 0u;
+    uint64_t par = 0;
+    while (strad != 0) {
+        const int j = __builtin_clz(strad);
+        strad ^= 0x80000000u >> j;
+        const int jb = c0 + j;
+        const int ja = jb == 0 ? k - 1 : jb - 1;
+        const double ax = rx[ja], ay = ry[ja], bx = rx[jb], by = ry[jb];
+        const bool b_above = (above >> (31 - j)) & 1u;
+        const double nx = by - ay;
+        const double ny = ax - bx;
+        const double t1 = x - ax;
+        const double t2 = y - ay;
+        const double s = t1 * nx + t2 * ny;
+        par ^= __builtin_amdgcn_ballot_w64(b_above ? (s <= 0.0) : (s >= 0.0));
+    }
+    return par;
+}
+
+// Crossing parity of every lane's point against the wave-uniform ring [b, e),
+// chunk by chunk.  Must be called with the whole wavefront active.
 __device__ __forceinline__ uint64_t ring_parity_compact_uniform(double x, double y, bool member,
                                                                 const double *__restrict__ vx,
                                                                 const double *__restrict__ vy, int64_t b,
@@ -131,47 +182,10 @@ __device__ __forceinline__ uint64_t ring_parity_compact_uniform(double x, double
         return 0;
     const double yq = y + 0.0;
     uint32_t prev = shift_in_above(0u, yq, ry[k - 1]);
-    for (int c0 = 0; c0 < k; c0 += 32) {
-        const int m = k - c0 < 32 ? k - c0 : 32;
-        uint32_t above = 0;
-        if (m == 32) {
-#pragma unroll
-            for (int t = 0; t < 32; ++t)
-                above = shift_in_above(above, yq, ry[c0 + t]);
-        } else {
-            // partial chunk: batches of 8 (clamped to the ring's last vertex,
-            // whose extra bits are masked below), then left-align
-            int t = 0;
-            for (; t < m; t += 8) {
-#pragma unroll
-                for (int tt = 0; tt < 8; ++tt)
-                    above = shift_in_above(above, yq, ry[c0 + (t + tt < m ? t + tt : m - 1)]);
-            }
-            above <<= (32 - t);
-        }
-        uint32_t strad = above ^ ((above >> 1) | (prev << 31));
-        if (m < 32)
-            strad &= ~(0xffffffffu >> m);
-        prev = (above >> (32 - m)) & 1u;
-        strad = member ? strad : 0u;
-        while (strad != 0) {
-            const int j = __builtin_clz(strad);
-            strad ^= 0x80000000u >> j;
-            const int jb = c0 + j;
-            const int ja = jb == 0 ? k - 1 : jb - 1;
-            const double ax = rx[ja], ay = ry[ja], bx = rx[jb], by = ry[jb];
-            const bool b_above = (above >> (31 - j)) & 1u;
-            const double nx = by - ay;
-            const double ny = ax - bx;
-            const double t1 = x - ax;
-            const double t2 = y - ay;
-            const double s = t1 * nx + t2 * ny;
-            par ^= __builtin_amdgcn_ballot_w64(b_above ? (s <= 0.0) : (s >= 0.0));
-        }
-    }
+    for (int c0 = 0; c0 < k; c0 += 32)
+        par ^= chunk_parity_uniform(x, y, yq, member, rx, ry, k, c0, prev);
     return par;
 }
-
 
 // Rows u of a workgroup item whose rings were not staged: lanes that share a
 // polygon run together (leader = first unfinished lane), each group walking

@@ -213,3 +213,42 @@ def test_plan_full_stress(P, mode):
 @pytest.mark.parametrize("mode", ["exact", "filtered"])
 def test_plan_full_footprints(P, mode):
     check_plan(P, W.footprints(), "footprints full", mode=mode)
+
+
+# ---------------------------------------------------------------- y-indexed single polygon
+@pytest.mark.parametrize("name", ["star", "fractal"])
+def test_plan_index_small(P, name):
+    st, cfg = check_plan(P, SMALL[name](), name, index=True)
+    assert cfg["index"] == 1
+
+
+def test_plan_index_fractal_full_sampled(P):
+    import torch
+    w = W.fractal()
+    note("index fractal full")
+    got, st, cfg = plan_run(P, w, index=True)
+    idx = np.sort(np.random.default_rng(12).choice(w.n_points, 2000, replace=False))
+    s = W.subsample(w, idx)
+    assert_same_mask(got[idx], oracle.classify_workload(s), "index fractal full (sampled)", s.px, s.py)
+
+
+def test_plan_index_degenerate(P):
+    rng = np.random.default_rng(4)
+    px = rng.uniform(-2, 2, 5000)
+    py = rng.uniform(-2, 2, 5000)
+    py[:50] = 0.0
+    py[50:100] = 1.0
+    for ring in ([(0.0, 0.0)], [(0.0, 0.0), (1.0, 1.0)], [(0, 0), (1, 0), (1, 1), (0, 1), (0, 0)],
+                 [(float(np.cos(t)), float(np.sin(t))) for t in np.linspace(0, 6.2, 3000)]):
+        vx = np.array([a for a, _ in ring], dtype=np.float64)
+        vy = np.array([b for _, b in ring], dtype=np.float64)
+        w = W.Workload("ring", px, py, np.array([0, vx.size], dtype=np.int64), vx, vy, None, {})
+        check_plan(P, w, f"index ring k={vx.size}", index=True)
+
+
+def test_plan_index_rejects_pair_index(P):
+    w = W.footprints(scale=0.001)
+    d = to_dev(w)
+    with pytest.raises(P.PipError) as e:
+        P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], index=True)
+    assert e.value.code == -1
