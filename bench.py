@@ -35,6 +35,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# Tuned plan configurations shipped with the package (written by the plan autotuner on MI355X);
+# a plan whose workload class is listed there is created without re-tuning.
+TUNE_CACHE = os.path.join(ROOT, "paper_2306_04316_amd", "tune_cache.txt")
 METRIC = "point-edge tests/s and points/s at bit-exact match; % of HBM/VALU roofline"
 
 WORKLOAD_TEXT = {
@@ -79,6 +82,8 @@ def parse():
     ap.add_argument("--index", action="store_true",
                     help="one polygon: y-indexed path (edges skipped by y-range tree, points in y order)")
     ap.add_argument("--no-tune", action="store_true", help="skip autotuning at plan creation")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="tuning cache (a listed workload class is not re-tuned; new results are appended)")
     ap.add_argument("--copies", type=int, default=4, help="device copies the steps rotate over")
     ap.add_argument("--compare-steps", type=int, default=10,
                     help="steps for the other-mode and per-pair comparison runs (0 = skip them)")
@@ -225,7 +230,8 @@ def main():
     def plan_opts(mode, kernel, index=False):
         return dict(mode=mode, kernel=kernel, pairs_per_lane=a.pairs_per_lane, lds_slots=a.lds_slots,
                     persistent=a.persistent, order=a.order, use_graph=not a.no_graph, index=index,
-                    tune=0 if (a.no_tune or index or kernel in ("per_pair", "segmented")) else 1)
+                    tune=0 if (a.no_tune or index or kernel in ("per_pair", "segmented")) else 1,
+                    tune_cache=a.tune_cache)
 
 
     T, N = w.n_tests, w.n_points
