@@ -53,7 +53,10 @@ WORKLOAD_TEXT = {
 # of this benchmark (bytes, after scaling by the counters' reading of a copy kernel of known size).
 # Keyed by (config, mode, kernel-source digest): an entry stops applying as soon as the kernel
 # sources change, and the benchmark then reports traffic as null.
-PROFILED_TRAFFIC: dict = {}
+PROFILED_TRAFFIC: dict = {
+    # footprints, exact mode, k_staged_batched_fp64<4> (profiles/staged_footprints_exact.md)
+    (2, "exact", "c65625e52aa4"): {"fetch_bytes": 219914998, "write_bytes": 10000064},
+}
 
 
 def kernel_digest() -> str:
@@ -308,7 +311,8 @@ def main():
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
 
     digest = kernel_digest()
-    traffic = PROFILED_TRAFFIC.get((a.config, a.mode, digest))
+    tr = PROFILED_TRAFFIC.get((a.config, a.mode, digest))
+    traffic = None if tr is None else tr["fetch_bytes"] + tr["write_bytes"]
     rec = {
         "metric": METRIC,
         "value": T / (ms_per_step * 1e-3),
@@ -331,7 +335,7 @@ def main():
                             "recheck": float(np.mean(phase[:, 2]))},
         "step_ms_events": {"mean": float(np.mean(step_ms)), "min": float(np.min(step_ms))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes per launch",
                      "kernel": "main classification kernel", "kernel_ms": main_ms, "kernel_ms_source": main_src,
                      "alg_bytes_per_launch": alg_bytes, "kernel_digest": digest},
         "compare": compare,
