@@ -11,7 +11,8 @@
  * Every side value is evaluated in IEEE binary64 with the operation order
  * t1 = p_x - a_x, t2 = p_y - a_y, s = t1*n_x + t2*n_y, each operation rounded
  * separately (no fused multiply-add).  Results are therefore bit-identical to
- * a plain CPU binary64 evaluation of the same rule, in every mode.
+ * a plain CPU binary64 evaluation of the same rule, in every mode.  The
+ * paper's second test (constraint 2, see pip_predicate) is available too.
  *
  * Layout (all arrays are DEVICE pointers, caller-owned, and must stay valid
  * until the work enqueued on `stream` completes):
@@ -88,6 +89,19 @@ typedef enum {
     PIP_MODE_FILTERED_FP32 = 1
 } pip_mode;
 
+/* The test that decides whether a straddling edge is crossed (paper, Method
+ * section).  Both evaluate every operation in binary64 (division correctly
+ * rounded, no fused multiply-add) and use the half-open straddle rule. */
+typedef enum {
+    /* constraint 1 (Algorithm 1): (p - a) . n <= 0, n = (b_y - a_y, a_x - b_x)
+     * oriented so n_x > 0 -- the default */
+    PIP_PRED_SIDE = 0,
+    /* constraint 2 (Algorithm 2): lambda = (p_y - a_y) / (b_y - a_y),
+     * x = a_x + lambda * (b_x - a_x), crossed when x >= p_x (the Method
+     * section's comparison; its listing uses a strict one) */
+    PIP_PRED_INTERSECTION = 1
+} pip_predicate;
+
 /* Work mapping of the main kernel. */
 typedef enum {
     PIP_KERNEL_AUTO = 0,
@@ -137,6 +151,7 @@ typedef struct {
     int32_t timing;         /* plans: 1 = record device-time events between the
                                phases of every execution (executions then run
                                eagerly, not as a graph) */
+    int32_t predicate;      /* pip_predicate (the filtered mode supports PIP_PRED_SIDE only) */
     int32_t index;          /* plans, exact mode, one polygon (point_poly NULL):
                                1 = build a y-range tree over the ring's edges and
                                visit the points in y order, so whole groups of

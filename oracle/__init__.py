@@ -49,12 +49,13 @@ def load(mutant: int = 0) -> ctypes.CDLL:
         return _libs[mutant]
     path = build(mutant, force=False)
     lib = ctypes.CDLL(path)
-    f = lib.pip_oracle_classify
-    f.restype = ctypes.c_int
-    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
-                  ctypes.c_void_p, ctypes.c_int64,
-                  ctypes.c_void_p, ctypes.c_void_p,
-                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    for name in ("pip_oracle_classify", "pip_oracle_classify_c2"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                      ctypes.c_void_p, ctypes.c_int64,
+                      ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     _libs[mutant] = lib
     return lib
 
@@ -64,8 +65,10 @@ def _ptr(a):
 
 
 def classify(px, py, offsets, vx, vy, point_poly=None, nthreads: int | None = None,
-             mutant: int = 0) -> np.ndarray:
-    """inside[i] in {0,1} for point (px[i], py[i]) against polygon point_poly[i] (or 0)."""
+             mutant: int = 0, predicate: int = 1) -> np.ndarray:
+    """inside[i] in {0,1} for point (px[i], py[i]) against polygon point_poly[i] (or 0).
+
+    predicate 1: constraint 1 (normal-side test); 2: constraint 2 (parametric intersection)."""
     px = np.ascontiguousarray(px, dtype=np.float64)
     py = np.ascontiguousarray(py, dtype=np.float64)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -79,15 +82,17 @@ def classify(px, py, offsets, vx, vy, point_poly=None, nthreads: int | None = No
     out = np.empty(n, dtype=np.uint8)
     if nthreads is None:
         nthreads = os.cpu_count() or 1
-    rc = load(mutant).pip_oracle_classify(_ptr(px), _ptr(py), n, _ptr(offsets), offsets.shape[0] - 1,
-                                          _ptr(vx), _ptr(vy), _ptr(point_poly), _ptr(out), int(nthreads))
+    fn = load(mutant).pip_oracle_classify_c2 if predicate == 2 else load(mutant).pip_oracle_classify
+    rc = fn(_ptr(px), _ptr(py), n, _ptr(offsets), offsets.shape[0] - 1,
+            _ptr(vx), _ptr(vy), _ptr(point_poly), _ptr(out), int(nthreads))
     if rc != 0:
         raise ValueError(f"pip_oracle_classify rejected its arguments (rc={rc})")
     return out
 
 
-def classify_workload(w, nthreads: int | None = None, mutant: int = 0) -> np.ndarray:
-    return classify(w.px, w.py, w.offsets, w.vx, w.vy, w.point_poly, nthreads=nthreads, mutant=mutant)
+def classify_workload(w, nthreads: int | None = None, mutant: int = 0, predicate: int = 1) -> np.ndarray:
+    return classify(w.px, w.py, w.offsets, w.vx, w.vy, w.point_poly, nthreads=nthreads, mutant=mutant,
+                    predicate=predicate)
 
 
 def classify_one(x: float, y: float, ring_x, ring_y, mutant: int = 0) -> int:

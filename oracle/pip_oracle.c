@@ -101,6 +101,35 @@ static int ring_parity(double x, double y, const double *vx, const double *vy, i
     return (int)(count & 1);
 }
 
+/*
+ * Constraint 2 (paper, Method section, second way of testing the constraint,
+ * eqs. lamda_eq1, lambda, find_x, and Algorithm 2): for a straddling edge
+ * (same half-open rule as above) with direction d = b - a, the ray meets the
+ * edge's line at lambda = (p_y - a_y) / d_y, x = a_x + lambda * d_x; the edge
+ * counts when x >= p_x ("x >= p_x" as the Method section states; Algorithm 2's
+ * listing uses a strict comparison -- reading taken: the text's, so that a
+ * point on an edge counts that edge as in constraint 1).  Each operation is
+ * rounded in binary64, the division correctly rounded, no fused multiply-add.
+ */
+static int ring_parity_c2(double x, double y, const double *vx, const double *vy, int64_t k)
+{
+    int64_t count = 0;
+    for (int64_t i = 0; i < k; ++i) {
+        int64_t j = (i + 1 == k) ? 0 : i + 1;
+        double ax = vx[i], ay = vy[i];
+        double bx = vx[j], by = vy[j];
+        if ((ay > y) == (by > y))
+            continue;
+        double dx = bx - ax;
+        double dy = by - ay;
+        double lam = (y - ay) / dy;
+        double xn = ax + lam * dx;
+        if (xn >= x)
+            ++count;
+    }
+    return (int)(count & 1);
+}
+
 typedef struct {
     const double *px, *py;
     const int64_t *offsets;
@@ -108,6 +137,7 @@ typedef struct {
     const int32_t *point_poly;
     uint8_t *inside;
     int64_t begin, end;
+    int predicate;
 } oracle_job;
 
 static void *oracle_worker(void *arg)
@@ -116,23 +146,17 @@ static void *oracle_worker(void *arg)
     for (int64_t i = j->begin; i < j->end; ++i) {
         int64_t q = j->point_poly ? (int64_t)j->point_poly[i] : 0;
         int64_t b = j->offsets[q], e = j->offsets[q + 1];
-        j->inside[i] = (uint8_t)ring_parity(j->px[i], j->py[i], j->vx + b, j->vy + b, e - b);
+        j->inside[i] = (uint8_t)(j->predicate == 2
+                                     ? ring_parity_c2(j->px[i], j->py[i], j->vx + b, j->vy + b, e - b)
+                                     : ring_parity(j->px[i], j->py[i], j->vx + b, j->vy + b, e - b));
     }
     return NULL;
 }
 
-/*
- * Classify n_points points.  Point i is tested against polygon point_poly[i]
- * (or polygon 0 when point_poly is NULL).  Polygon q's ring is
- * vx/vy[offsets[q] .. offsets[q+1]).  All pointers are host pointers.
- * Writes inside[i] = 1 (inside) or 0 (outside).  Uses up to nthreads POSIX
- * threads over contiguous ranges of points (results do not depend on it).
- * Returns 0 on success, -1 on bad arguments.
- */
-int pip_oracle_classify(const double *px, const double *py, int64_t n_points,
-                        const int64_t *offsets, int64_t n_polys,
-                        const double *vx, const double *vy,
-                        const int32_t *point_poly, uint8_t *inside, int nthreads)
+static int classify_impl(const double *px, const double *py, int64_t n_points,
+                         const int64_t *offsets, int64_t n_polys,
+                         const double *vx, const double *vy,
+                         const int32_t *point_poly, uint8_t *inside, int nthreads, int predicate)
 {
     if (n_points < 0 || n_polys < 1 || !offsets || !inside)
         return -1;
@@ -164,6 +188,7 @@ int pip_oracle_classify(const double *px, const double *py, int64_t n_points,
         jobs[t].inside = inside;
         jobs[t].begin = n_points * t / nthreads;
         jobs[t].end = n_points * (t + 1) / nthreads;
+        jobs[t].predicate = predicate;
     }
     int started = 0;
     for (int t = 1; t < nthreads; ++t) {
@@ -177,4 +202,30 @@ int pip_oracle_classify(const double *px, const double *py, int64_t n_points,
     for (int t = started + 1; t < nthreads; ++t)   /* threads that failed to start */
         oracle_worker(&jobs[t]);
     return 0;
+}
+
+/*
+ * Classify n_points points with constraint 1 (the normal-side test; see the
+ * top of this file).  Point i is tested against polygon point_poly[i] (or
+ * polygon 0 when point_poly is NULL).  Polygon q's ring is
+ * vx/vy[offsets[q] .. offsets[q+1]).  All pointers are host pointers.
+ * Writes inside[i] = 1 (inside) or 0 (outside).  Uses up to nthreads POSIX
+ * threads over contiguous ranges of points (results do not depend on it).
+ * Returns 0 on success, -1 on bad arguments.
+ */
+int pip_oracle_classify(const double *px, const double *py, int64_t n_points,
+                        const int64_t *offsets, int64_t n_polys,
+                        const double *vx, const double *vy,
+                        const int32_t *point_poly, uint8_t *inside, int nthreads)
+{
+    return classify_impl(px, py, n_points, offsets, n_polys, vx, vy, point_poly, inside, nthreads, 1);
+}
+
+/* The same with constraint 2 (parametric intersection; see ring_parity_c2). */
+int pip_oracle_classify_c2(const double *px, const double *py, int64_t n_points,
+                           const int64_t *offsets, int64_t n_polys,
+                           const double *vx, const double *vy,
+                           const int32_t *point_poly, uint8_t *inside, int nthreads)
+{
+    return classify_impl(px, py, n_points, offsets, n_polys, vx, vy, point_poly, inside, nthreads, 2);
 }

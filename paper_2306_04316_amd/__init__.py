@@ -47,7 +47,7 @@ def _stream_handle(stream):
 
 def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block=0, lds_slots=0,
             persistent=-1, order=-1, use_graph=True, tune=0, force_recheck=False, bound_scale=1.0,
-            tune_cache=None, timing=False, index=False) -> _lib.pip_options:
+            tune_cache=None, timing=False, index=False, predicate="side") -> _lib.pip_options:
     o = _lib.pip_options()
     _lib.load().pip_options_init(ctypes.byref(o))
     o.mode = _lib.MODES[mode] if isinstance(mode, str) else int(mode)
@@ -65,6 +65,7 @@ def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block
     o.tune_cache = tune_cache.encode() if tune_cache else None
     o.timing = 1 if timing else 0
     o.index = 1 if index else 0
+    o.predicate = _lib.PREDICATES[predicate] if isinstance(predicate, str) else int(predicate)
     return o
 
 
@@ -144,13 +145,13 @@ class Plan:
 
 
 def classify(px, py, offsets, vx, vy, point_poly=None, *, kernel="auto", validate=False, out=None,
-             stream=None, pairs_per_lane=0, block=0, lds_slots=0):
+             stream=None, pairs_per_lane=0, block=0, lds_slots=0, predicate="side"):
     """inside[i] for point i against polygon point_poly[i] (or polygon 0)."""
     import torch
     lib = _lib.load()
     n = px.numel()
     out = _check_inputs(px, py, offsets, vx, vy, point_poly, out)
-    o = options("exact", kernel, validate, pairs_per_lane, block, lds_slots)
+    o = options("exact", kernel, validate, pairs_per_lane, block, lds_slots, predicate=predicate)
     with torch.cuda.device(px.device):
         rc = lib.pip_classify(_ptr(px), _ptr(py), n, _ptr(offsets), offsets.numel() - 1, _ptr(vx), _ptr(vy),
                               vx.numel(), _ptr(point_poly), _ptr(out), ctypes.byref(o), _stream_handle(stream))

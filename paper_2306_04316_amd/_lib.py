@@ -13,6 +13,7 @@ STATUS_NAMES = {0: "PIP_OK", -1: "PIP_EINVAL", -2: "PIP_ERANGE", -3: "PIP_EDOM",
 
 MODES = {"exact": 0, "fp64": 0, "filtered": 1, "fp32": 1}
 KERNELS = {"auto": 0, "per_pair": 1, "segmented": 2, "staged": 3, "runs": 4}
+PREDICATES = {"side": 0, "c1": 0, "intersection": 1, "c2": 1}
 
 
 class PipError(RuntimeError):
@@ -27,7 +28,7 @@ class pip_options(ctypes.Structure):
                 ("lds_slots", ctypes.c_int32), ("persistent", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("tune", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
                 ("bound_scale", ctypes.c_float), ("tune_cache", ctypes.c_char_p), ("timing", ctypes.c_int32),
-                ("index", ctypes.c_int32)]
+                ("predicate", ctypes.c_int32), ("index", ctypes.c_int32)]
 
 
 class pip_plan_config(ctypes.Structure):

@@ -145,6 +145,7 @@ void pip_options_init(pip_options *opts)
     opts->tune_cache = NULL;
     opts->timing = 0;
     opts->index = 0;
+    opts->predicate = PIP_PRED_SIDE;
 }
 
 int pip_abi_version(void) { return PIP_ABI_VERSION; }
@@ -168,7 +169,10 @@ int pip_classify(const double *px, const double *py, int64_t n_points, const int
         return fail(PIP_EINVAL, "pip_classify supports PIP_MODE_EXACT_FP64 only (mode=%d); use a plan", o.mode);
     if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_RUNS)
         return fail(PIP_EINVAL, "unknown kernel %d", o.kernel);
+    if (o.predicate != PIP_PRED_SIDE && o.predicate != PIP_PRED_INTERSECTION)
+        return fail(PIP_EINVAL, "unknown predicate %d", o.predicate);
     Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
+    p.pred = o.predicate;
     PIP_TRY(check_host_args(p));
     DeviceInfo *dev = nullptr;
     PIP_TRY(current_device(&dev));

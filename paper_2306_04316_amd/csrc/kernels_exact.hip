@@ -15,6 +15,7 @@ namespace {
 // One lane per pair.  Each lane walks its own polygon's ring with ordinary
 // (per-lane) global loads.  No preprocessing, no data sharing beyond what the
 // caches give.
+template <int PRED>
 __global__ __launch_bounds__(256) void k_per_pair_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys,
@@ -36,7 +37,7 @@ __global__ __launch_bounds__(256) void k_per_pair_fp64(
         for (int64_t j = b; j < e; ++j) {
             const double bx = vx[j], by = vy[j];
             const bool b_above = by > y;
-            par ^= edge_cross(x, y, ax, ay, a_above, bx, by, b_above);
+            par ^= edge_cross<PRED>(x, y, ax, ay, a_above, bx, by, b_above);
             ax = bx;
             ay = by;
             a_above = b_above;
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(256) void k_per_pair_fp64(
 // batch, shared by all of them), then the next group goes.  With pairs sorted
 // by polygon a row sees one or two groups.
 
-template <bool HAS_INDEX, int U>
+template <int PRED, bool HAS_INDEX, int U>
 __global__ __launch_bounds__(256) void k_segmented_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys,
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(256) void k_segmented_fp64(
             int64_t b = offsets[qu], e = offsets[qu + 1];
             clamp_ring(b, e, nv);
             const uint64_t member = todo & __builtin_amdgcn_ballot_w64(q[u] == qu);
-            par |= ring_parity_compact_uniform(x[u], y[u], (member >> lane) & 1u, vx, vy, b, e) & member;
+            par |= ring_parity_compact_uniform<PRED>(x[u], y[u], (member >> lane) & 1u, vx, vy, b, e) & member;
             todo &= ~member;
         }
         if (valid)
@@ -130,7 +131,9 @@ struct StageLayout {
 
 // Classify the 256*U pairs starting at p0 (one workgroup, 256 threads).
 // smem: dynamic LDS of staged_smem_bytes(max_edges, max_rings) bytes.
-template <int U>
+// Edge records: constraint 1 stores (a_x, a_y, n_x, n_y) with the normal
+// oriented n_x > 0; constraint 2 stores (a_x, a_y, d_x, d_y), d = b - a.
+template <int PRED, int U>
 __device__ __forceinline__ void staged_item_fp64(
     int64_t p0, const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys,
@@ -206,13 +209,17 @@ __device__ __forceinline__ void staged_item_fp64(
             for (int j = lane; j < k; j += 64) {
                 const int jp = j == 0 ? k - 1 : j - 1;
                 const double ax = rx[jp], ay = ry[jp], bx = rx[j], by = ry[j];
-                double nx = by - ay;
-                double ny = ax - bx;
-                if (nx < 0.0) {
-                    nx = -nx;
-                    ny = -ny;
+                if (PRED == kIntersection) {
+                    E[e0 + j] = make_double4(ax, ay, bx - ax, by - ay);
+                } else {
+                    double nx = by - ay;
+                    double ny = ax - bx;
+                    if (nx < 0.0) {
+                        nx = -nx;
+                        ny = -ny;
+                    }
+                    E[e0 + j] = make_double4(ax, ay, nx, ny);
                 }
-                E[e0 + j] = make_double4(ax, ay, nx, ny);
                 Y[yb + 1 + j] = by;
                 if (j == k - 1)
                     Y[yb] = by;
@@ -269,10 +276,18 @@ __device__ __forceinline__ void staged_item_fp64(
                     const int j = __builtin_clz(strad);
                     strad ^= 0x80000000u >> j;
                     const double4 rec = er[j];
-                    const double t1 = xu - rec.x;
-                    const double t2 = yu - rec.y;
-                    const double sv = t1 * rec.z + t2 * rec.w;
-                    par ^= __builtin_amdgcn_ballot_w64(sv <= 0.0);
+                    bool cr;
+                    if (PRED == kIntersection) {
+                        const double lam = (yu - rec.y) / rec.w;
+                        const double xn = rec.x + lam * rec.z;
+                        cr = xn >= xu;
+                    } else {
+                        const double t1 = xu - rec.x;
+                        const double t2 = yu - rec.y;
+                        const double sv = t1 * rec.z + t2 * rec.w;
+                        cr = sv <= 0.0;
+                    }
+                    par ^= __builtin_amdgcn_ballot_w64(cr);
                 }
             }
             const int64_t i = p0 + u * 256 + tid;
@@ -283,14 +298,14 @@ __device__ __forceinline__ void staged_item_fp64(
     }
 
     // fallback: groups of lanes sharing a polygon, ring streamed through scalar loads
-    group_walk_rows<U>(p0, x, y, q, n, offsets, n_polys, vx, vy, nv, inside);
+    group_walk_rows<PRED, U>(p0, x, y, q, n, offsets, n_polys, vx, vy, nv, inside);
 }
 
 // Batched form.  With a queue, a grid sized to the resident capacity pulls
 // items (blocks of 256*U pairs) from an atomic counter in the order given by
 // `order` (heaviest first; NULL = natural order) until the list is exhausted.
 // Without a queue, workgroup b takes item order[b] (or b).
-template <int U>
+template <int PRED, int U>
 __global__ __launch_bounds__(256) void k_staged_batched_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys,
@@ -303,7 +318,7 @@ __global__ __launch_bounds__(256) void k_staged_batched_fp64(
     __shared__ int s_item;
     if (!queue) {
         const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
-        staged_item_fp64<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly,
+        staged_item_fp64<PRED, U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly,
                             inside, max_edges, max_rings, smem, &s_kmax);
         return;
     }
@@ -316,7 +331,7 @@ __global__ __launch_bounds__(256) void k_staged_batched_fp64(
         if (it >= n_items)
             break;
         const int item = order ? order[it] : it;
-        staged_item_fp64<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly,
+        staged_item_fp64<PRED, U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly,
                             inside, max_edges, max_rings, smem, &s_kmax);
         __syncthreads();
     }
@@ -333,7 +348,7 @@ __global__ __launch_bounds__(256) void k_staged_batched_fp64(
 // then every lane evaluates the side value for its own straddling edges only.
 // A run has a single polygon, so no lane waits for another polygon's ring,
 // and the ring's size is the run's cost whatever it is (3 or 10^6 vertices).
-template <int U>
+template <int PRED, int U>
 __device__ __forceinline__ void runs_item_fp64(
     int64_t p0, const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys,
@@ -377,7 +392,7 @@ __device__ __forceinline__ void runs_item_fp64(
         const double2 pt = P[j < WP ? j : WP - 1];
         int64_t b = offsets[qs], e = offsets[qs + 1];
         clamp_ring(b, e, nv);
-        const uint64_t par = ring_parity_compact_uniform(pt.x, pt.y, member, vx, vy, b, e);
+        const uint64_t par = ring_parity_compact_uniform<PRED>(pt.x, pt.y, member, vx, vy, b, e);
         if (member)
             inside[wbase + j] = (uint8_t)((par >> lane) & 1u);
         s += cnt;
@@ -387,7 +402,7 @@ __device__ __forceinline__ void runs_item_fp64(
 // LDS per workgroup: 4 wavefronts x 64*U pairs x (point 16 B + polygon id 4 B)
 inline size_t runs_lds_bytes(int pairs_per_lane) { return (size_t)4 * 64 * pairs_per_lane * (16 + 4); }
 
-template <int U>
+template <int PRED, int U>
 __global__ __launch_bounds__(256) void k_runs_batched_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys,
@@ -399,7 +414,7 @@ __global__ __launch_bounds__(256) void k_runs_batched_fp64(
     __shared__ int s_item;
     if (!queue) {
         const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
-        runs_item_fp64<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside,
+        runs_item_fp64<PRED, U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside,
                           smem);
         return;
     }
@@ -412,7 +427,7 @@ __global__ __launch_bounds__(256) void k_runs_batched_fp64(
         if (it >= n_items)
             break;
         const int item = order ? order[it] : it;
-        runs_item_fp64<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside,
+        runs_item_fp64<PRED, U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside,
                           smem);
         __syncthreads();
     }
@@ -473,37 +488,49 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 
 int launch_per_pair(const Problem &p, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_per_pair_fp64, dim3(grid_for(p.n_points, 256)), dim3(256), 0, stream, p.px, p.py,
-                       p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside);
+    if (p.pred == kIntersection)
+        hipLaunchKernelGGL(k_per_pair_fp64<kIntersection>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, stream,
+                           p.px, p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly,
+                           p.inside);
+    else
+        hipLaunchKernelGGL(k_per_pair_fp64<kSide>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, stream, p.px,
+                           p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside);
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
 }
 
-template <int U>
+template <int PRED, int U>
 static int launch_segmented_u(const Problem &p, hipStream_t stream, int block)
 {
     const int64_t per_block = (int64_t)block * U;
     const dim3 grid(grid_for(p.n_points, (int)per_block)), blk(block);
     if (p.point_poly)
-        hipLaunchKernelGGL((k_segmented_fp64<true, U>), grid, blk, 0, stream, p.px, p.py, p.n_points, p.offsets,
+        hipLaunchKernelGGL((k_segmented_fp64<PRED, true, U>), grid, blk, 0, stream, p.px, p.py, p.n_points, p.offsets,
                            p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside);
     else
-        hipLaunchKernelGGL((k_segmented_fp64<false, U>), grid, blk, 0, stream, p.px, p.py, p.n_points,
+        hipLaunchKernelGGL((k_segmented_fp64<PRED, false, U>), grid, blk, 0, stream, p.px, p.py, p.n_points,
                            p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside);
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
+}
+
+template <int PRED>
+static int launch_segmented_p(const Problem &p, hipStream_t stream, int pairs_per_lane, int block)
+{
+    switch (pairs_per_lane) {
+    case 1: return launch_segmented_u<PRED, 1>(p, stream, block);
+    case 2: return launch_segmented_u<PRED, 2>(p, stream, block);
+    case 8: return launch_segmented_u<PRED, 8>(p, stream, block);
+    default: return launch_segmented_u<PRED, 4>(p, stream, block);
+    }
 }
 
 int launch_segmented(const Problem &p, hipStream_t stream, int pairs_per_lane, int block)
 {
     if (block != 64 && block != 128 && block != 256)
         block = 256;
-    switch (pairs_per_lane) {
-    case 1: return launch_segmented_u<1>(p, stream, block);
-    case 2: return launch_segmented_u<2>(p, stream, block);
-    case 8: return launch_segmented_u<8>(p, stream, block);
-    default: return launch_segmented_u<4>(p, stream, block);
-    }
+    return p.pred == kIntersection ? launch_segmented_p<kIntersection>(p, stream, pairs_per_lane, block)
+                                   : launch_segmented_p<kSide>(p, stream, pairs_per_lane, block);
 }
 
 size_t staged_smem_bytes(int max_edges, int max_rings)
@@ -530,7 +557,12 @@ int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_la
     if (grid <= 0)
         return PIP_OK;
 #define PIP_LAUNCH_S(UU)                                                                                         \
-    hipLaunchKernelGGL((k_staged_batched_fp64<UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,            \
+    if (p.pred == kIntersection)                                                                                 \
+        hipLaunchKernelGGL((k_staged_batched_fp64<kIntersection, UU>), dim3(grid), dim3(256), shmem, stream, p.px, \
+                           p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly,        \
+                           p.inside, max_edges, max_rings, order, n_items, queue);                                 \
+    else                                                                                                         \
+    hipLaunchKernelGGL((k_staged_batched_fp64<kSide, UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,     \
                        p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside,        \
                        max_edges, max_rings, order, n_items, queue)
     if (U == 1)
@@ -551,11 +583,11 @@ int staged_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu)
     int nb = 0;
     hipError_t e;
     if (U == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<1>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 1>, 256, shmem);
     else if (U == 4)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<4>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 4>, 256, shmem);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<2>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 2>, 256, shmem);
     if (e != hipSuccess)
         return fail(PIP_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
     *blocks_per_cu = nb < 1 ? 1 : nb;
@@ -574,7 +606,12 @@ int launch_runs_batched(const Problem &p, hipStream_t stream, int pairs_per_lane
     if (grid <= 0)
         return PIP_OK;
 #define PIP_LAUNCH_R(UU)                                                                                         \
-    hipLaunchKernelGGL((k_runs_batched_fp64<UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py, p.n_points,  \
+    if (p.pred == kIntersection)                                                                                 \
+        hipLaunchKernelGGL((k_runs_batched_fp64<kIntersection, UU>), dim3(grid), dim3(256), shmem, stream, p.px,  \
+                           p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly,        \
+                           p.inside, order, n_items, queue);                                                       \
+    else                                                                                                         \
+    hipLaunchKernelGGL((k_runs_batched_fp64<kSide, UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py, p.n_points, \
                        p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside, order, n_items, queue)
     if (U == 1)
         PIP_LAUNCH_R(1);
@@ -594,11 +631,11 @@ int runs_occupancy(int pairs_per_lane, int *blocks_per_cu)
     int nb = 0;
     hipError_t e;
     if (U == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_runs_batched_fp64<1>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_runs_batched_fp64<kSide, 1>, 256, shmem);
     else if (U == 4)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_runs_batched_fp64<4>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_runs_batched_fp64<kSide, 4>, 256, shmem);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_runs_batched_fp64<2>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_runs_batched_fp64<kSide, 2>, 256, shmem);
     if (e != hipSuccess)
         return fail(PIP_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
     *blocks_per_cu = nb < 1 ? 1 : nb;

@@ -149,7 +149,7 @@ __device__ __forceinline__ void filtered_item(
     if (!staged) {
         // Rings too large for the workgroup's LDS (or unsorted pairs): these
         // pairs take the exact binary64 wave-uniform walk instead.
-        group_walk_rows<U>(p0, x, y, q, n, offsets, n_polys, vx, vy, nv, inside);
+        group_walk_rows<kSide, U>(p0, x, y, q, n, offsets, n_polys, vx, vy, nv, inside);
         return;
     }
 

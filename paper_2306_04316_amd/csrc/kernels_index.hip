@@ -151,6 +151,7 @@ __device__ __forceinline__ bool node_hit(double y, double2 bnd, uint32_t &prev)
 }
 
 // Rows of 64 y-ordered points against the one ring, walked through the tree.
+template <int PRED>
 __global__ __launch_bounds__(256) void k_runs_indexed_fp64(const double2 *__restrict__ spt,
                                                            const int32_t *__restrict__ sidx, int64_t n,
                                                            const double *__restrict__ rx,
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(256) void k_runs_indexed_fp64(const double2 *__rest
                 for (int c = 32 * g1; c < ce; ++c) {
                     if (!node_hit(p.y, tr.b0[c], prev))
                         continue;
-                    par ^= chunk_parity_uniform(p.x, p.y, yq, member, rx, ry, k, 32 * c, prev);
+                    par ^= chunk_parity_uniform<PRED>(p.x, p.y, yq, member, rx, ry, k, 32 * c, prev);
                 }
             }
         }
@@ -256,9 +257,14 @@ int launch_runs_indexed(const Problem &p, hipStream_t s, const IndexLayout &L, u
     tr.n0 = L.n0;
     tr.n1 = L.n1;
     tr.n2 = L.n2;
-    hipLaunchKernelGGL(k_runs_indexed_fp64, dim3(grid_for(p.n_points, 256)), dim3(256), 0, s,
-                       (const double2 *)(ws + L.o_spt), (const int32_t *)(ws + L.o_sidx), p.n_points, p.vx, p.vy,
-                       (int)p.n_vertices, tr, p.inside);
+    if (p.pred == kIntersection)
+        hipLaunchKernelGGL(k_runs_indexed_fp64<kIntersection>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, s,
+                           (const double2 *)(ws + L.o_spt), (const int32_t *)(ws + L.o_sidx), p.n_points, p.vx,
+                           p.vy, (int)p.n_vertices, tr, p.inside);
+    else
+        hipLaunchKernelGGL(k_runs_indexed_fp64<kSide>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, s,
+                           (const double2 *)(ws + L.o_spt), (const int32_t *)(ws + L.o_sidx), p.n_points, p.vx,
+                           p.vy, (int)p.n_vertices, tr, p.inside);
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
 }

@@ -51,6 +51,7 @@ struct Problem {
     int64_t n_vertices;
     const int32_t *point_poly;
     uint8_t *inside;
+    int pred = 0;   // pip_predicate
 };
 
 int check_host_args(const Problem &p);

@@ -193,8 +193,9 @@ std::string tune_key(const pip_plan *pl)
         return b;
     };
     char buf[160];
-    snprintf(buf, sizeof buf, "gfx950:m%d:k%d:n%d:p%d:v%d:i%d", pl->o.mode, pl->o.kernel, lg(pl->p.n_points),
-             lg(pl->p.n_polys), lg(pl->p.n_vertices), pl->p.point_poly ? 1 : 0);
+    snprintf(buf, sizeof buf, "gfx950:m%d:k%d:n%d:p%d:v%d:i%d%s", pl->o.mode, pl->o.kernel, lg(pl->p.n_points),
+             lg(pl->p.n_polys), lg(pl->p.n_vertices), pl->p.point_poly ? 1 : 0,
+             pl->o.predicate == PIP_PRED_INTERSECTION ? ":c2" : "");
     return buf;
 }
 
@@ -398,6 +399,10 @@ int check_options(const pip_options *opts, pip_options &o)
         return fail(PIP_EINVAL, "bound_scale must be >= 0");
     if (o.index && o.mode != PIP_MODE_EXACT_FP64)
         return fail(PIP_EINVAL, "the y-index runs in the exact mode only");
+    if (o.predicate != PIP_PRED_SIDE && o.predicate != PIP_PRED_INTERSECTION)
+        return fail(PIP_EINVAL, "unknown predicate %d", o.predicate);
+    if (o.predicate != PIP_PRED_SIDE && o.mode != PIP_MODE_EXACT_FP64)
+        return fail(PIP_EINVAL, "the filtered mode implements the side test (constraint 1) only");
     return PIP_OK;
 }
 
@@ -419,6 +424,7 @@ int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t 
     pip_options o;
     PIP_TRY(check_options(opts, o));
     Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
+    p.pred = o.predicate;
     PIP_TRY(check_host_args(p));
     DeviceInfo *dev = nullptr;
     PIP_TRY(current_device(&dev));

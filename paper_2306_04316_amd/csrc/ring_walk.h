@@ -27,20 +27,39 @@ __device__ __forceinline__ void clamp_ring(int64_t &b, int64_t &e, int64_t nv)
     e = (e - b > INT32_MAX) ? b + INT32_MAX : e;
 }
 
+// Which test decides a straddling edge's crossing (paper, Method section):
+//   kSide: constraint 1, (p - a) . n <= 0 with the normal oriented n_x > 0
+//   kIntersection: constraint 2, lambda = (p_y - a_y) / d_y,
+//                  x = a_x + lambda * d_x, crossing iff x >= p_x
+enum Predicate : int { kSide = 0, kIntersection = 1 };
+
+// Crossing bit of a straddling edge (a, b); b_above says which endpoint is
+// above the ray (so the normal's orientation needs no negation, see above).
+template <int PRED>
+__device__ __forceinline__ bool straddle_crosses(double x, double y, double ax, double ay, double bx, double by,
+                                                 bool b_above)
+{
+    if (PRED == kIntersection) {
+        const double dx = bx - ax;
+        const double dy = by - ay;
+        const double lam = (y - ay) / dy;
+        const double xn = ax + lam * dx;
+        return xn >= x;
+    }
+    const double nx = by - ay;
+    const double ny = ax - bx;
+    const double t1 = x - ax;
+    const double t2 = y - ay;
+    const double s = t1 * nx + t2 * ny;
+    return b_above ? (s <= 0.0) : (s >= 0.0);
+}
+
 // Crossing-parity contribution of edge (a, b) for point (x, y).
+template <int PRED>
 __device__ __forceinline__ unsigned edge_cross(double x, double y, double ax, double ay, bool a_above,
                                                double bx, double by, bool b_above)
 {
-    unsigned c = 0;
-    if (a_above != b_above) {
-        const double nx = by - ay;
-        const double ny = ax - bx;
-        const double t1 = x - ax;
-        const double t2 = y - ay;
-        const double s = t1 * nx + t2 * ny;
-        c = b_above ? (s <= 0.0) : (s >= 0.0);
-    }
-    return c;
+    return (a_above != b_above && straddle_crosses<PRED>(x, y, ax, ay, bx, by, b_above)) ? 1u : 0u;
 }
 
 // Shift the "vertex above the ray" bit of y_v into the low end of word w.
@@ -57,63 +76,6 @@ __device__ __forceinline__ uint32_t shift_in_above(uint32_t w, double yq, double
     return __builtin_amdgcn_alignbit(w, hi, 31);
 }
 
-// One edge step in lane-mask form, for a whole wavefront at once.  Every lane
-// runs it (uniform control flow); bit l of each mask belongs to lane l.
-//   ca/cb : lanes whose point is below a / b (a_y > p_y, b_y > p_y)
-//   st    : straddling lanes (exactly one endpoint above the ray)
-// The crossing test is (b above ? s' <= 0 : s' >= 0) with the unnegated normal
-// (see the note at the top of this file).  Returns the lanes whose crossing
-// count the edge increments; updates ca to cb.
-__device__ __forceinline__ uint64_t edge_step_mask(double x, double y, double ax, double ay, double bx, double by,
-                                                   uint64_t &ca)
-{
-    const uint64_t cb = __builtin_amdgcn_ballot_w64(by > y);
-    const uint64_t st = ca ^ cb;
-    const double nx = by - ay;
-    const double ny = ax - bx;
-    const double t1 = x - ax;
-    const double t2 = y - ay;
-    const double s = t1 * nx + t2 * ny;
-    const uint64_t le = __builtin_amdgcn_ballot_w64(s <= 0.0);
-    const uint64_t ge = __builtin_amdgcn_ballot_w64(s >= 0.0);
-    ca = cb;
-    return st & ((cb & le) | (~cb & ge));
-}
-
-// Walk ring [b, e) (wave-uniform, streamed through scalar loads) for every
-// lane's point; returns the lanes with an odd crossing count.  Must be called
-// with the whole wavefront active.
-__device__ __forceinline__ uint64_t ring_parity_uniform(double x, double y, const double *__restrict__ vx,
-                                                        const double *__restrict__ vy, int64_t b, int64_t e)
-{
-    // ring-relative 32-bit indices keep the loop control in scalar ALU
-    // instructions (gfx9 has no 64-bit scalar ordered compare)
-    const int k = (int)(e - b);
-    const double *__restrict__ rx = vx + b;
-    const double *__restrict__ ry = vy + b;
-    uint64_t par = 0;
-    if (k <= 0)
-        return 0;
-    double ax = rx[k - 1], ay = ry[k - 1];     // closing edge v_{k-1} -> v_0 first
-    uint64_t ca = __builtin_amdgcn_ballot_w64(ay > y);
-    for (int j0 = 0; j0 < k; j0 += 8) {
-        double bxs[8], bys[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int j = (j0 + t < k) ? j0 + t : k - 1;   // clamped: repeats v_{k-1}, a zero-length edge
-            bxs[t] = rx[j];
-            bys[t] = ry[j];
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            par ^= edge_step_mask(x, y, ax, ay, bxs[t], bys[t], ca);
-            ax = bxs[t];
-            ay = bys[t];
-        }
-    }
-    return par;
-}
-
 // One 32-edge chunk of a wave-uniform ring with compacted side tests: edges
 // c0 .. c0+m-1 (m <= 32), i.e. vertices v_{c0-1} -> v_{c0} onwards.  The ring's
 // y values stream through scalar loads into each lane's 32-bit "above" word
@@ -122,6 +84,7 @@ __device__ __forceinline__ uint64_t ring_parity_uniform(double x, double y, cons
 // itself.  `prev` holds the above bit of v_{c0-1} on entry and of the chunk's
 // last vertex on exit.  Returns the lanes with an odd number of crossings in
 // the chunk.
+template <int PRED>
 __device__ __forceinline__ uint64_t chunk_parity_uniform(double x, double y, double yq, bool member,
                                                          const double *__restrict__ rx,
                                                          const double *__restrict__ ry, int k, int c0,
@@ -157,18 +120,14 @@ __device__ __forceinline__ uint64_t chunk_parity_uniform(double x, double y, dou
         const int ja = jb == 0 ? k - 1 : jb - 1;
         const double ax = rx[ja], ay = ry[ja], bx = rx[jb], by = ry[jb];
         const bool b_above = (above >> (31 - j)) & 1u;
-        const double nx = by - ay;
-        const double ny = ax - bx;
-        const double t1 = x - ax;
-        const double t2 = y - ay;
-        const double s = t1 * nx + t2 * ny;
-        par ^= __builtin_amdgcn_ballot_w64(b_above ? (s <= 0.0) : (s >= 0.0));
+        par ^= __builtin_amdgcn_ballot_w64(straddle_crosses<PRED>(x, y, ax, ay, bx, by, b_above));
     }
     return par;
 }
 
 // Crossing parity of every lane's point against the wave-uniform ring [b, e),
 // chunk by chunk.  Must be called with the whole wavefront active.
+template <int PRED>
 __device__ __forceinline__ uint64_t ring_parity_compact_uniform(double x, double y, bool member,
                                                                 const double *__restrict__ vx,
                                                                 const double *__restrict__ vy, int64_t b,
@@ -183,14 +142,14 @@ __device__ __forceinline__ uint64_t ring_parity_compact_uniform(double x, double
     const double yq = y + 0.0;
     uint32_t prev = shift_in_above(0u, yq, ry[k - 1]);
     for (int c0 = 0; c0 < k; c0 += 32)
-        par ^= chunk_parity_uniform(x, y, yq, member, rx, ry, k, c0, prev);
+        par ^= chunk_parity_uniform<PRED>(x, y, yq, member, rx, ry, k, c0, prev);
     return par;
 }
 
 // Rows u of a workgroup item whose rings were not staged: lanes that share a
 // polygon run together (leader = first unfinished lane), each group walking
 // its ring wave-uniformly with compacted side tests.
-template <int U>
+template <int PRED, int U>
 __device__ __forceinline__ void group_walk_rows(int64_t p0, const double (&x)[U], const double (&y)[U],
                                                 const int (&q)[U], int64_t n, const int64_t *__restrict__ offsets,
                                                 int64_t n_polys, const double *__restrict__ vx,
@@ -211,7 +170,7 @@ __device__ __forceinline__ void group_walk_rows(int64_t p0, const double (&x)[U]
             int64_t b = offsets[qu], e = offsets[qu + 1];
             clamp_ring(b, e, nv);
             const uint64_t member = todo & __builtin_amdgcn_ballot_w64(qv == qu);
-            par |= ring_parity_compact_uniform(x[u], y[u], (member >> lane) & 1u, vx, vy, b, e) & member;
+            par |= ring_parity_compact_uniform<PRED>(x[u], y[u], (member >> lane) & 1u, vx, vy, b, e) & member;
             todo &= ~member;
         }
         if (i < n)

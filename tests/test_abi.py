@@ -81,6 +81,19 @@ def test_host_argument_errors(lib):
     o.kernel = 0
     rc = lib.pip_classify(dummy, dummy, 10, None, 1, dummy, dummy, 4, None, dummy, ctypes.byref(o), None)
     assert rc == _lib.PIP_EINVAL
+    # unknown predicate
+    o.predicate = 7
+    rc = lib.pip_classify(dummy, dummy, 10, dummy, 1, dummy, dummy, 4, None, dummy, ctypes.byref(o), None)
+    assert rc == _lib.PIP_EINVAL and b"predicate" in lib.pip_last_error()
+    # constraint 2 is not offered by the binary32 filter
+    o.predicate = 1
+    o.mode = 1
+    plan = ctypes.c_void_p()
+    rc = lib.pip_plan_create(ctypes.byref(plan), dummy, dummy, 10, dummy, 1, dummy, dummy, 4, None, dummy,
+                             ctypes.byref(o), None)
+    assert rc == _lib.PIP_EINVAL and b"filtered" in lib.pip_last_error()
+    o.predicate = 0
+    o.mode = 0
     # copy probe with a size that is not a multiple of 16
     rc = lib.pip_probe_copy(dummy, dummy, 17, None)
     assert rc == _lib.PIP_EINVAL
