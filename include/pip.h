@@ -131,9 +131,11 @@ typedef struct {
     int32_t lds_slots;      /* tuning, staged kernel: edges a workgroup can stage in
                                LDS (40 bytes each exact, 20 filtered; at most 2048);
                                0 = default */
-    int32_t persistent;     /* plans: 1 = a resident grid pulls work items from an
-                               atomic queue, 0 = one workgroup per item,
-                               -1 = automatic */
+    int32_t persistent;     /* plans: 1 = a resident grid walks the work items
+                               (staged exact kernel: fixed stride, polygon ranges
+                               looked up 64 items ahead; other kernels: an
+                               atomic queue), 0 or -1 = one workgroup per item
+                               (default) */
     int32_t order;          /* plans: 1 = items heaviest first (estimated edges x
                                pairs), 0 = natural order, -1 = automatic */
     int32_t use_graph;      /* plans: 1 = capture the step sequence in a HIP graph

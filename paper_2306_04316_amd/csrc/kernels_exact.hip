@@ -107,12 +107,16 @@ __global__ __launch_bounds__(256) void k_segmented_fp64(
 // ---------------------------------------------------------------- staged (rings in LDS, compacted side tests)
 // A workgroup owns 256*U consecutive pairs (thread t, row u: pair
 // base + 256u + t).  When the pairs are sorted by polygon, the rings they test
-// form one contiguous vertex range.  The workgroup stages it once in LDS as
-//   Y : per ring, y_{k-1}, y_0, .., y_{k-1}   (the straddle pass input)
-//   E : per edge j = (v_{j-1}, v_j), the record (a_x, a_y, n_x, n_y) with the
-//       normal n = (b_y - a_y, a_x - b_x) negated when n_x < 0, computed in
-//       binary64 exactly as the rule states (so the side value below is the
-//       rule's, bit for bit).
+// form one contiguous vertex range [vb, ve).  The workgroup stages it once in
+// LDS, all threads together (one coalesced load per vertex, edges of every
+// ring in parallel):
+//   T  : ring starts relative to vb (T[r] .. T[r+1]-1 are ring r's vertices)
+//   Y  : y of every vertex of the range (the straddle pass input)
+//   XR : x of every vertex (only to build E)
+//   E  : per edge j = (v_{j-1}, v_j) of its ring, the record (a_x, a_y, n_x, n_y)
+//        with the normal n = (b_y - a_y, a_x - b_x) negated when n_x < 0,
+//        computed in binary64 exactly as the rule states (so the side value
+//        below is the rule's, bit for bit).
 // Each lane then runs two phases per 32-vertex chunk of its own ring:
 //   1. straddle pass: above_j = (y_j > p_y) for every vertex (one compare,
 //      exact), shifted into a 32-bit word; straddle bits = above XOR above
@@ -123,11 +127,75 @@ __global__ __launch_bounds__(256) void k_segmented_fp64(
 // short; phase 1 costs two vector instructions per vertex.
 // A workgroup whose rings do not fit (or whose pairs are not sorted) falls
 // back to the scalar-load group walk.
-struct StageLayout {
-    int t_off;   // int   T[n_rings + 1]: ring start (edge index) relative to the range start
-    int y_off;   // double Y[n_edges + n_rings + pad]
-    int e_off;   // double4 E[n_edges]
+struct StagedLds {
+    int *T;
+    double *Y;
+    double *XR;
+    double4 *E;
 };
+
+__device__ __forceinline__ StagedLds staged_lds(unsigned char *smem, int max_edges, int max_rings)
+{
+    StagedLds L;
+    L.T = (int *)smem;
+    size_t o = (((size_t)(max_rings + 1) * 4 + 31) & ~(size_t)31);
+    L.Y = (double *)(smem + o);
+    o += (((size_t)max_edges + 64) * 8 + 31) & ~(size_t)31;
+    L.XR = (double *)(smem + o);
+    o += ((size_t)max_edges * 8 + 31) & ~(size_t)31;
+    L.E = (double4 *)(smem + o);
+    return L;
+}
+
+// Ring of staged vertex e: the r with T[r] <= e < T[r+1] (T sorted, T[0] = 0,
+// T[nr] > e).  Returns -1 when the table is not sorted around e (offsets that
+// are not monotone; such inputs have unspecified results, but every access
+// stays inside the staged range).
+__device__ __forceinline__ int staged_ring_of(const int *T, int nr, int e)
+{
+    int lo = 0, hi = nr;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (T[mid] <= e)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return (T[lo] <= e && e < T[lo + 1]) ? lo : -1;
+}
+
+// Where a work item's rings lie: the polygons of its first and last pair
+// (pairs sorted by polygon) and their vertex range [vb, vb + nv).  `ok` is
+// false when the ids are out of range or not ordered.
+struct ItemRange {
+    int64_t vb;
+    int qf, ql;
+    int nv;
+    int ok;
+};
+
+__device__ __forceinline__ ItemRange item_range(int64_t p0, int64_t pairs, int64_t n, const int64_t *__restrict__ offsets,
+                                                int64_t n_polys, int64_t nv, const int32_t *__restrict__ point_poly)
+{
+    ItemRange R;
+    const int64_t plast = (p0 + pairs < n ? p0 + pairs : n) - 1;
+    R.qf = 0;
+    R.ql = 0;
+    if (point_poly) {
+        R.qf = point_poly[p0];
+        R.ql = point_poly[plast];
+    }
+    R.ok = (uint32_t)R.qf < (uint64_t)n_polys && (uint32_t)R.ql < (uint64_t)n_polys && R.qf <= R.ql;
+    int64_t vb = 0, ve = 0;
+    if (R.ok) {
+        vb = offsets[R.qf];
+        ve = offsets[R.ql + 1];
+        clamp_ring(vb, ve, nv);
+    }
+    R.vb = vb;
+    R.nv = (int)(ve - vb);   // clamp_ring keeps it within [0, INT32_MAX]
+    return R;
+}
 
 // Classify the 256*U pairs starting at p0 (one workgroup, 256 threads).
 // smem: dynamic LDS of staged_smem_bytes(max_edges, max_rings) bytes.
@@ -139,13 +207,12 @@ __device__ __forceinline__ void staged_item_fp64(
     const int64_t *__restrict__ offsets, int64_t n_polys,
     const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
     const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
-    unsigned char *smem, int *s_kmax)
+    unsigned char *smem, const ItemRange R)
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wid = tid >> 6;
     const int ypad = 64;
-    const int y_alloc = max_edges + max_rings + ypad;
+    const int y_alloc = max_edges + ypad;
     double x[U], y[U];
     int q[U];
 #pragma unroll
@@ -161,91 +228,67 @@ __device__ __forceinline__ void staged_item_fp64(
         }
     }
 
-    // polygon range of the workgroup, from its first and last pair (sorted input)
-    const int64_t plast = (p0 + 256 * U < n ? p0 + 256 * U : n) - 1;
-    int qf = 0, ql = 0;
-    if (point_poly) {
-        qf = point_poly[p0];
-        ql = point_poly[plast];
-    }
-    const bool range_ok = (uint32_t)qf < (uint64_t)n_polys && (uint32_t)ql < (uint64_t)n_polys && qf <= ql;
-    int64_t vb = 0, ve = 0;
-    if (range_ok) {
-        vb = offsets[qf];
-        ve = offsets[ql + 1];
-        clamp_ring(vb, ve, nv);
-    }
+    // the workgroup's polygon range (the same for every thread, so `fits` is uniform)
+    const int qf = R.qf, ql = R.ql;
+    const int64_t vb = R.vb, ve = R.vb + R.nv;
     const int nr = ql - qf + 1;
+    const int nvr = R.nv;
+    const bool fits = R.ok && nvr <= max_edges && nr <= max_rings;
     bool mine_ok = true;
 #pragma unroll
     for (int u = 0; u < U; ++u)
         mine_ok = mine_ok && (q[u] < 0 || (q[u] >= qf && q[u] <= ql));
-    const bool staged =
-        __syncthreads_and(range_ok && ve - vb <= max_edges && nr <= max_rings && mine_ok);
 
-    int *T = (int *)smem;
-    double *Y = (double *)(smem + (((max_rings + 1) * 4 + 15) & ~15));
-    double4 *E = (double4 *)((unsigned char *)Y + ((((int64_t)max_edges + max_rings + ypad) * 8 + 31) & ~31));
-
-    if (staged) {
-        if (tid == 0)
-            *s_kmax = 0;
+    const StagedLds L = staged_lds(smem, max_edges, max_rings);
+    if (fits) {
         for (int r = tid; r <= nr; r += 256) {
             int64_t o = offsets[qf + r];
             o = o < vb ? vb : (o > ve ? ve : o);
-            T[r] = (int)(o - vb);
+            L.T[r] = (int)(o - vb);
         }
-        __syncthreads();
-        int kmax_local = 0;
-        for (int r = wid; r < nr; r += 4) {
-            const int e0 = T[r];
-            int e1 = T[r + 1];
-            e1 = e1 < e0 ? e0 : e1;
-            const int k = e1 - e0;
-            kmax_local = k > kmax_local ? k : kmax_local;
-            const int yb = e0 + r;
-            const double *__restrict__ rx = vx + vb + e0;
-            const double *__restrict__ ry = vy + vb + e0;
-            for (int j = lane; j < k; j += 64) {
-                const int jp = j == 0 ? k - 1 : j - 1;
-                const double ax = rx[jp], ay = ry[jp], bx = rx[j], by = ry[j];
-                if (PRED == kIntersection) {
-                    E[e0 + j] = make_double4(ax, ay, bx - ax, by - ay);
-                } else {
-                    double nx = by - ay;
-                    double ny = ax - bx;
-                    if (nx < 0.0) {
-                        nx = -nx;
-                        ny = -ny;
-                    }
-                    E[e0 + j] = make_double4(ax, ay, nx, ny);
+        for (int e = tid; e < nvr; e += 256) {
+            L.XR[e] = vx[vb + e];
+            L.Y[e] = vy[vb + e];
+        }
+        if (tid < ypad)
+            L.Y[nvr + tid] = 0.0;
+    }
+    const bool staged = __syncthreads_and(fits && mine_ok);
+
+    if (staged) {
+        for (int e = tid; e < nvr; e += 256) {
+            const int r = staged_ring_of(L.T, nr, e);
+            if (r < 0)
+                continue;
+            const int e0 = L.T[r];
+            const int ep = e == e0 ? L.T[r + 1] - 1 : e - 1;
+            const double ax = L.XR[ep], ay = L.Y[ep], bx = L.XR[e], by = L.Y[e];
+            if (PRED == kIntersection) {
+                L.E[e] = make_double4(ax, ay, bx - ax, by - ay);
+            } else {
+                double nx = by - ay;
+                double ny = ax - bx;
+                if (nx < 0.0) {
+                    nx = -nx;
+                    ny = -ny;
                 }
-                Y[yb + 1 + j] = by;
-                if (j == k - 1)
-                    Y[yb] = by;
+                L.E[e] = make_double4(ax, ay, nx, ny);
             }
         }
-        if (lane == 0)
-            atomicMax(s_kmax, kmax_local);
-        const int ytot = (int)(ve - vb) + nr;
-        if (tid < ypad)
-            Y[ytot + tid] = 0.0;
         __syncthreads();
-        const int kmax_b = *s_kmax;
 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int r = (q[u] < 0 ? qf : q[u]) - qf;
-            const int e0 = T[r];
-            int k = T[r + 1] - e0;
+            const int e0 = L.T[r];
+            int k = L.T[r + 1] - e0;
             k = k < 0 ? 0 : k;
-            const int yb = e0 + r;
             const double xu = x[u], yu = y[u];
             const double yq = yu + 0.0;
             uint64_t par = 0;
             // anchor: above bit of v_{k-1}
-            uint32_t above_prev = (k > 0 && Y[yb] > yu) ? 1u : 0u;
-            for (int c0 = 0; c0 < kmax_b; c0 += 32) {
+            uint32_t above_prev = (k > 0 && L.Y[e0 + k - 1] > yu) ? 1u : 0u;
+            for (int c0 = 0; c0 < max_edges; c0 += 32) {
                 if (__builtin_amdgcn_ballot_w64(k > c0) == 0)
                     break;
                 // phase 1: above bits of vertices c0 .. c0+31, first vertex in bit 31
@@ -253,9 +296,9 @@ __device__ __forceinline__ void staged_item_fp64(
                 // Lanes whose ring ended read past it (their bits are masked
                 // below); the clamp keeps those reads inside the Y allocation.
                 // A lane still inside its ring is never clamped: its chunk
-                // starts at most at the last staged slot, 64 slots before the end.
-                const int ybase = yb + 1 + c0;
-                const double *yr = Y + (ybase < y_alloc - 32 ? ybase : y_alloc - 32);
+                // starts at most at the last staged vertex, 64 slots before the end.
+                const int ybase = e0 + c0;
+                const double *yr = L.Y + (ybase < y_alloc - 32 ? ybase : y_alloc - 32);
                 int t = 0;
                 for (; t < 32; t += 4) {
                     if (__builtin_amdgcn_ballot_w64(k > c0 + t) == 0)
@@ -271,7 +314,7 @@ __device__ __forceinline__ void staged_item_fp64(
                     strad &= rem <= 0 ? 0u : ~(0xffffffffu >> rem);
                 above_prev = rem >= 32 ? (above & 1u) : above_prev;
                 // phase 2: side tests for this lane's straddling edges only
-                const double4 *er = E + e0 + c0;
+                const double4 *er = L.E + e0 + c0;
                 while (strad != 0) {
                     const int j = __builtin_clz(strad);
                     strad ^= 0x80000000u >> j;
@@ -301,39 +344,81 @@ __device__ __forceinline__ void staged_item_fp64(
     group_walk_rows<PRED, U>(p0, x, y, q, n, offsets, n_polys, vx, vy, nv, inside);
 }
 
-// Batched form.  With a queue, a grid sized to the resident capacity pulls
-// items (blocks of 256*U pairs) from an atomic counter in the order given by
-// `order` (heaviest first; NULL = natural order) until the list is exhausted.
-// Without a queue, workgroup b takes item order[b] (or b).
+// The range as wave-uniform values (the table entries below are read from
+// LDS by every lane at the same address).
+__device__ __forceinline__ ItemRange uniform_range(const ItemRange &R)
+{
+    ItemRange U;
+    const uint64_t vb = (uint64_t)R.vb;
+    U.vb = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(vb >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)vb));
+    U.qf = __builtin_amdgcn_readfirstlane(R.qf);
+    U.ql = __builtin_amdgcn_readfirstlane(R.ql);
+    U.nv = __builtin_amdgcn_readfirstlane(R.nv);
+    U.ok = __builtin_amdgcn_readfirstlane(R.ok);
+    return U;
+}
+
+// Batched form.  Without `persistent`, workgroup b takes item order[b] (or b)
+// and finds its polygon range itself: pair ids, then offsets, then vertices,
+// three dependent loads before any work.
+// With `persistent`, a grid sized to the resident capacity walks the item
+// list with a fixed stride (workgroup b: list positions b, b + G, b + 2G, ..).
+// Before each block of 64 of its items, 64 lanes look up all 64 polygon
+// ranges at once into an LDS table; each item then issues its point, ring
+// table and vertex loads together, so an item waits for one memory round
+// trip instead of three.  There is no shared counter to contend for: the
+// stride is fixed, and the heaviest-first order (if given) deals the costly
+// items out evenly.
+// Eight waves per SIMD hide the load latency best; the side-test variants fit
+// that register budget (64 VGPRs) without spilling, the intersection-test
+// variant with its division does not and keeps the compiler's choice.
 template <int PRED, int U>
-__global__ __launch_bounds__(256) void k_staged_batched_fp64(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRED == kSide ? 8 : 1)))
+void k_staged_batched_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys,
     const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
     const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
-    const int32_t *__restrict__ order, int n_items, unsigned *queue)
+    const int32_t *__restrict__ order, int n_items, int persistent)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_kmax;
-    __shared__ int s_item;
-    if (!queue) {
+    constexpr int IP = 256 * U;
+    if (!persistent) {
         const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
-        staged_item_fp64<PRED, U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly,
-                            inside, max_edges, max_rings, smem, &s_kmax);
+        const int64_t p0 = (int64_t)item * IP;
+        const ItemRange R = item_range(p0, IP, n, offsets, n_polys, nv, point_poly);
+        staged_item_fp64<PRED, U>(p0, px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside, max_edges,
+                                  max_rings, smem, R);
         return;
     }
-    for (;;) {
-        if (threadIdx.x == 0)
-            s_item = (int)atomicAdd(queue, 1u);
+    __shared__ ItemRange s_range[64];
+    __shared__ int s_item[64];
+    const int64_t G = gridDim.x;
+    for (int64_t first = blockIdx.x; first < n_items; first += 64 * G) {
+        __syncthreads();   // the previous block's items are done with the table
+        if (threadIdx.x < 64) {
+            const int64_t pos = first + (int64_t)threadIdx.x * G;
+            int item = -1;
+            ItemRange R;
+            R.vb = 0;
+            R.qf = R.ql = R.nv = R.ok = 0;
+            if (pos < n_items) {
+                item = order ? order[pos] : (int)pos;
+                R = item_range((int64_t)item * IP, IP, n, offsets, n_polys, nv, point_poly);
+            }
+            s_item[threadIdx.x] = item;
+            s_range[threadIdx.x] = R;
+        }
         __syncthreads();
-        const int it = s_item;
-        __syncthreads();
-        if (it >= n_items)
-            break;
-        const int item = order ? order[it] : it;
-        staged_item_fp64<PRED, U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly,
-                            inside, max_edges, max_rings, smem, &s_kmax);
-        __syncthreads();
+        for (int j = 0; j < 64; ++j) {
+            const int item = __builtin_amdgcn_readfirstlane(s_item[j]);
+            if (item < 0)
+                break;
+            staged_item_fp64<PRED, U>((int64_t)item * IP, px, py, n, offsets, n_polys, vx, vy, nv, point_poly,
+                                      inside, max_edges, max_rings, smem, uniform_range(s_range[j]));
+            __syncthreads();   // the next item reuses the staging area
+        }
     }
 }
 
@@ -535,9 +620,11 @@ int launch_segmented(const Problem &p, hipStream_t stream, int pairs_per_lane, i
 
 size_t staged_smem_bytes(int max_edges, int max_rings)
 {
-    const size_t t = (((size_t)(max_rings + 1) * 4 + 15) & ~(size_t)15);
-    const size_t yb = ((((size_t)max_edges + max_rings + 64) * 8 + 31) & ~(size_t)31);
-    return t + yb + (size_t)max_edges * 32;
+    // T | Y (with a 64-slot pad) | XR | E, each 32-byte aligned (as staged_lds lays them out)
+    size_t o = (((size_t)(max_rings + 1) * 4 + 31) & ~(size_t)31);
+    o += (((size_t)max_edges + 64) * 8 + 31) & ~(size_t)31;
+    o += ((size_t)max_edges * 8 + 31) & ~(size_t)31;
+    return o + (size_t)max_edges * 32;
 }
 
 int staged_max_rings(int pairs_per_lane)
@@ -547,12 +634,13 @@ int staged_max_rings(int pairs_per_lane)
 }
 
 int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_lane, int max_edges,
-                          const int32_t *order, int n_items, unsigned *queue, int grid)
+                          const int32_t *order, int n_items, bool persistent, int grid)
 {
     const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
     const int max_rings = staged_max_rings(U);
     const size_t shmem = staged_smem_bytes(max_edges, max_rings);
-    if (!queue)
+    const int pers = persistent ? 1 : 0;
+    if (!persistent)
         grid = n_items;
     if (grid <= 0)
         return PIP_OK;
@@ -560,11 +648,11 @@ int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_la
     if (p.pred == kIntersection)                                                                                 \
         hipLaunchKernelGGL((k_staged_batched_fp64<kIntersection, UU>), dim3(grid), dim3(256), shmem, stream, p.px, \
                            p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly,        \
-                           p.inside, max_edges, max_rings, order, n_items, queue);                                 \
+                           p.inside, max_edges, max_rings, order, n_items, pers);                                  \
     else                                                                                                         \
     hipLaunchKernelGGL((k_staged_batched_fp64<kSide, UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,     \
                        p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside,        \
-                       max_edges, max_rings, order, n_items, queue)
+                       max_edges, max_rings, order, n_items, pers)
     if (U == 1)
         PIP_LAUNCH_S(1);
     else if (U == 4)
@@ -648,7 +736,7 @@ int launch_staged(const Problem &p, hipStream_t stream, int pairs_per_lane, int 
     // clamped to the device's LDS per workgroup
     const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
     const int n_items = (int)((p.n_points + 256 * U - 1) / (256 * U));
-    return launch_staged_batched(p, stream, U, lds_slots, nullptr, n_items, nullptr, 0);
+    return launch_staged_batched(p, stream, U, lds_slots, nullptr, n_items, false, 0);
 }
 
 int launch_validate(const Problem &p, unsigned *flags, hipStream_t stream)

@@ -70,7 +70,7 @@ int launch_runs_batched(const Problem &p, hipStream_t stream, int pairs_per_lane
 int staged_max_rings(int pairs_per_lane);
 int staged_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu);
 int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_lane, int max_edges,
-                          const int32_t *order, int n_items, unsigned *queue, int grid);
+                          const int32_t *order, int n_items, bool persistent, int grid);
 
 // ---------------------------------------------------------------- filtered binary32 path
 size_t filtered_smem_bytes(int max_edges, int max_rings);

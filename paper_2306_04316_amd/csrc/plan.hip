@@ -86,9 +86,13 @@ bool phase_empty(const pip_plan *pl, const pip_plan_config &c, int ph)
         return true;
     if (c.index)
         return ph == kRecheck;
-    if (ph == kPrep)   // counters (queue, recheck count) or the item order are needed
-        return !(staged_kind(c) && (c.persistent || c.mode == PIP_MODE_FILTERED_FP32 ||
-                                    (c.order == 1 && pl->p.point_poly)));
+    if (ph == kPrep) {   // needed for the item order, or the counters (queue, recheck count)
+        if (!staged_kind(c))
+            return true;
+        const bool lpt = c.order == 1 && pl->p.point_poly;
+        const bool counters = c.mode == PIP_MODE_FILTERED_FP32 || (c.persistent && c.kernel == PIP_KERNEL_RUNS);
+        return !(lpt || counters);
+    }
     if (ph == kRecheck)
         return c.mode != PIP_MODE_FILTERED_FP32;
     return false;
@@ -121,7 +125,8 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
             return launch_segmented(p, s, c.pairs_per_lane, 256);
         if (c.kernel == PIP_KERNEL_RUNS)
             return launch_runs_batched(p, s, c.pairs_per_lane, order, c.n_items, queue, c.grid);
-        return launch_staged_batched(p, s, c.pairs_per_lane, c.lds_slots, order, c.n_items, queue, c.grid);
+        return launch_staged_batched(p, s, c.pairs_per_lane, c.lds_slots, order, c.n_items, c.persistent != 0,
+                                     c.grid);
     }
     return launch_recheck(p, s, pl->recheck, pl->counters + kRecheckCount, pl->cu_count * 8);
 }
@@ -455,7 +460,9 @@ int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t 
     }
     c.pairs_per_lane = o.pairs_per_lane > 0 ? o.pairs_per_lane : 4;
     c.lds_slots = o.lds_slots > 0 ? std::min(o.lds_slots, 2048) : 256;
-    c.persistent = o.persistent >= 0 ? (o.persistent ? 1 : 0) : (point_poly ? 1 : 0);
+    // one workgroup per item unless asked: the hardware dispatcher already
+    // starts a new workgroup wherever one finishes
+    c.persistent = o.persistent > 0 ? 1 : 0;
     c.order = o.order >= 0 ? (o.order ? 1 : 0) : (point_poly ? 1 : 0);
     c.use_graph = (o.use_graph && !o.timing) ? 1 : 0;
     if (c.pairs_per_lane != 1 && c.pairs_per_lane != 2 && c.pairs_per_lane != 4)
