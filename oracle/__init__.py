@@ -5,8 +5,10 @@ this package.  The GPU library (``paper_2306_04316_amd``) never imports it and
 the two share no code.
 
 ``pip_oracle.c`` holds the definition (paper, Method section, constraint 1 and
-Algorithm 1, with the half-open straddle rule); this module only compiles it
-with gcc (binary64, no contraction, no fast-math) and marshals numpy arrays.
+Algorithm 1, with the half-open straddle rule; constraint 2 and Algorithm 2;
+polygons of several rings as the XOR of their rings' parities); this module
+only compiles it with gcc (binary64, no contraction, no fast-math) and
+marshals numpy arrays.
 """
 from __future__ import annotations
 
@@ -56,6 +58,12 @@ def load(mutant: int = 0) -> ctypes.CDLL:
                       ctypes.c_void_p, ctypes.c_int64,
                       ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    f = lib.pip_oracle_classify_rings
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
     _libs[mutant] = lib
     return lib
 
@@ -90,7 +98,37 @@ def classify(px, py, offsets, vx, vy, point_poly=None, nthreads: int | None = No
     return out
 
 
+def classify_rings(px, py, poly_rings, ring_offsets, vx, vy, point_poly=None, nthreads: int | None = None,
+                   mutant: int = 0, predicate: int = 1) -> np.ndarray:
+    """Polygons of several rings: polygon q owns rings poly_rings[q]..poly_rings[q+1]-1,
+    ring r the vertices ring_offsets[r]..ring_offsets[r+1]-1 (parity XORed over rings)."""
+    px = np.ascontiguousarray(px, dtype=np.float64)
+    py = np.ascontiguousarray(py, dtype=np.float64)
+    poly_rings = np.ascontiguousarray(poly_rings, dtype=np.int64)
+    ring_offsets = np.ascontiguousarray(ring_offsets, dtype=np.int64)
+    vx = np.ascontiguousarray(vx, dtype=np.float64)
+    vy = np.ascontiguousarray(vy, dtype=np.float64)
+    if point_poly is not None:
+        point_poly = np.ascontiguousarray(point_poly, dtype=np.int32)
+    n = px.shape[0]
+    if (py.shape[0] != n or vx.shape[0] != vy.shape[0] or ring_offsets[-1] > vx.shape[0]
+            or poly_rings[-1] > ring_offsets.shape[0] - 1):
+        raise ValueError("inconsistent array sizes")
+    out = np.empty(n, dtype=np.uint8)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    rc = load(mutant).pip_oracle_classify_rings(
+        _ptr(px), _ptr(py), n, _ptr(poly_rings), poly_rings.shape[0] - 1, _ptr(ring_offsets),
+        ring_offsets.shape[0] - 1, _ptr(vx), _ptr(vy), _ptr(point_poly), _ptr(out), int(nthreads), int(predicate))
+    if rc != 0:
+        raise ValueError(f"pip_oracle_classify_rings rejected its arguments (rc={rc})")
+    return out
+
+
 def classify_workload(w, nthreads: int | None = None, mutant: int = 0, predicate: int = 1) -> np.ndarray:
+    if getattr(w, "poly_rings", None) is not None:
+        return classify_rings(w.px, w.py, w.poly_rings, w.offsets, w.vx, w.vy, w.point_poly, nthreads=nthreads,
+                              mutant=mutant, predicate=predicate)
     return classify(w.px, w.py, w.offsets, w.vx, w.vy, w.point_poly, nthreads=nthreads, mutant=mutant,
                     predicate=predicate)
 

@@ -132,7 +132,8 @@ static int ring_parity_c2(double x, double y, const double *vx, const double *vy
 
 typedef struct {
     const double *px, *py;
-    const int64_t *offsets;
+    const int64_t *poly_rings;   /* NULL: ring q is polygon q */
+    const int64_t *offsets;      /* ring vertex ranges */
     const double *vx, *vy;
     const int32_t *point_poly;
     uint8_t *inside;
@@ -140,21 +141,51 @@ typedef struct {
     int predicate;
 } oracle_job;
 
+static int one_ring(const oracle_job *j, double x, double y, int64_t r)
+{
+    int64_t b = j->offsets[r], e = j->offsets[r + 1];
+    return j->predicate == 2 ? ring_parity_c2(x, y, j->vx + b, j->vy + b, e - b)
+                             : ring_parity(x, y, j->vx + b, j->vy + b, e - b);
+}
+
+/*
+ * Polygons made of several rings (holes, or several separate parts): the
+ * even-odd rule counts the crossings of all edges of all rings, each ring
+ * closing on itself and no edge joining two rings, so the parity is the XOR
+ * of the rings' parities.  (An extension beyond the paper, whose polygon is a
+ * single closed ring; on a one-ring polygon it is exactly the rule above.)
+ */
+static int poly_parity(const oracle_job *j, double x, double y, int64_t q)
+{
+    if (!j->poly_rings)
+        return one_ring(j, x, y, q);
+    int64_t r0 = j->poly_rings[q], r1 = j->poly_rings[q + 1];
+#if PIP_ORACLE_MUTANT == 8
+    /* mutant: the polygon's rings walked as one chain (edges joining rings) */
+    if (r1 <= r0)
+        return 0;
+    int64_t b = j->offsets[r0], e = j->offsets[r1];
+    return ring_parity(x, y, j->vx + b, j->vy + b, e - b);
+#else
+    int par = 0;
+    for (int64_t r = r0; r < r1; ++r)
+        par ^= one_ring(j, x, y, r);
+    return par;
+#endif
+}
+
 static void *oracle_worker(void *arg)
 {
     oracle_job *j = (oracle_job *)arg;
     for (int64_t i = j->begin; i < j->end; ++i) {
         int64_t q = j->point_poly ? (int64_t)j->point_poly[i] : 0;
-        int64_t b = j->offsets[q], e = j->offsets[q + 1];
-        j->inside[i] = (uint8_t)(j->predicate == 2
-                                     ? ring_parity_c2(j->px[i], j->py[i], j->vx + b, j->vy + b, e - b)
-                                     : ring_parity(j->px[i], j->py[i], j->vx + b, j->vy + b, e - b));
+        j->inside[i] = (uint8_t)poly_parity(j, j->px[i], j->py[i], q);
     }
     return NULL;
 }
 
 static int classify_impl(const double *px, const double *py, int64_t n_points,
-                         const int64_t *offsets, int64_t n_polys,
+                         const int64_t *poly_rings, const int64_t *offsets, int64_t n_polys,
                          const double *vx, const double *vy,
                          const int32_t *point_poly, uint8_t *inside, int nthreads, int predicate)
 {
@@ -182,6 +213,7 @@ static int classify_impl(const double *px, const double *py, int64_t n_points,
     pthread_t tids[256];
     for (int t = 0; t < nthreads; ++t) {
         jobs[t].px = px; jobs[t].py = py;
+        jobs[t].poly_rings = poly_rings;
         jobs[t].offsets = offsets;
         jobs[t].vx = vx; jobs[t].vy = vy;
         jobs[t].point_poly = point_poly;
@@ -218,7 +250,7 @@ int pip_oracle_classify(const double *px, const double *py, int64_t n_points,
                         const double *vx, const double *vy,
                         const int32_t *point_poly, uint8_t *inside, int nthreads)
 {
-    return classify_impl(px, py, n_points, offsets, n_polys, vx, vy, point_poly, inside, nthreads, 1);
+    return classify_impl(px, py, n_points, NULL, offsets, n_polys, vx, vy, point_poly, inside, nthreads, 1);
 }
 
 /* The same with constraint 2 (parametric intersection; see ring_parity_c2). */
@@ -227,5 +259,25 @@ int pip_oracle_classify_c2(const double *px, const double *py, int64_t n_points,
                            const double *vx, const double *vy,
                            const int32_t *point_poly, uint8_t *inside, int nthreads)
 {
-    return classify_impl(px, py, n_points, offsets, n_polys, vx, vy, point_poly, inside, nthreads, 2);
+    return classify_impl(px, py, n_points, NULL, offsets, n_polys, vx, vy, point_poly, inside, nthreads, 2);
+}
+
+/*
+ * Polygons of several rings (see poly_parity): polygon q owns rings
+ * poly_rings[q] .. poly_rings[q+1]-1 and ring r the vertices
+ * vx/vy[ring_offsets[r] .. ring_offsets[r+1]).  predicate 1 = constraint 1,
+ * 2 = constraint 2.  The index arrays must be monotone CSR arrays.
+ */
+int pip_oracle_classify_rings(const double *px, const double *py, int64_t n_points,
+                              const int64_t *poly_rings, int64_t n_polys,
+                              const int64_t *ring_offsets, int64_t n_rings,
+                              const double *vx, const double *vy,
+                              const int32_t *point_poly, uint8_t *inside, int nthreads, int predicate)
+{
+    if (!poly_rings || n_rings < 0 || (predicate != 1 && predicate != 2))
+        return -1;
+    if (n_polys >= 1 && (poly_rings[0] < 0 || poly_rings[n_polys] > n_rings))
+        return -1;
+    return classify_impl(px, py, n_points, poly_rings, ring_offsets, n_polys, vx, vy, point_poly, inside,
+                         nthreads, predicate);
 }

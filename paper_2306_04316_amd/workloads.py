@@ -20,6 +20,11 @@ not available here, so five synthetic workloads stand in for it:
                  5..50 m) with points on vertices, within 1e-9 m of edges and
                  level with a horizontal edge
 
+and one more for polygons of several rings (country and building shapes
+have holes and detached parts):
+
+     holes       footprints of 2 with courtyard holes and detached parts
+
 Every workload accepts ``scale`` (fraction of polygons / points kept) so the
 same recipe yields the small cases used by parity tests.  All coordinates are
 float64; offsets are int64; the pair index is int32 and sorted by polygon.
@@ -32,7 +37,7 @@ import math
 import numpy as np
 
 __all__ = ["Workload", "make", "CONFIG_NAMES", "star", "footprints", "fractal",
-           "batched", "stress", "subsample"]
+           "batched", "stress", "holes", "subsample"]
 
 CONFIG_NAMES = {1: "star", 2: "footprints", 3: "fractal", 4: "batched", 5: "stress"}
 
@@ -47,6 +52,10 @@ class Workload:
     vy: np.ndarray                 # float64 [V]
     point_poly: np.ndarray | None  # int32 [N] or None (every point vs polygon 0)
     params: dict
+    # polygons of several rings: polygon q owns rings poly_rings[q] .. poly_rings[q+1]-1
+    # and `offsets` is then the ring CSR (ring r = vertices offsets[r] .. offsets[r+1]-1);
+    # None: one ring per polygon, `offsets` is the polygon CSR
+    poly_rings: np.ndarray | None = None
 
     @property
     def n_points(self) -> int:
@@ -54,15 +63,27 @@ class Workload:
 
     @property
     def n_polys(self) -> int:
+        if self.poly_rings is not None:
+            return int(self.poly_rings.shape[0] - 1)
+        return int(self.offsets.shape[0] - 1)
+
+    @property
+    def n_rings(self) -> int:
         return int(self.offsets.shape[0] - 1)
 
     @property
     def n_vertices(self) -> int:
         return int(self.vx.shape[0])
 
+    def poly_vertex_counts(self) -> np.ndarray:
+        """Edges of each polygon (all rings)."""
+        if self.poly_rings is None:
+            return np.diff(self.offsets)
+        return np.diff(self.offsets[self.poly_rings])
+
     def edges_per_pair(self) -> np.ndarray:
-        """Number of edges each pair tests (= the ring's stored vertex count)."""
-        k = np.diff(self.offsets)
+        """Number of edges each pair tests (= the polygon's stored vertex count)."""
+        k = self.poly_vertex_counts()
         if self.point_poly is None:
             return np.full(self.n_points, int(k[0]), dtype=np.int64)
         return k[self.point_poly]
@@ -70,7 +91,7 @@ class Workload:
     @property
     def n_tests(self) -> int:
         """T = sum over pairs of the number of edges tested."""
-        k = np.diff(self.offsets)
+        k = self.poly_vertex_counts()
         if self.point_poly is None:
             return int(k[0]) * self.n_points
         counts = np.bincount(self.point_poly, minlength=self.n_polys)
@@ -78,7 +99,9 @@ class Workload:
 
     def nbytes_algorithmic(self) -> int:
         """Bytes the method must move once: points, pair index, mask, vertices, offsets."""
-        b = 16 * self.n_points + 1 * self.n_points + 16 * self.n_vertices + 8 * (self.n_polys + 1)
+        b = 16 * self.n_points + 1 * self.n_points + 16 * self.n_vertices + 8 * (self.n_rings + 1)
+        if self.poly_rings is not None:
+            b += 8 * (self.n_polys + 1)
         if self.point_poly is not None:
             b += 4 * self.n_points
         return b
@@ -142,6 +165,26 @@ def footprints(seed: int = 0, n_polys: int = 100_000, pts_per_poly: int = 100,
     """
     rng = np.random.default_rng(seed)
     P = max(1, int(round(n_polys * scale)))
+    X, Y, cnt, _, _ = _footprint_local(rng, P, kmax)
+    phi = rng.uniform(0.0, math.pi, P)
+    cxs = rng.uniform(0.0, 2.0, P)
+    cys = rng.uniform(5.0, 7.0, P)
+    cph, sph = np.cos(phi)[:, None], np.sin(phi)[:, None]
+    RX = cxs[:, None] + (X * cph - Y * sph)
+    RY = cys[:, None] + (X * sph + Y * cph)
+    valid = np.arange(kmax)[None, :] < cnt[:, None]
+    vx = RX[valid]
+    vy = RY[valid]
+    off = _csr_from_counts(cnt)
+    npts = np.full(P, int(pts_per_poly), dtype=np.int64)
+    px, py, pp = _points_in_inflated_bbox(rng, off, vx, vy, npts)
+    return Workload("footprints", px, py, off, vx, vy, pp,
+                    dict(config=2, seed=seed, n_polys=P, pts_per_poly=pts_per_poly))
+
+
+def _footprint_local(rng, P, kmax):
+    """Footprint rings in local coordinates (centred, unrotated): X, Y [P, kmax],
+    vertex counts, widths, heights (the draws of `footprints` before placement)."""
     k = np.clip(np.rint(rng.lognormal(math.log(6.0), 0.5, P)), 4, kmax).astype(np.int64)
     is_L = (rng.random(P) < 0.5) & (k >= 6)
     w = np.exp(rng.uniform(math.log(5e-5), math.log(5e-4), P))
@@ -198,21 +241,59 @@ def footprints(seed: int = 0, n_polys: int = 100_000, pts_per_poly: int = 100,
         ny_[r, e + 1] = my
         X[act], Y[act] = nx_, ny_
         cnt[act] += 1
+    return X, Y, cnt, w, h
 
+
+def holes(seed: int = 0, n_polys: int = 100_000, pts_per_poly: int = 100, scale: float = 1.0,
+          p_hole: float = 0.5, p_part: float = 0.2, kmax: int = 32) -> Workload:
+    """Footprints made of several rings: courtyards (holes) and detached parts.
+
+    Each polygon's outer ring is drawn as in `footprints`.  With probability
+    `p_hole` it gets a rectangular hole (clockwise) of half-sizes U[0.04, 0.08]
+    of the width and height, centred at (-0.3 w, -0.3 h) in the footprint's
+    frame (inside both rectangles and L-shapes, whose notch never reaches
+    x < -0.2 w and y < -0.2 h); with probability `p_part` a detached
+    rectangular part (counter-clockwise) of half-sizes U[0.1, 0.2] of w and h
+    centred at (0.8 w, 0).  Rings of a polygon are stored outer, hole, part;
+    points are uniform in the polygon's bbox (all rings) inflated by 20%.
+    """
+    rng = np.random.default_rng(seed)
+    P = max(1, int(round(n_polys * scale)))
+    X, Y, cnt, w, h = _footprint_local(rng, P, kmax)
+    has_hole = rng.random(P) < p_hole
+    ha, hb = rng.uniform(0.04, 0.08, P) * w, rng.uniform(0.04, 0.08, P) * h
+    has_part = rng.random(P) < p_part
+    pa, pb = rng.uniform(0.1, 0.2, P) * w, rng.uniform(0.1, 0.2, P) * h
     phi = rng.uniform(0.0, math.pi, P)
     cxs = rng.uniform(0.0, 2.0, P)
     cys = rng.uniform(5.0, 7.0, P)
+
+    hx0, hy0 = -0.3 * w, -0.3 * h
+    HX = np.stack([hx0 - ha, hx0 - ha, hx0 + ha, hx0 + ha], axis=1)   # clockwise
+    HY = np.stack([hy0 - hb, hy0 + hb, hy0 + hb, hy0 - hb], axis=1)
+    px0 = 0.8 * w
+    QX = np.stack([px0 - pa, px0 + pa, px0 + pa, px0 - pa], axis=1)   # counter-clockwise
+    QY = np.stack([-pb, -pb, pb, pb], axis=1)
+    AX = np.concatenate([X, HX, QX], axis=1)
+    AY = np.concatenate([Y, HY, QY], axis=1)
+    valid = np.concatenate([np.arange(kmax)[None, :] < cnt[:, None],
+                            np.repeat(has_hole[:, None], 4, axis=1),
+                            np.repeat(has_part[:, None], 4, axis=1)], axis=1)
     cph, sph = np.cos(phi)[:, None], np.sin(phi)[:, None]
-    RX = cxs[:, None] + (X * cph - Y * sph)
-    RY = cys[:, None] + (X * sph + Y * cph)
-    valid = cols < cnt[:, None]
+    RX = cxs[:, None] + (AX * cph - AY * sph)
+    RY = cys[:, None] + (AX * sph + AY * cph)
     vx = RX[valid]
     vy = RY[valid]
-    off = _csr_from_counts(cnt)
+    ring_counts = np.stack([cnt, 4 * has_hole, 4 * has_part], axis=1).ravel()
+    ring_counts = ring_counts[ring_counts > 0]
+    ring_off = _csr_from_counts(ring_counts)
+    poly_rings = _csr_from_counts(1 + has_hole.astype(np.int64) + has_part.astype(np.int64))
+    poly_off = _csr_from_counts(cnt + 4 * has_hole + 4 * has_part)
     npts = np.full(P, int(pts_per_poly), dtype=np.int64)
-    px, py, pp = _points_in_inflated_bbox(rng, off, vx, vy, npts)
-    return Workload("footprints", px, py, off, vx, vy, pp,
-                    dict(config=2, seed=seed, n_polys=P, pts_per_poly=pts_per_poly))
+    px, py, pp = _points_in_inflated_bbox(rng, poly_off, vx, vy, npts)
+    return Workload("holes", px, py, ring_off, vx, vy, pp,
+                    dict(seed=seed, n_polys=P, pts_per_poly=pts_per_poly, p_hole=p_hole, p_part=p_part),
+                    poly_rings=poly_rings)
 
 
 # --------------------------------------------------------------------------- 3
@@ -380,4 +461,4 @@ def subsample(w: Workload, idx: np.ndarray) -> Workload:
     """The pairs `idx` of `w` (same polygons), e.g. for sampled oracle checks."""
     pp = None if w.point_poly is None else np.ascontiguousarray(w.point_poly[idx])
     return Workload(w.name + "[sample]", np.ascontiguousarray(w.px[idx]), np.ascontiguousarray(w.py[idx]),
-                    w.offsets, w.vx, w.vy, pp, dict(w.params, sample=int(idx.shape[0])))
+                    w.offsets, w.vx, w.vy, pp, dict(w.params, sample=int(idx.shape[0])), poly_rings=w.poly_rings)
