@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PIP_ABI_VERSION 1
+#define PIP_ABI_VERSION 2
 
 #if defined(__GNUC__) || defined(__clang__)
 #define PIP_API __attribute__((visibility("default")))
@@ -234,6 +234,40 @@ PIP_API int pip_plan_create(pip_plan **out,
                     const double *vx, const double *vy, int64_t n_vertices,
                     const int32_t *point_poly, uint8_t *inside,
                     const pip_options *opts, void *stream);
+
+/*
+ * Polygons of several rings (holes, detached parts) -- an extension beyond
+ * the paper, whose polygon is one closed ring: the even-odd rule is applied
+ * over all edges of all rings of the polygon, each ring closing on itself and
+ * no edge joining two rings, i.e. the parity is the XOR of the rings'
+ * parities (Method section, constraint 1 or 2 per edge as selected).
+ *   poly_rings   [n_polys + 1] int64, device: polygon q owns rings
+ *                poly_rings[q] .. poly_rings[q+1]-1 (poly_rings[0] = 0,
+ *                monotone, poly_rings[n_polys] = n_rings)
+ *   ring_offsets [n_rings + 1] int64, device: ring r owns vertices
+ *                ring_offsets[r] .. ring_offsets[r+1]-1 (a CSR over
+ *                n_vertices, as `offsets` above)
+ * Every other argument, the error behaviour and the ownership rules are those
+ * of pip_classify / pip_plan_create (validate = 1 also checks poly_rings).
+ * Kernels: PIP_KERNEL_AUTO (= staged), PIP_KERNEL_STAGED, PIP_KERNEL_PER_PAIR;
+ * exact mode only; no y-index (PIP_ENOTSUP / PIP_EINVAL otherwise).
+ * poly_rings NULL is PIP_EINVAL.  With one ring per polygon the results are
+ * those of pip_classify on ring_offsets.
+ */
+PIP_API int pip_classify_rings(const double *px, const double *py, int64_t n_points,
+                       const int64_t *poly_rings, int64_t n_polys,
+                       const int64_t *ring_offsets, int64_t n_rings,
+                       const double *vx, const double *vy, int64_t n_vertices,
+                       const int32_t *point_poly, uint8_t *inside,
+                       const pip_options *opts, void *stream);
+
+PIP_API int pip_plan_create_rings(pip_plan **out,
+                          const double *px, const double *py, int64_t n_points,
+                          const int64_t *poly_rings, int64_t n_polys,
+                          const int64_t *ring_offsets, int64_t n_rings,
+                          const double *vx, const double *vy, int64_t n_vertices,
+                          const int32_t *point_poly, uint8_t *inside,
+                          const pip_options *opts, void *stream);
 
 /* Enqueue one execution on `stream` (asynchronous). */
 PIP_API int pip_plan_execute(pip_plan *plan, void *stream);

@@ -17,7 +17,7 @@ import ctypes
 from . import _lib
 from ._lib import PipError  # noqa: F401
 
-__all__ = ["classify", "Plan", "PipError", "abi_version", "probe_copy", "to_device"]
+__all__ = ["classify", "classify_rings", "Plan", "PipError", "abi_version", "probe_copy", "to_device"]
 
 
 def _require(t, dtype, name, numel=None):
@@ -95,18 +95,31 @@ class Plan:
     The tensors must stay alive (and at the same addresses) while the plan exists.
     """
 
-    def __init__(self, px, py, offsets, vx, vy, point_poly=None, *, out=None, stream=None, **opts):
+    def __init__(self, px, py, offsets, vx, vy, point_poly=None, *, out=None, stream=None, poly_rings=None,
+                 **opts):
+        """With `poly_rings` (int64, n_polys+1), polygons have several rings and
+        `offsets` is the ring CSR (pip_plan_create_rings)."""
         import torch
         self._lib = _lib.load()
         self.out = _check_inputs(px, py, offsets, vx, vy, point_poly, out)
-        self._keep = (px, py, offsets, vx, vy, point_poly, self.out)
+        if poly_rings is not None:
+            _require(poly_rings, torch.int64, "poly_rings")
+        self._keep = (px, py, offsets, vx, vy, point_poly, poly_rings, self.out)
         self._opts = options(**opts)
         self.device = px.device
         h = ctypes.c_void_p()
         with torch.cuda.device(px.device):
-            rc = self._lib.pip_plan_create(ctypes.byref(h), _ptr(px), _ptr(py), px.numel(), _ptr(offsets),
-                                           offsets.numel() - 1, _ptr(vx), _ptr(vy), vx.numel(), _ptr(point_poly),
-                                           _ptr(self.out), ctypes.byref(self._opts), _stream_handle(stream))
+            if poly_rings is None:
+                rc = self._lib.pip_plan_create(ctypes.byref(h), _ptr(px), _ptr(py), px.numel(), _ptr(offsets),
+                                               offsets.numel() - 1, _ptr(vx), _ptr(vy), vx.numel(),
+                                               _ptr(point_poly), _ptr(self.out), ctypes.byref(self._opts),
+                                               _stream_handle(stream))
+            else:
+                rc = self._lib.pip_plan_create_rings(ctypes.byref(h), _ptr(px), _ptr(py), px.numel(),
+                                                     _ptr(poly_rings), poly_rings.numel() - 1, _ptr(offsets),
+                                                     offsets.numel() - 1, _ptr(vx), _ptr(vy), vx.numel(),
+                                                     _ptr(point_poly), _ptr(self.out), ctypes.byref(self._opts),
+                                                     _stream_handle(stream))
         _lib.check(rc)
         self._h = h
 
@@ -159,6 +172,24 @@ def classify(px, py, offsets, vx, vy, point_poly=None, *, kernel="auto", validat
     return out
 
 
+def classify_rings(px, py, poly_rings, ring_offsets, vx, vy, point_poly=None, *, kernel="auto", validate=False,
+                   out=None, stream=None, pairs_per_lane=0, lds_slots=0, predicate="side"):
+    """inside[i] for point i against polygon point_poly[i] (or 0) made of the rings
+    poly_rings[q] .. poly_rings[q+1]-1, ring r = vertices ring_offsets[r] .. ring_offsets[r+1]-1."""
+    import torch
+    lib = _lib.load()
+    n = px.numel()
+    out = _check_inputs(px, py, ring_offsets, vx, vy, point_poly, out)
+    _require(poly_rings, torch.int64, "poly_rings")
+    o = options("exact", kernel, validate, pairs_per_lane, 0, lds_slots, predicate=predicate)
+    with torch.cuda.device(px.device):
+        rc = lib.pip_classify_rings(_ptr(px), _ptr(py), n, _ptr(poly_rings), poly_rings.numel() - 1,
+                                    _ptr(ring_offsets), ring_offsets.numel() - 1, _ptr(vx), _ptr(vy), vx.numel(),
+                                    _ptr(point_poly), _ptr(out), ctypes.byref(o), _stream_handle(stream))
+    _lib.check(rc)
+    return out
+
+
 def probe_copy(dst, src, stream=None):
     """Plain streaming copy of src into dst (same byte size, multiple of 16)."""
     nbytes = src.numel() * src.element_size()
@@ -178,4 +209,6 @@ def to_device(w, device="cuda"):
              offsets=torch.from_numpy(w.offsets).to(device), vx=torch.from_numpy(w.vx).to(device),
              vy=torch.from_numpy(w.vy).to(device))
     d["point_poly"] = None if w.point_poly is None else torch.from_numpy(w.point_poly).to(device)
+    if getattr(w, "poly_rings", None) is not None:
+        d["poly_rings"] = torch.from_numpy(w.poly_rings).to(device)
     return d

@@ -56,6 +56,10 @@ _SIGS = {
     "pip_probe_copy": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "pip_plan_create": (ctypes.c_int, [ctypes.POINTER(_VP), _VP, _VP, _I64, _VP, _I64, _VP, _VP, _I64, _VP, _VP,
                                        ctypes.POINTER(pip_options), _VP]),
+    "pip_classify_rings": (ctypes.c_int, [_VP, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _VP, _I64, _VP, _VP,
+                                          ctypes.POINTER(pip_options), _VP]),
+    "pip_plan_create_rings": (ctypes.c_int, [ctypes.POINTER(_VP), _VP, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _VP,
+                                             _I64, _VP, _VP, ctypes.POINTER(pip_options), _VP]),
     "pip_plan_execute": (ctypes.c_int, [_VP, _VP]),
     "pip_plan_stats": (ctypes.c_int, [_VP, ctypes.POINTER(pip_stats)]),
     "pip_plan_timing": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),

@@ -98,6 +98,8 @@ int check_host_args(const Problem &p)
         return fail(PIP_EINVAL, "n_polys exceeds the int32 pair index range");
     if (!p.offsets)
         return fail(PIP_EINVAL, "offsets is NULL");
+    if (p.poly_rings && (p.n_rings < 0 || p.n_rings > INT32_MAX))
+        return fail(PIP_EINVAL, "n_rings=%lld out of range", (long long)p.n_rings);
     if (p.n_vertices > 0 && (!p.vx || !p.vy))
         return fail(PIP_EINVAL, "vx/vy is NULL");
     if (p.n_points > 0 && (!p.px || !p.py || !p.inside))
@@ -152,11 +154,12 @@ int pip_abi_version(void) { return PIP_ABI_VERSION; }
 
 const char *pip_last_error(void) { return g_err; }
 
-int pip_classify(const double *px, const double *py, int64_t n_points, const int64_t *offsets, int64_t n_polys,
-                 const double *vx, const double *vy, int64_t n_vertices, const int32_t *point_poly,
-                 uint8_t *inside, const pip_options *opts, void *stream)
+}  // extern "C"
+
+namespace pip {
+namespace {
+int classify_problem(Problem p, const pip_options *opts, void *stream)
 {
-    clear_error();
     pip_options o;
     pip_options_init(&o);
     if (opts) {
@@ -171,7 +174,6 @@ int pip_classify(const double *px, const double *py, int64_t n_points, const int
         return fail(PIP_EINVAL, "unknown kernel %d", o.kernel);
     if (o.predicate != PIP_PRED_SIDE && o.predicate != PIP_PRED_INTERSECTION)
         return fail(PIP_EINVAL, "unknown predicate %d", o.predicate);
-    Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
     p.pred = o.predicate;
     PIP_TRY(check_host_args(p));
     DeviceInfo *dev = nullptr;
@@ -179,18 +181,46 @@ int pip_classify(const double *px, const double *py, int64_t n_points, const int
     hipStream_t s = (hipStream_t)stream;
     if (o.validate)
         PIP_TRY(validate_on_device(p, dev, s));
-    if (n_points == 0)
+    if (p.n_points == 0)
         return PIP_OK;
     if (o.kernel == PIP_KERNEL_PER_PAIR)
         return launch_per_pair(p, s);
     if (o.kernel == PIP_KERNEL_SEGMENTED)
         return launch_segmented(p, s, o.pairs_per_lane, o.block);
     const int ppl = o.pairs_per_lane > 0 ? o.pairs_per_lane : 4;
-    if (o.kernel == PIP_KERNEL_RUNS || o.kernel == PIP_KERNEL_AUTO) {
+    if (o.kernel == PIP_KERNEL_RUNS || (o.kernel == PIP_KERNEL_AUTO && !p.poly_rings)) {
         const int u = ppl == 1 ? 1 : (ppl == 2 ? 2 : 4);
-        return launch_runs_batched(p, s, u, nullptr, (int)((n_points + 256 * u - 1) / (256 * u)), nullptr, 0);
+        return launch_runs_batched(p, s, u, nullptr, (int)((p.n_points + 256 * u - 1) / (256 * u)), nullptr, 0);
     }
     return launch_staged(p, s, ppl, clamp_lds_slots(o.lds_slots > 0 ? o.lds_slots : 256, false, ppl, dev));
+}
+}  // namespace
+}  // namespace pip
+
+extern "C" {
+
+int pip_classify(const double *px, const double *py, int64_t n_points, const int64_t *offsets, int64_t n_polys,
+                 const double *vx, const double *vy, int64_t n_vertices, const int32_t *point_poly,
+                 uint8_t *inside, const pip_options *opts, void *stream)
+{
+    clear_error();
+    Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
+    p.n_rings = n_polys;
+    return classify_problem(p, opts, stream);
+}
+
+int pip_classify_rings(const double *px, const double *py, int64_t n_points, const int64_t *poly_rings,
+                       int64_t n_polys, const int64_t *ring_offsets, int64_t n_rings, const double *vx,
+                       const double *vy, int64_t n_vertices, const int32_t *point_poly, uint8_t *inside,
+                       const pip_options *opts, void *stream)
+{
+    clear_error();
+    if (!poly_rings)
+        return fail(PIP_EINVAL, "poly_rings is NULL");
+    Problem p{px, py, n_points, ring_offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
+    p.poly_rings = poly_rings;
+    p.n_rings = n_rings;
+    return classify_problem(p, opts, stream);
 }
 
 int pip_probe_copy(void *dst, const void *src, int64_t nbytes, void *stream)

@@ -12,14 +12,14 @@ namespace pip {
 namespace {
 
 // ---------------------------------------------------------------- plain per-pair baseline
-// One lane per pair.  Each lane walks its own polygon's ring with ordinary
-// (per-lane) global loads.  No preprocessing, no data sharing beyond what the
-// caches give.
+// One lane per pair.  Each lane walks its own polygon's ring (or rings) with
+// ordinary (per-lane) global loads.  No preprocessing, no data sharing beyond
+// what the caches give.
 template <int PRED>
 __global__ __launch_bounds__(256) void k_per_pair_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
-    const int64_t *__restrict__ offsets, int64_t n_polys,
-    const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
+    const int64_t *__restrict__ offsets, int64_t n_polys, const int64_t *__restrict__ poly_rings,
+    int64_t n_rings, const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
     const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -27,11 +27,15 @@ __global__ __launch_bounds__(256) void k_per_pair_fp64(
         return;
     int64_t q = point_poly ? (int64_t)point_poly[i] : 0;
     q = ((uint64_t)q < (uint64_t)n_polys) ? q : 0;
-    int64_t b = offsets[q], e = offsets[q + 1];
-    clamp_ring(b, e, nv);
+    int64_t r0, r1;
+    poly_ring_range(poly_rings, n_rings, q, r0, r1);
     const double x = px[i], y = py[i];
     unsigned par = 0;
-    if (e > b) {
+    for (int64_t r = r0; r < r1; ++r) {
+        int64_t b = offsets[r], e = offsets[r + 1];
+        clamp_ring(b, e, nv);
+        if (e <= b)
+            continue;
         double ax = vx[e - 1], ay = vy[e - 1];   // closing edge v_{k-1} -> v_0 first
         bool a_above = ay > y;
         for (int64_t j = b; j < e; ++j) {
@@ -128,7 +132,8 @@ __global__ __launch_bounds__(256) void k_segmented_fp64(
 // A workgroup whose rings do not fit (or whose pairs are not sorted) falls
 // back to the scalar-load group walk.
 struct StagedLds {
-    int *T;
+    int *T;    // ring starts, relative to the range start
+    int *PR;   // polygons of several rings: first ring of each polygon (relative)
     double *Y;
     double *XR;
     double4 *E;
@@ -139,6 +144,8 @@ __device__ __forceinline__ StagedLds staged_lds(unsigned char *smem, int max_edg
     StagedLds L;
     L.T = (int *)smem;
     size_t o = (((size_t)(max_rings + 1) * 4 + 31) & ~(size_t)31);
+    L.PR = (int *)(smem + o);
+    o += (((size_t)(max_rings + 1) * 4 + 31) & ~(size_t)31);
     L.Y = (double *)(smem + o);
     o += (((size_t)max_edges + 64) * 8 + 31) & ~(size_t)31;
     L.XR = (double *)(smem + o);
@@ -164,18 +171,24 @@ __device__ __forceinline__ int staged_ring_of(const int *T, int nr, int e)
     return (T[lo] <= e && e < T[lo + 1]) ? lo : -1;
 }
 
-// Where a work item's rings lie: the polygons of its first and last pair
-// (pairs sorted by polygon) and their vertex range [vb, vb + nv).  `ok` is
-// false when the ids are out of range or not ordered.
+// Where a work item's rings lie: the polygons qf..ql of its first and last
+// pair (pairs sorted by polygon), their rings rf .. rf+nr-1 and the vertex
+// range [vb, vb + nv).  `ok` is false when the ids are out of range or not
+// ordered.  Without a ring index (MR false), ring q is polygon q.
 struct ItemRange {
     int64_t vb;
+    int64_t rf;
     int qf, ql;
+    int nr;
     int nv;
     int ok;
 };
 
-__device__ __forceinline__ ItemRange item_range(int64_t p0, int64_t pairs, int64_t n, const int64_t *__restrict__ offsets,
-                                                int64_t n_polys, int64_t nv, const int32_t *__restrict__ point_poly)
+template <bool MR>
+__device__ __forceinline__ ItemRange item_range(int64_t p0, int64_t pairs, int64_t n,
+                                                const int64_t *__restrict__ offsets, int64_t n_polys,
+                                                const int64_t *__restrict__ poly_rings, int64_t n_rings, int64_t nv,
+                                                const int32_t *__restrict__ point_poly)
 {
     ItemRange R;
     const int64_t plast = (p0 + pairs < n ? p0 + pairs : n) - 1;
@@ -186,26 +199,102 @@ __device__ __forceinline__ ItemRange item_range(int64_t p0, int64_t pairs, int64
         R.ql = point_poly[plast];
     }
     R.ok = (uint32_t)R.qf < (uint64_t)n_polys && (uint32_t)R.ql < (uint64_t)n_polys && R.qf <= R.ql;
-    int64_t vb = 0, ve = 0;
+    int64_t vb = 0, ve = 0, rf = 0, rl = 0;
     if (R.ok) {
-        vb = offsets[R.qf];
-        ve = offsets[R.ql + 1];
+        if (MR) {
+            rf = poly_rings[R.qf];
+            rl = poly_rings[R.ql + 1];
+            rf = rf < 0 ? 0 : (rf > n_rings ? n_rings : rf);
+            rl = rl < rf ? rf : (rl > n_rings ? n_rings : rl);
+        } else {
+            rf = R.qf;
+            rl = (int64_t)R.ql + 1;
+        }
+        vb = offsets[rf];
+        ve = offsets[rl];
         clamp_ring(vb, ve, nv);
     }
     R.vb = vb;
+    R.rf = rf;
+    R.nr = rl - rf > INT32_MAX ? INT32_MAX : (int)(rl - rf);
     R.nv = (int)(ve - vb);   // clamp_ring keeps it within [0, INT32_MAX]
     return R;
+}
+
+// Crossing parity of every lane's point against its staged ring: edges
+// e0 .. e0+k-1 (k = 0: nothing).  Two phases per 32-vertex chunk:
+//   1. straddle pass: above_j = (y_j > p_y) for every vertex (one compare,
+//      exact), shifted into a 32-bit word; straddle bits = above XOR above
+//      shifted by one (half-open rule);
+//   2. side tests only for the lane's straddling edges, one set bit at a time.
+// Returns the lanes with an odd count.  Must be called by the whole wavefront.
+template <int PRED>
+__device__ __forceinline__ uint64_t staged_ring_parity(const StagedLds &L, int e0, int k, double xu, double yu,
+                                                       int max_edges, int y_alloc)
+{
+    const double yq = yu + 0.0;
+    uint64_t par = 0;
+    // anchor: above bit of v_{k-1}
+    uint32_t above_prev = (k > 0 && L.Y[e0 + k - 1] > yu) ? 1u : 0u;
+    for (int c0 = 0; c0 < max_edges; c0 += 32) {
+        if (__builtin_amdgcn_ballot_w64(k > c0) == 0)
+            break;
+        // phase 1: above bits of vertices c0 .. c0+31, first vertex in bit 31
+        uint32_t above = 0;
+        // Lanes whose ring ended read past it (their bits are masked below);
+        // the clamp keeps those reads inside the Y allocation.  A lane still
+        // inside its ring is never clamped: its chunk starts at most at the
+        // last staged vertex, 64 slots before the end.
+        const int ybase = e0 + c0;
+        const double *yr = L.Y + (ybase < y_alloc - 32 ? ybase : y_alloc - 32);
+        int t = 0;
+        for (; t < 32; t += 4) {
+            if (__builtin_amdgcn_ballot_w64(k > c0 + t) == 0)
+                break;
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+                above = shift_in_above(above, yq, yr[t + tt]);
+        }
+        above = t < 32 ? above << (32 - t) : above;
+        uint32_t strad = above ^ ((above >> 1) | (above_prev << 31));
+        const int rem = k - c0;
+        if (rem < 32)
+            strad &= rem <= 0 ? 0u : ~(0xffffffffu >> rem);
+        above_prev = rem >= 32 ? (above & 1u) : above_prev;
+        // phase 2: side tests for this lane's straddling edges only
+        const double4 *er = L.E + e0 + c0;
+        while (strad != 0) {
+            const int j = __builtin_clz(strad);
+            strad ^= 0x80000000u >> j;
+            const double4 rec = er[j];
+            bool cr;
+            if (PRED == kIntersection) {
+                const double lam = (yu - rec.y) / rec.w;
+                const double xn = rec.x + lam * rec.z;
+                cr = xn >= xu;
+            } else {
+                const double t1 = xu - rec.x;
+                const double t2 = yu - rec.y;
+                const double sv = t1 * rec.z + t2 * rec.w;
+                cr = sv <= 0.0;
+            }
+            par ^= __builtin_amdgcn_ballot_w64(cr);
+        }
+    }
+    return par;
 }
 
 // Classify the 256*U pairs starting at p0 (one workgroup, 256 threads).
 // smem: dynamic LDS of staged_smem_bytes(max_edges, max_rings) bytes.
 // Edge records: constraint 1 stores (a_x, a_y, n_x, n_y) with the normal
 // oriented n_x > 0; constraint 2 stores (a_x, a_y, d_x, d_y), d = b - a.
-template <int PRED, int U>
+// MR: polygons of several rings; the lane XORs the parities of its
+// polygon's rings (PR[j] .. PR[j+1]-1 in the staged ring table).
+template <int PRED, int U, bool MR>
 __device__ __forceinline__ void staged_item_fp64(
     int64_t p0, const double *__restrict__ px, const double *__restrict__ py, int64_t n,
-    const int64_t *__restrict__ offsets, int64_t n_polys,
-    const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
+    const int64_t *__restrict__ offsets, int64_t n_polys, const int64_t *__restrict__ poly_rings,
+    int64_t n_rings, const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
     const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
     unsigned char *smem, const ItemRange R)
 {
@@ -222,18 +311,20 @@ __device__ __forceinline__ void staged_item_fp64(
         y[u] = 0.0;
         q[u] = -1;
         if (i < n) {
-            x[u] = px[i];
-            y[u] = py[i];
-            q[u] = point_poly ? point_poly[i] : 0;
+            // read once: streamed past the caches
+            x[u] = __builtin_nontemporal_load(px + i);
+            y[u] = __builtin_nontemporal_load(py + i);
+            q[u] = point_poly ? __builtin_nontemporal_load(point_poly + i) : 0;
         }
     }
 
-    // the workgroup's polygon range (the same for every thread, so `fits` is uniform)
+    // the workgroup's range (the same for every thread, so `fits` is uniform)
     const int qf = R.qf, ql = R.ql;
     const int64_t vb = R.vb, ve = R.vb + R.nv;
-    const int nr = ql - qf + 1;
+    const int np = ql - qf + 1;   // polygons
+    const int nr = R.nr;          // rings
     const int nvr = R.nv;
-    const bool fits = R.ok && nvr <= max_edges && nr <= max_rings;
+    const bool fits = R.ok && nvr <= max_edges && nr <= max_rings && np <= max_rings;
     bool mine_ok = true;
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -242,9 +333,16 @@ __device__ __forceinline__ void staged_item_fp64(
     const StagedLds L = staged_lds(smem, max_edges, max_rings);
     if (fits) {
         for (int r = tid; r <= nr; r += 256) {
-            int64_t o = offsets[qf + r];
+            int64_t o = offsets[R.rf + r];
             o = o < vb ? vb : (o > ve ? ve : o);
             L.T[r] = (int)(o - vb);
+        }
+        if (MR) {
+            for (int j = tid; j <= np; j += 256) {
+                int64_t g = poly_rings[qf + j] - R.rf;
+                g = g < 0 ? 0 : (g > nr ? nr : g);
+                L.PR[j] = (int)g;
+            }
         }
         for (int e = tid; e < nvr; e += 256) {
             L.XR[e] = vx[vb + e];
@@ -279,59 +377,30 @@ __device__ __forceinline__ void staged_item_fp64(
 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int r = (q[u] < 0 ? qf : q[u]) - qf;
-            const int e0 = L.T[r];
-            int k = L.T[r + 1] - e0;
-            k = k < 0 ? 0 : k;
-            const double xu = x[u], yu = y[u];
-            const double yq = yu + 0.0;
+            const int j = (q[u] < 0 ? qf : q[u]) - qf;
             uint64_t par = 0;
-            // anchor: above bit of v_{k-1}
-            uint32_t above_prev = (k > 0 && L.Y[e0 + k - 1] > yu) ? 1u : 0u;
-            for (int c0 = 0; c0 < max_edges; c0 += 32) {
-                if (__builtin_amdgcn_ballot_w64(k > c0) == 0)
-                    break;
-                // phase 1: above bits of vertices c0 .. c0+31, first vertex in bit 31
-                uint32_t above = 0;
-                // Lanes whose ring ended read past it (their bits are masked
-                // below); the clamp keeps those reads inside the Y allocation.
-                // A lane still inside its ring is never clamped: its chunk
-                // starts at most at the last staged vertex, 64 slots before the end.
-                const int ybase = e0 + c0;
-                const double *yr = L.Y + (ybase < y_alloc - 32 ? ybase : y_alloc - 32);
-                int t = 0;
-                for (; t < 32; t += 4) {
-                    if (__builtin_amdgcn_ballot_w64(k > c0 + t) == 0)
+            if (MR) {
+                // the polygon's rings, in step across the wavefront (lanes
+                // whose polygon has fewer rings run the extra steps with k = 0)
+                const int r0 = L.PR[j];
+                int r1 = L.PR[j + 1];
+                r1 = r1 < r0 ? r0 : r1;
+                for (int step = 0;; ++step) {
+                    const int rr = r0 + step;
+                    const bool act = rr < r1;
+                    if (__builtin_amdgcn_ballot_w64(act) == 0)
                         break;
-#pragma unroll
-                    for (int tt = 0; tt < 4; ++tt)
-                        above = shift_in_above(above, yq, yr[t + tt]);
+                    const int rs = act ? rr : 0;
+                    const int e0 = L.T[rs];
+                    int k = act ? L.T[rs + 1] - e0 : 0;
+                    k = k < 0 ? 0 : k;
+                    par ^= staged_ring_parity<PRED>(L, e0, k, x[u], y[u], max_edges, y_alloc);
                 }
-                above = t < 32 ? above << (32 - t) : above;
-                uint32_t strad = above ^ ((above >> 1) | (above_prev << 31));
-                const int rem = k - c0;
-                if (rem < 32)
-                    strad &= rem <= 0 ? 0u : ~(0xffffffffu >> rem);
-                above_prev = rem >= 32 ? (above & 1u) : above_prev;
-                // phase 2: side tests for this lane's straddling edges only
-                const double4 *er = L.E + e0 + c0;
-                while (strad != 0) {
-                    const int j = __builtin_clz(strad);
-                    strad ^= 0x80000000u >> j;
-                    const double4 rec = er[j];
-                    bool cr;
-                    if (PRED == kIntersection) {
-                        const double lam = (yu - rec.y) / rec.w;
-                        const double xn = rec.x + lam * rec.z;
-                        cr = xn >= xu;
-                    } else {
-                        const double t1 = xu - rec.x;
-                        const double t2 = yu - rec.y;
-                        const double sv = t1 * rec.z + t2 * rec.w;
-                        cr = sv <= 0.0;
-                    }
-                    par ^= __builtin_amdgcn_ballot_w64(cr);
-                }
+            } else {
+                const int e0 = L.T[j];
+                int k = L.T[j + 1] - e0;
+                k = k < 0 ? 0 : k;
+                par = staged_ring_parity<PRED>(L, e0, k, x[u], y[u], max_edges, y_alloc);
             }
             const int64_t i = p0 + u * 256 + tid;
             if (i < n)
@@ -340,8 +409,9 @@ __device__ __forceinline__ void staged_item_fp64(
         return;
     }
 
-    // fallback: groups of lanes sharing a polygon, ring streamed through scalar loads
-    group_walk_rows<PRED, U>(p0, x, y, q, n, offsets, n_polys, vx, vy, nv, inside);
+    // fallback: groups of lanes sharing a polygon, rings streamed through scalar loads
+    group_walk_rows<PRED, U>(p0, x, y, q, n, offsets, n_polys, MR ? poly_rings : nullptr, MR ? n_rings : n_polys, vx,
+                             vy, nv, inside);
 }
 
 // The range as wave-uniform values (the table entries below are read from
@@ -352,8 +422,12 @@ __device__ __forceinline__ ItemRange uniform_range(const ItemRange &R)
     const uint64_t vb = (uint64_t)R.vb;
     U.vb = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(vb >> 32)) << 32) |
                      (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)vb));
+    const uint64_t rf = (uint64_t)R.rf;
+    U.rf = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(rf >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)rf));
     U.qf = __builtin_amdgcn_readfirstlane(R.qf);
     U.ql = __builtin_amdgcn_readfirstlane(R.ql);
+    U.nr = __builtin_amdgcn_readfirstlane(R.nr);
     U.nv = __builtin_amdgcn_readfirstlane(R.nv);
     U.ok = __builtin_amdgcn_readfirstlane(R.ok);
     return U;
@@ -373,12 +447,12 @@ __device__ __forceinline__ ItemRange uniform_range(const ItemRange &R)
 // Eight waves per SIMD hide the load latency best; the side-test variants fit
 // that register budget (64 VGPRs) without spilling, the intersection-test
 // variant with its division does not and keeps the compiler's choice.
-template <int PRED, int U>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRED == kSide ? 8 : 1)))
+template <int PRED, int U, bool MR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRED == kSide && !MR ? 8 : 1)))
 void k_staged_batched_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
-    const int64_t *__restrict__ offsets, int64_t n_polys,
-    const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
+    const int64_t *__restrict__ offsets, int64_t n_polys, const int64_t *__restrict__ poly_rings,
+    int64_t n_rings, const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
     const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
     const int32_t *__restrict__ order, int n_items, int persistent)
 {
@@ -387,9 +461,9 @@ void k_staged_batched_fp64(
     if (!persistent) {
         const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
         const int64_t p0 = (int64_t)item * IP;
-        const ItemRange R = item_range(p0, IP, n, offsets, n_polys, nv, point_poly);
-        staged_item_fp64<PRED, U>(p0, px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside, max_edges,
-                                  max_rings, smem, R);
+        const ItemRange R = item_range<MR>(p0, IP, n, offsets, n_polys, poly_rings, n_rings, nv, point_poly);
+        staged_item_fp64<PRED, U, MR>(p0, px, py, n, offsets, n_polys, poly_rings, n_rings, vx, vy, nv, point_poly,
+                                      inside, max_edges, max_rings, smem, R);
         return;
     }
     __shared__ ItemRange s_range[64];
@@ -401,11 +475,11 @@ void k_staged_batched_fp64(
             const int64_t pos = first + (int64_t)threadIdx.x * G;
             int item = -1;
             ItemRange R;
-            R.vb = 0;
-            R.qf = R.ql = R.nv = R.ok = 0;
+            R.vb = R.rf = 0;
+            R.qf = R.ql = R.nr = R.nv = R.ok = 0;
             if (pos < n_items) {
                 item = order ? order[pos] : (int)pos;
-                R = item_range((int64_t)item * IP, IP, n, offsets, n_polys, nv, point_poly);
+                R = item_range<MR>((int64_t)item * IP, IP, n, offsets, n_polys, poly_rings, n_rings, nv, point_poly);
             }
             s_item[threadIdx.x] = item;
             s_range[threadIdx.x] = R;
@@ -415,8 +489,9 @@ void k_staged_batched_fp64(
             const int item = __builtin_amdgcn_readfirstlane(s_item[j]);
             if (item < 0)
                 break;
-            staged_item_fp64<PRED, U>((int64_t)item * IP, px, py, n, offsets, n_polys, vx, vy, nv, point_poly,
-                                      inside, max_edges, max_rings, smem, uniform_range(s_range[j]));
+            staged_item_fp64<PRED, U, MR>((int64_t)item * IP, px, py, n, offsets, n_polys, poly_rings, n_rings, vx,
+                                          vy, nv, point_poly, inside, max_edges, max_rings, smem,
+                                          uniform_range(s_range[j]));
             __syncthreads();   // the next item reuses the staging area
         }
     }
@@ -554,6 +629,22 @@ __global__ __launch_bounds__(256) void k_validate_polys(
         atomicOr(flags, f);
 }
 
+// Ring index of polygons of several rings: a monotone CSR over n_rings rings.
+__global__ __launch_bounds__(256) void k_validate_rings(const int64_t *__restrict__ poly_rings, int64_t n_polys,
+                                                        int64_t n_rings, unsigned *flags)
+{
+    unsigned f = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t q = t0; q < n_polys; q += stride)
+        if (poly_rings[q] > poly_rings[q + 1])
+            f |= VALIDATE_ERANGE;
+    if (t0 == 0 && (poly_rings[0] != 0 || poly_rings[n_polys] != n_rings))
+        f |= VALIDATE_ERANGE;
+    if (f)
+        atomicOr(flags, f);
+}
+
 __global__ void k_clear_word(unsigned *w) { *w = 0u; }
 
 // ---------------------------------------------------------------- HBM calibration copy
@@ -575,11 +666,12 @@ int launch_per_pair(const Problem &p, hipStream_t stream)
 {
     if (p.pred == kIntersection)
         hipLaunchKernelGGL(k_per_pair_fp64<kIntersection>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, stream,
-                           p.px, p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly,
-                           p.inside);
+                           p.px, p.py, p.n_points, p.offsets, p.n_polys, p.poly_rings, p.n_rings, p.vx, p.vy,
+                           p.n_vertices, p.point_poly, p.inside);
     else
         hipLaunchKernelGGL(k_per_pair_fp64<kSide>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, stream, p.px,
-                           p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside);
+                           p.py, p.n_points, p.offsets, p.n_polys, p.poly_rings, p.n_rings, p.vx, p.vy,
+                           p.n_vertices, p.point_poly, p.inside);
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
 }
@@ -612,6 +704,8 @@ static int launch_segmented_p(const Problem &p, hipStream_t stream, int pairs_pe
 
 int launch_segmented(const Problem &p, hipStream_t stream, int pairs_per_lane, int block)
 {
+    if (p.poly_rings)
+        return fail(PIP_ENOTSUP, "the segmented kernel takes one ring per polygon; use the staged or per-pair kernel");
     if (block != 64 && block != 128 && block != 256)
         block = 256;
     return p.pred == kIntersection ? launch_segmented_p<kIntersection>(p, stream, pairs_per_lane, block)
@@ -620,8 +714,8 @@ int launch_segmented(const Problem &p, hipStream_t stream, int pairs_per_lane, i
 
 size_t staged_smem_bytes(int max_edges, int max_rings)
 {
-    // T | Y (with a 64-slot pad) | XR | E, each 32-byte aligned (as staged_lds lays them out)
-    size_t o = (((size_t)(max_rings + 1) * 4 + 31) & ~(size_t)31);
+    // T | PR | Y (with a 64-slot pad) | XR | E, each 32-byte aligned (as staged_lds lays them out)
+    size_t o = 2 * (((size_t)(max_rings + 1) * 4 + 31) & ~(size_t)31);
     o += (((size_t)max_edges + 64) * 8 + 31) & ~(size_t)31;
     o += ((size_t)max_edges * 8 + 31) & ~(size_t)31;
     return o + (size_t)max_edges * 32;
@@ -644,21 +738,30 @@ int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_la
         grid = n_items;
     if (grid <= 0)
         return PIP_OK;
-#define PIP_LAUNCH_S(UU)                                                                                         \
-    if (p.pred == kIntersection)                                                                                 \
-        hipLaunchKernelGGL((k_staged_batched_fp64<kIntersection, UU>), dim3(grid), dim3(256), shmem, stream, p.px, \
-                           p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly,        \
-                           p.inside, max_edges, max_rings, order, n_items, pers);                                  \
-    else                                                                                                         \
-    hipLaunchKernelGGL((k_staged_batched_fp64<kSide, UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,     \
-                       p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside,        \
-                       max_edges, max_rings, order, n_items, pers)
-    if (U == 1)
+#define PIP_LAUNCH_S3(PP, UU, MM)                                                                               \
+    hipLaunchKernelGGL((k_staged_batched_fp64<PP, UU, MM>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,      \
+                       p.n_points, p.offsets, p.n_polys, p.poly_rings, p.n_rings, p.vx, p.vy, p.n_vertices,        \
+                       p.point_poly, p.inside, max_edges, max_rings, order, n_items, pers)
+#define PIP_LAUNCH_S2(PP, UU)                                                                                   \
+    if (p.poly_rings)                                                                                           \
+        PIP_LAUNCH_S3(PP, UU, true);                                                                            \
+    else                                                                                                        \
+        PIP_LAUNCH_S3(PP, UU, false)
+#define PIP_LAUNCH_S(UU)                                                                                        \
+    if (p.pred == kIntersection) {                                                                              \
+        PIP_LAUNCH_S2(kIntersection, UU);                                                                       \
+    } else {                                                                                                    \
+        PIP_LAUNCH_S2(kSide, UU);                                                                               \
+    }
+    if (U == 1) {
         PIP_LAUNCH_S(1);
-    else if (U == 4)
+    } else if (U == 4) {
         PIP_LAUNCH_S(4);
-    else
+    } else {
         PIP_LAUNCH_S(2);
+    }
+#undef PIP_LAUNCH_S3
+#undef PIP_LAUNCH_S2
 #undef PIP_LAUNCH_S
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
@@ -671,11 +774,11 @@ int staged_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu)
     int nb = 0;
     hipError_t e;
     if (U == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 1>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 1, false>, 256, shmem);
     else if (U == 4)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 4>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 4, false>, 256, shmem);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 2>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 2, false>, 256, shmem);
     if (e != hipSuccess)
         return fail(PIP_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
     *blocks_per_cu = nb < 1 ? 1 : nb;
@@ -687,6 +790,8 @@ size_t runs_smem_bytes(int pairs_per_lane) { return runs_lds_bytes(pairs_per_lan
 int launch_runs_batched(const Problem &p, hipStream_t stream, int pairs_per_lane, const int32_t *order,
                         int n_items, unsigned *queue, int grid)
 {
+    if (p.poly_rings)
+        return fail(PIP_ENOTSUP, "the runs kernel takes one ring per polygon; use the staged or per-pair kernel");
     const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
     const size_t shmem = runs_smem_bytes(U);
     if (!queue)
@@ -747,10 +852,17 @@ int launch_validate(const Problem &p, unsigned *flags, hipStream_t stream)
     g = g > 4096 ? 4096 : g;
     hipLaunchKernelGGL(k_validate_points, dim3(g), dim3(256), 0, stream, p.px, p.py, p.n_points, p.point_poly,
                        p.n_polys, flags);
-    unsigned g2 = grid_for(p.n_vertices > p.n_polys ? p.n_vertices : p.n_polys, 256);
+    // offsets is the ring CSR (n_rings + 1 entries; n_rings = n_polys without a ring index)
+    unsigned g2 = grid_for(p.n_vertices > p.n_rings ? p.n_vertices : p.n_rings, 256);
     g2 = g2 < 1 ? 1 : (g2 > 4096 ? 4096 : g2);
-    hipLaunchKernelGGL(k_validate_polys, dim3(g2), dim3(256), 0, stream, p.offsets, p.n_polys, p.vx, p.vy,
+    hipLaunchKernelGGL(k_validate_polys, dim3(g2), dim3(256), 0, stream, p.offsets, p.n_rings, p.vx, p.vy,
                        p.n_vertices, flags);
+    if (p.poly_rings) {
+        unsigned g3 = grid_for(p.n_polys, 256);
+        g3 = g3 < 1 ? 1 : (g3 > 4096 ? 4096 : g3);
+        hipLaunchKernelGGL(k_validate_rings, dim3(g3), dim3(256), 0, stream, p.poly_rings, p.n_polys, p.n_rings,
+                           flags);
+    }
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
 }

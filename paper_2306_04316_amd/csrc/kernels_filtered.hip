@@ -121,9 +121,10 @@ __device__ __forceinline__ void filtered_item(
         y[u] = 0.0;
         q[u] = -1;
         if (i < n) {
-            x[u] = px[i];
-            y[u] = py[i];
-            q[u] = point_poly ? point_poly[i] : 0;
+            // read once: streamed past the caches
+            x[u] = __builtin_nontemporal_load(px + i);
+            y[u] = __builtin_nontemporal_load(py + i);
+            q[u] = point_poly ? __builtin_nontemporal_load(point_poly + i) : 0;
         }
     }
     const int64_t plast = (p0 + 256 * U < n ? p0 + 256 * U : n) - 1;
@@ -149,7 +150,7 @@ __device__ __forceinline__ void filtered_item(
     if (!staged) {
         // Rings too large for the workgroup's LDS (or unsorted pairs): these
         // pairs take the exact binary64 wave-uniform walk instead.
-        group_walk_rows<kSide, U>(p0, x, y, q, n, offsets, n_polys, vx, vy, nv, inside);
+        group_walk_rows<kSide, U>(p0, x, y, q, n, offsets, n_polys, nullptr, n_polys, vx, vy, nv, inside);
         return;
     }
 
@@ -386,6 +387,8 @@ int launch_filtered(const Problem &p, hipStream_t stream, int pairs_per_lane, in
                     int force_recheck, int32_t *recheck, unsigned *recheck_count, const int32_t *order,
                     int n_items, unsigned *queue, int grid)
 {
+    if (p.poly_rings)
+        return fail(PIP_ENOTSUP, "the filtered mode takes one ring per polygon");
     const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
     const int max_rings = 256 * U < 128 ? 256 * U : 128;
     const size_t shmem = filtered_smem_bytes(max_edges, max_rings);
@@ -429,6 +432,8 @@ int filtered_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu)
 
 int launch_recheck(const Problem &p, hipStream_t stream, const int32_t *list, const unsigned *count, int grid)
 {
+    if (p.poly_rings)
+        return fail(PIP_ENOTSUP, "the filtered mode takes one ring per polygon");
     hipLaunchKernelGGL(k_recheck_fp64, dim3(grid), dim3(256), 0, stream, p.px, p.py, p.offsets, p.n_polys, p.vx,
                        p.vy, p.n_vertices, p.point_poly, p.inside, list, count, (int64_t)p.n_points);
     PIP_HIP_TRY(hipGetLastError());

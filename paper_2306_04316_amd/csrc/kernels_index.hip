@@ -222,6 +222,8 @@ IndexLayout index_layout(int64_t n_points, int64_t k)
 
 int launch_index_prep(const Problem &p, hipStream_t s, const IndexLayout &L, unsigned char *ws)
 {
+    if (p.poly_rings)
+        return fail(PIP_ENOTSUP, "the y-index takes one ring");
     // one polygon: its ring is the whole vertex array (offsets = {0, n_vertices})
     const int k = (int)p.n_vertices;
     double2 *b0 = (double2 *)(ws + L.o_b0), *b1 = (double2 *)(ws + L.o_b1), *b2 = (double2 *)(ws + L.o_b2);
@@ -248,6 +250,8 @@ int launch_index_prep(const Problem &p, hipStream_t s, const IndexLayout &L, uns
 
 int launch_runs_indexed(const Problem &p, hipStream_t s, const IndexLayout &L, unsigned char *ws)
 {
+    if (p.poly_rings)
+        return fail(PIP_ENOTSUP, "the y-index takes one ring");
     if (p.n_points <= 0)
         return PIP_OK;
     Tree tr;

@@ -24,7 +24,8 @@ __global__ __launch_bounds__(256) void k_fill_u32(unsigned *p, int n, unsigned v
 }
 
 __device__ __forceinline__ int item_bucket(int it, const int32_t *__restrict__ pp, int64_t n,
-                                           const int64_t *__restrict__ offsets, int64_t n_polys, int item_pairs)
+                                           const int64_t *__restrict__ offsets, int64_t n_polys,
+                                           const int64_t *__restrict__ poly_rings, int64_t n_rings, int item_pairs)
 {
     const int64_t p0 = (int64_t)it * item_pairs;
     const int64_t p1 = (p0 + item_pairs < n ? p0 + item_pairs : n) - 1;
@@ -36,7 +37,14 @@ __device__ __forceinline__ int item_bucket(int it, const int32_t *__restrict__ p
         qa = qb;
         qb = t;
     }
-    int64_t span = offsets[qb + 1] - offsets[qa];
+    int64_t ra = qa, rb = qb + 1;   // the rings of polygons qa..qb
+    if (poly_rings) {
+        ra = poly_rings[qa];
+        rb = poly_rings[qb + 1];
+        ra = ra < 0 ? 0 : (ra > n_rings ? n_rings : ra);
+        rb = rb < ra ? ra : (rb > n_rings ? n_rings : rb);
+    }
+    int64_t span = offsets[rb] - offsets[ra];
     span = span < 1 ? 1 : span;
     const int64_t nr = qb - qa + 1;
     int64_t kavg = span / nr;
@@ -48,6 +56,7 @@ __device__ __forceinline__ int item_bucket(int it, const int32_t *__restrict__ p
 // counters[0..31] histogram, [32..63] scatter cursors (both zeroed first)
 __global__ __launch_bounds__(256) void k_item_hist(const int32_t *__restrict__ pp, int64_t n,
                                                    const int64_t *__restrict__ offsets, int64_t n_polys,
+                                                   const int64_t *__restrict__ poly_rings, int64_t n_rings,
                                                    int item_pairs, int n_items, uint8_t *__restrict__ bucket,
                                                    unsigned *counters)
 {
@@ -56,7 +65,7 @@ __global__ __launch_bounds__(256) void k_item_hist(const int32_t *__restrict__ p
         h[threadIdx.x] = 0;
     __syncthreads();
     for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < n_items; it += gridDim.x * blockDim.x) {
-        const int b = item_bucket(it, pp, n, offsets, n_polys, item_pairs);
+        const int b = item_bucket(it, pp, n, offsets, n_polys, poly_rings, n_rings, item_pairs);
         bucket[it] = (uint8_t)b;
         atomicAdd(&h[b], 1u);
     }
@@ -118,7 +127,7 @@ int launch_item_order(const Problem &p, hipStream_t stream, int item_pairs, int 
     unsigned g = grid_for(n_items, 256);
     g = g > 1024 ? 1024 : g;
     hipLaunchKernelGGL(k_item_hist, dim3(g), dim3(256), 0, stream, p.point_poly, p.n_points, p.offsets, p.n_polys,
-                       item_pairs, n_items, bucket, counters);
+                       p.poly_rings, p.n_rings, item_pairs, n_items, bucket, counters);
     const int chunk = 2048;
     hipLaunchKernelGGL(k_item_scatter, dim3(grid_for(n_items, chunk)), dim3(256), 0, stream, bucket, n_items, chunk,
                        counters, order);

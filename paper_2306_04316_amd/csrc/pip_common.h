@@ -52,6 +52,10 @@ struct Problem {
     const int32_t *point_poly;
     uint8_t *inside;
     int pred = 0;   // pip_predicate
+    // polygons of several rings: polygon q owns rings poly_rings[q] .. poly_rings[q+1]-1
+    // and offsets (n_rings + 1 entries) is the ring CSR; NULL: one ring per polygon
+    const int64_t *poly_rings = nullptr;
+    int64_t n_rings = 0;   // = n_polys when poly_rings is NULL
 };
 
 int check_host_args(const Problem &p);

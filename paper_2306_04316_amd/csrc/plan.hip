@@ -198,9 +198,9 @@ std::string tune_key(const pip_plan *pl)
         return b;
     };
     char buf[160];
-    snprintf(buf, sizeof buf, "gfx950:m%d:k%d:n%d:p%d:v%d:i%d%s", pl->o.mode, pl->o.kernel, lg(pl->p.n_points),
+    snprintf(buf, sizeof buf, "gfx950:m%d:k%d:n%d:p%d:v%d:i%d%s%s", pl->o.mode, pl->o.kernel, lg(pl->p.n_points),
              lg(pl->p.n_polys), lg(pl->p.n_vertices), pl->p.point_poly ? 1 : 0,
-             pl->o.predicate == PIP_PRED_INTERSECTION ? ":c2" : "");
+             pl->o.predicate == PIP_PRED_INTERSECTION ? ":c2" : "", pl->p.poly_rings ? ":rings" : "");
     return buf;
 }
 
@@ -230,7 +230,7 @@ bool cache_lookup(const pip_plan *pl, pip_plan_config &c)
         const bool sane = (kern == PIP_KERNEL_STAGED || kern == PIP_KERNEL_RUNS) && (u == 1 || u == 2 || u == 4) &&
                           l >= 16 && l <= 2048 && (pe == 0 || pe == 1) && (od == 0 || od == 1) &&
                           (gr == 0 || gr == 1) &&
-                          !(pl->o.mode == PIP_MODE_FILTERED_FP32 && kern != PIP_KERNEL_STAGED);
+                          !((pl->o.mode == PIP_MODE_FILTERED_FP32 || pl->p.poly_rings) && kern != PIP_KERNEL_STAGED);
         if (key == k && sane) {
             c.kernel = kern;
             c.pairs_per_lane = u;
@@ -325,7 +325,7 @@ int autotune(pip_plan *pl, hipStream_t s)
     const int lds_opts[] = {128, 256, 512, 1024};
     const int ppl_opts[] = {1, 2, 4};
     std::vector<int> kernels;
-    if (pl->o.mode == PIP_MODE_FILTERED_FP32 || pl->o.kernel == PIP_KERNEL_STAGED)
+    if (pl->o.mode == PIP_MODE_FILTERED_FP32 || pl->o.kernel == PIP_KERNEL_STAGED || pl->p.poly_rings)
         kernels = {PIP_KERNEL_STAGED};
     else if (pl->o.kernel == PIP_KERNEL_RUNS)
         kernels = {PIP_KERNEL_RUNS};
@@ -418,17 +418,28 @@ using namespace pip;
 
 extern "C" {
 
-int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t n_points, const int64_t *offsets,
-                    int64_t n_polys, const double *vx, const double *vy, int64_t n_vertices,
-                    const int32_t *point_poly, uint8_t *inside, const pip_options *opts, void *stream)
+}  // extern "C"
+
+namespace pip {
+namespace {
+int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream)
 {
-    clear_error();
+    const int64_t n_points = p.n_points, n_vertices = p.n_vertices;
+    const int64_t *offsets = p.offsets;
+    const int32_t *point_poly = p.point_poly;
     if (!out)
         return fail(PIP_EINVAL, "out is NULL");
     *out = nullptr;
     pip_options o;
     PIP_TRY(check_options(opts, o));
-    Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
+    if (p.poly_rings) {
+        if (o.mode != PIP_MODE_EXACT_FP64)
+            return fail(PIP_ENOTSUP, "the filtered mode takes one ring per polygon");
+        if (o.index)
+            return fail(PIP_EINVAL, "the y-index takes one ring");
+        if (o.kernel == PIP_KERNEL_SEGMENTED || o.kernel == PIP_KERNEL_RUNS)
+            return fail(PIP_ENOTSUP, "polygons of several rings run on the staged or per-pair kernel");
+    }
     p.pred = o.predicate;
     PIP_TRY(check_host_args(p));
     DeviceInfo *dev = nullptr;
@@ -451,7 +462,7 @@ int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t 
         // rings shared by every pair of a large single polygon stream best through
         // scalar loads; batched small rings best through LDS
         c.kernel = PIP_KERNEL_STAGED;
-        if (o.mode == PIP_MODE_EXACT_FP64 && !point_poly && n_points > 0) {
+        if (o.mode == PIP_MODE_EXACT_FP64 && !point_poly && !p.poly_rings && n_points > 0) {
             int64_t o2[2] = {0, 0};
             if (hipMemcpy(o2, offsets, sizeof o2, hipMemcpyDeviceToHost) == hipSuccess && o2[1] - o2[0] > 512)
                 c.kernel = PIP_KERNEL_RUNS;
@@ -538,6 +549,37 @@ int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t 
     }
     *out = pl;
     return PIP_OK;
+}
+}  // namespace
+}  // namespace pip
+
+extern "C" {
+
+int pip_plan_create(pip_plan **out, const double *px, const double *py, int64_t n_points, const int64_t *offsets,
+                    int64_t n_polys, const double *vx, const double *vy, int64_t n_vertices,
+                    const int32_t *point_poly, uint8_t *inside, const pip_options *opts, void *stream)
+{
+    clear_error();
+    Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
+    p.n_rings = n_polys;
+    return plan_create(out, p, opts, stream);
+}
+
+int pip_plan_create_rings(pip_plan **out, const double *px, const double *py, int64_t n_points,
+                          const int64_t *poly_rings, int64_t n_polys, const int64_t *ring_offsets, int64_t n_rings,
+                          const double *vx, const double *vy, int64_t n_vertices, const int32_t *point_poly,
+                          uint8_t *inside, const pip_options *opts, void *stream)
+{
+    clear_error();
+    if (!poly_rings) {
+        if (out)
+            *out = nullptr;
+        return fail(PIP_EINVAL, "poly_rings is NULL");
+    }
+    Problem p{px, py, n_points, ring_offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
+    p.poly_rings = poly_rings;
+    p.n_rings = n_rings;
+    return plan_create(out, p, opts, stream);
 }
 
 int pip_plan_execute(pip_plan *pl, void *stream)

@@ -27,6 +27,23 @@ __device__ __forceinline__ void clamp_ring(int64_t &b, int64_t &e, int64_t nv)
     e = (e - b > INT32_MAX) ? b + INT32_MAX : e;
 }
 
+// Rings [r0, r1) of polygon q: with a ring index (polygons of several rings),
+// poly_rings[q] .. poly_rings[q+1]-1 clamped to [0, n_rings]; without one,
+// ring q alone (offsets is then the polygon CSR).
+__device__ __forceinline__ void poly_ring_range(const int64_t *__restrict__ poly_rings, int64_t n_rings, int64_t q,
+                                                int64_t &r0, int64_t &r1)
+{
+    if (!poly_rings) {
+        r0 = q;
+        r1 = q + 1;
+        return;
+    }
+    r0 = poly_rings[q];
+    r1 = poly_rings[q + 1];
+    r0 = r0 < 0 ? 0 : (r0 > n_rings ? n_rings : r0);
+    r1 = r1 < r0 ? r0 : (r1 > n_rings ? n_rings : r1);
+}
+
 // Which test decides a straddling edge's crossing (paper, Method section):
 //   kSide: constraint 1, (p - a) . n <= 0 with the normal oriented n_x > 0
 //   kIntersection: constraint 2, lambda = (p_y - a_y) / d_y,
@@ -149,10 +166,13 @@ __device__ __forceinline__ uint64_t ring_parity_compact_uniform(double x, double
 // Rows u of a workgroup item whose rings were not staged: lanes that share a
 // polygon run together (leader = first unfinished lane), each group walking
 // its ring wave-uniformly with compacted side tests.
+// Polygons of several rings XOR their rings' parities (poly_rings as in
+// poly_ring_range; NULL = one ring per polygon).
 template <int PRED, int U>
 __device__ __forceinline__ void group_walk_rows(int64_t p0, const double (&x)[U], const double (&y)[U],
                                                 const int (&q)[U], int64_t n, const int64_t *__restrict__ offsets,
-                                                int64_t n_polys, const double *__restrict__ vx,
+                                                int64_t n_polys, const int64_t *__restrict__ poly_rings,
+                                                int64_t n_rings, const double *__restrict__ vx,
                                                 const double *__restrict__ vy, int64_t nv,
                                                 uint8_t *__restrict__ inside)
 {
@@ -167,10 +187,16 @@ __device__ __forceinline__ void group_walk_rows(int64_t p0, const double (&x)[U]
         while (todo) {
             const int leader = __builtin_ctzll(todo);
             const int qu = __builtin_amdgcn_readlane(qv, leader);
-            int64_t b = offsets[qu], e = offsets[qu + 1];
-            clamp_ring(b, e, nv);
             const uint64_t member = todo & __builtin_amdgcn_ballot_w64(qv == qu);
-            par |= ring_parity_compact_uniform<PRED>(x[u], y[u], (member >> lane) & 1u, vx, vy, b, e) & member;
+            int64_t r0, r1;
+            poly_ring_range(poly_rings, n_rings, qu, r0, r1);
+            uint64_t gp = 0;
+            for (int64_t r = r0; r < r1; ++r) {
+                int64_t b = offsets[r], e = offsets[r + 1];
+                clamp_ring(b, e, nv);
+                gp ^= ring_parity_compact_uniform<PRED>(x[u], y[u], (member >> lane) & 1u, vx, vy, b, e);
+            }
+            par |= gp & member;
             todo &= ~member;
         }
         if (i < n)

@@ -94,6 +94,18 @@ def test_host_argument_errors(lib):
     assert rc == _lib.PIP_EINVAL and b"filtered" in lib.pip_last_error()
     o.predicate = 0
     o.mode = 0
+    # polygons of several rings: the ring index is required
+    rc = lib.pip_classify_rings(dummy, dummy, 10, None, 1, dummy, 1, dummy, dummy, 4, None, dummy,
+                                ctypes.byref(o), None)
+    assert rc == _lib.PIP_EINVAL and b"poly_rings" in lib.pip_last_error()
+    rc = lib.pip_classify_rings(dummy, dummy, 10, dummy, 1, dummy, -1, dummy, dummy, 4, None, dummy,
+                                ctypes.byref(o), None)
+    assert rc == _lib.PIP_EINVAL and b"n_rings" in lib.pip_last_error()
+    o.mode = 1
+    rc = lib.pip_plan_create_rings(ctypes.byref(plan), dummy, dummy, 10, dummy, 1, dummy, 1, dummy, dummy, 4, None,
+                                   dummy, ctypes.byref(o), None)
+    assert rc == _lib.PIP_ENOTSUP
+    o.mode = 0
     # copy probe with a size that is not a multiple of 16
     rc = lib.pip_probe_copy(dummy, dummy, 17, None)
     assert rc == _lib.PIP_EINVAL
