@@ -64,6 +64,10 @@ def load(mutant: int = 0) -> ctypes.CDLL:
                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                   ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    f = lib.pip_oracle_bbox_join
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     _libs[mutant] = lib
     return lib
 
@@ -140,3 +144,31 @@ def classify_one(x: float, y: float, ring_x, ring_y, mutant: int = 0) -> int:
     off = np.array([0, rx.shape[0]], dtype=np.int64)
     return int(classify(np.array([x], dtype=np.float64), np.array([y], dtype=np.float64), off, rx, ry,
                         nthreads=1, mutant=mutant)[0])
+
+
+def bbox_join(px, py, offsets, vx, vy, poly_rings=None, nthreads: int | None = None, mutant: int = 0):
+    """Candidate pairs by closed bounding box: (pair_point int64[M], pair_poly int32[M]),
+    listed by polygon, then by point index."""
+    px = np.ascontiguousarray(px, dtype=np.float64)
+    py = np.ascontiguousarray(py, dtype=np.float64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    vx = np.ascontiguousarray(vx, dtype=np.float64)
+    vy = np.ascontiguousarray(vy, dtype=np.float64)
+    if poly_rings is not None:
+        poly_rings = np.ascontiguousarray(poly_rings, dtype=np.int64)
+        n_polys = poly_rings.shape[0] - 1
+    else:
+        n_polys = offsets.shape[0] - 1
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    counts = np.zeros(max(n_polys, 1), dtype=np.int64)
+    lib = load(mutant)
+    args = (_ptr(px), _ptr(py), px.shape[0], _ptr(poly_rings), n_polys, _ptr(offsets), _ptr(vx), _ptr(vy))
+    if lib.pip_oracle_bbox_join(*args, _ptr(counts), None, int(nthreads)) != 0:
+        raise ValueError("pip_oracle_bbox_join rejected its arguments")
+    counts = counts[:n_polys]
+    pair_point = np.empty(max(int(counts.sum()), 1), dtype=np.int64)
+    if lib.pip_oracle_bbox_join(*args, _ptr(counts), _ptr(pair_point), int(nthreads)) != 0:
+        raise ValueError("pip_oracle_bbox_join rejected its arguments")
+    m = int(counts.sum())
+    return pair_point[:m], np.repeat(np.arange(n_polys, dtype=np.int32), counts)

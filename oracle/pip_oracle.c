@@ -281,3 +281,132 @@ int pip_oracle_classify_rings(const double *px, const double *py, int64_t n_poin
     return classify_impl(px, py, n_points, poly_rings, ring_offsets, n_polys, vx, vy, point_poly, inside,
                          nthreads, predicate);
 }
+
+/*
+ * Candidate pairs by bounding box (the paper's data preparation kept only the
+ * points inside the polygon's bounding box, Simulation section; here for many
+ * polygons at once): pair (i, q) is a candidate when point i lies in the
+ * closed axis-aligned box [min x, max x] x [min y, max y] of polygon q's
+ * vertices (all its rings).  A polygon without vertices has no candidates.
+ * Comparisons only, so the result is exact.  Brute force over all points for
+ * every polygon; pairs are listed by polygon, then by point index.
+ */
+typedef struct {
+    const double *px, *py;
+    int64_t n_points;
+    const int64_t *poly_rings, *offsets;
+    const double *vx, *vy;
+    int64_t q0, q1;
+    int64_t *counts;          /* [n_polys] */
+    const int64_t *starts;    /* [n_polys] or NULL (count pass) */
+    int64_t *pair_point;
+} join_job;
+
+static int poly_bbox(const join_job *j, int64_t q, double *x0, double *x1, double *y0, double *y1)
+{
+    int64_t r0 = j->poly_rings ? j->poly_rings[q] : q;
+    int64_t r1 = j->poly_rings ? j->poly_rings[q + 1] : q + 1;
+    int64_t b = j->offsets[r0], e = j->offsets[r1];
+    if (e <= b)
+        return 0;
+    *x0 = *x1 = j->vx[b];
+    *y0 = *y1 = j->vy[b];
+    for (int64_t v = b + 1; v < e; ++v) {
+        if (j->vx[v] < *x0) *x0 = j->vx[v];
+        if (j->vx[v] > *x1) *x1 = j->vx[v];
+        if (j->vy[v] < *y0) *y0 = j->vy[v];
+        if (j->vy[v] > *y1) *y1 = j->vy[v];
+    }
+    return 1;
+}
+
+static void *join_worker(void *arg)
+{
+    join_job *j = (join_job *)arg;
+    for (int64_t q = j->q0; q < j->q1; ++q) {
+        double x0, x1, y0, y1;
+        int64_t c = 0;
+        if (poly_bbox(j, q, &x0, &x1, &y0, &y1)) {
+            for (int64_t i = 0; i < j->n_points; ++i) {
+                double x = j->px[i], y = j->py[i];
+#if PIP_ORACLE_MUTANT == 9
+                int in = x0 <= x && x < x1 && y0 <= y && y <= y1;   /* mutant: half-open in x */
+#else
+                int in = x0 <= x && x <= x1 && y0 <= y && y <= y1;
+#endif
+                if (in) {
+                    if (j->starts)
+                        j->pair_point[j->starts[q] + c] = i;
+                    ++c;
+                }
+            }
+        }
+        j->counts[q] = c;
+    }
+    return NULL;
+}
+
+static void join_run(join_job *proto, int64_t n_polys, int nthreads)
+{
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    join_job jobs[256];
+    pthread_t tids[256];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = *proto;
+        jobs[t].q0 = n_polys * t / nthreads;
+        jobs[t].q1 = n_polys * (t + 1) / nthreads;
+    }
+    int started = 0;
+    for (int t = 1; t < nthreads; ++t) {
+        if (pthread_create(&tids[t], NULL, join_worker, &jobs[t]) != 0)
+            break;
+        started = t;
+    }
+    join_worker(&jobs[0]);
+    for (int t = 1; t <= started; ++t)
+        pthread_join(tids[t], NULL);
+    for (int t = started + 1; t < nthreads; ++t)
+        join_worker(&jobs[t]);
+}
+
+/*
+ * counts[q] = number of candidate points of polygon q.  If pair_point is not
+ * NULL (capacity = sum of counts), also lists them: polygon 0's points in
+ * ascending index order, then polygon 1's, ...  poly_rings may be NULL (one
+ * ring per polygon; offsets then has n_polys + 1 entries).  Returns 0, or -1
+ * on bad arguments.
+ */
+int pip_oracle_bbox_join(const double *px, const double *py, int64_t n_points,
+                         const int64_t *poly_rings, int64_t n_polys, const int64_t *offsets,
+                         const double *vx, const double *vy, int64_t *counts, int64_t *pair_point,
+                         int nthreads)
+{
+    if (n_points < 0 || n_polys < 0 || !offsets || !counts || (n_points > 0 && (!px || !py)))
+        return -1;
+    join_job proto;
+    proto.px = px; proto.py = py; proto.n_points = n_points;
+    proto.poly_rings = poly_rings; proto.offsets = offsets;
+    proto.vx = vx; proto.vy = vy;
+    proto.counts = counts;
+    proto.starts = NULL;
+    proto.pair_point = NULL;
+    join_run(&proto, n_polys, nthreads);
+    if (!pair_point)
+        return 0;
+    int64_t *starts = (int64_t *)malloc((size_t)(n_polys > 0 ? n_polys : 1) * sizeof(int64_t));
+    if (!starts)
+        return -1;
+    int64_t s = 0;
+    for (int64_t q = 0; q < n_polys; ++q) {
+        starts[q] = s;
+        s += counts[q];
+    }
+    proto.starts = starts;
+    proto.pair_point = pair_point;
+    join_run(&proto, n_polys, nthreads);
+    free(starts);
+    return 0;
+}

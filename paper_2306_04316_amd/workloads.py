@@ -37,7 +37,7 @@ import math
 import numpy as np
 
 __all__ = ["Workload", "make", "CONFIG_NAMES", "star", "footprints", "fractal",
-           "batched", "stress", "holes", "subsample"]
+           "batched", "stress", "holes", "raw_points", "subsample"]
 
 CONFIG_NAMES = {1: "star", 2: "footprints", 3: "fractal", 4: "batched", 5: "stress"}
 
@@ -294,6 +294,14 @@ def holes(seed: int = 0, n_polys: int = 100_000, pts_per_poly: int = 100, scale:
     return Workload("holes", px, py, ring_off, vx, vy, pp,
                     dict(seed=seed, n_polys=P, pts_per_poly=pts_per_poly, p_hole=p_hole, p_part=p_part),
                     poly_rings=poly_rings)
+
+
+def raw_points(w: Workload, seed: int = 1) -> Workload:
+    """The pairs' points of `w` as raw points (shuffled, no pair index) with the
+    same polygons: the input of candidate-pair generation."""
+    perm = np.random.default_rng(seed).permutation(w.n_points)
+    return Workload(w.name + "[raw]", np.ascontiguousarray(w.px[perm]), np.ascontiguousarray(w.py[perm]),
+                    w.offsets, w.vx, w.vy, None, dict(w.params, raw_points=True), poly_rings=w.poly_rings)
 
 
 # --------------------------------------------------------------------------- 3
