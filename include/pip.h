@@ -291,6 +291,45 @@ PIP_API int pip_plan_get_config(const pip_plan *plan, pip_plan_config *cfg);
 PIP_API int pip_plan_destroy(pip_plan *plan);
 
 /*
+ * Candidate pairs by bounding box -- the step before classification (the
+ * paper's data preparation kept the points inside the polygon's bounding box,
+ * Simulation section; here for many polygons at once).  Pair (i, q) is a
+ * candidate when point i lies in the closed box [min x, max x] x [min y, max y]
+ * of polygon q's vertices (all its rings).  Exact (comparisons only).
+ *
+ * pip_join_create: points px/py [n_points] and polygons as for pip_classify
+ * (offsets [n_polys + 1], poly_rings NULL) or pip_classify_rings (poly_rings
+ * [n_polys + 1] and ring offsets [n_rings + 1]); all device pointers, which
+ * must stay valid until pip_join_fill's work has completed.  Builds a grid
+ * over the points, counts the candidates, synchronises `stream` and returns
+ * their number in *n_pairs.  The join owns its workspace (about 40 bytes per
+ * point and per polygon).  n_points and n_polys must be below 2^31.
+ * Finite coordinates are required (non-finite ones give unspecified pairs).
+ * Errors: PIP_EINVAL (NULL or negative arguments), PIP_ENOMEM, PIP_EHIP,
+ * PIP_ENOTSUP (not gfx950).
+ *
+ * pip_join_fill: writes the n_pairs candidates, grouped by polygon in
+ * ascending order (the order the classification kernels want; within a
+ * polygon the order is not specified): pair_point[k] (int64 point index),
+ * pair_poly[k] (int32, usable as point_poly), pair_px/pair_py[k] (the
+ * point's coordinates, usable as px/py).  Device pointers with n_pairs
+ * entries; any of them may be NULL (not written).  Asynchronous on `stream`.
+ */
+typedef struct pip_join pip_join;
+
+PIP_API int pip_join_create(pip_join **out, const double *px, const double *py, int64_t n_points,
+                    const int64_t *poly_rings, int64_t n_polys,
+                    const int64_t *offsets, int64_t n_rings,
+                    const double *vx, const double *vy, int64_t n_vertices,
+                    int64_t *n_pairs, void *stream);
+
+PIP_API int pip_join_fill(pip_join *join, int64_t *pair_point, int32_t *pair_poly,
+                  double *pair_px, double *pair_py, void *stream);
+
+/* Waits for the device, then releases the join's workspace.  NULL is a no-op. */
+PIP_API int pip_join_destroy(pip_join *join);
+
+/*
  * Diagnostic: copy nbytes (a multiple of 16) from src to dst with a plain
  * streaming kernel.  Used to calibrate HBM traffic counters against a
  * kernel of known size.  Asynchronous on `stream`.

@@ -17,7 +17,8 @@ import ctypes
 from . import _lib
 from ._lib import PipError  # noqa: F401
 
-__all__ = ["classify", "classify_rings", "Plan", "PipError", "abi_version", "probe_copy", "to_device"]
+__all__ = ["classify", "classify_rings", "candidate_pairs", "Plan", "PipError", "abi_version", "probe_copy",
+           "to_device"]
 
 
 def _require(t, dtype, name, numel=None):
@@ -187,6 +188,41 @@ def classify_rings(px, py, poly_rings, ring_offsets, vx, vy, point_poly=None, *,
                                     _ptr(ring_offsets), ring_offsets.numel() - 1, _ptr(vx), _ptr(vy), vx.numel(),
                                     _ptr(point_poly), _ptr(out), ctypes.byref(o), _stream_handle(stream))
     _lib.check(rc)
+    return out
+
+
+def candidate_pairs(px, py, offsets, vx, vy, poly_rings=None, *, stream=None):
+    """Candidate pairs by closed bounding box (pip_join_*): a dict of device tensors
+    point (int64), poly (int32), px, py (float64), grouped by polygon in ascending
+    order -- ready to classify as Plan(px, py, offsets, vx, vy, poly, ...)."""
+    import torch
+    lib = _lib.load()
+    _require(px, torch.float64, "px")
+    _require(py, torch.float64, "py", px.numel())
+    _require(offsets, torch.int64, "offsets")
+    _require(vx, torch.float64, "vx")
+    _require(vy, torch.float64, "vy", vx.numel())
+    if poly_rings is not None:
+        _require(poly_rings, torch.int64, "poly_rings")
+        n_polys, n_rings = poly_rings.numel() - 1, offsets.numel() - 1
+    else:
+        n_polys, n_rings = offsets.numel() - 1, offsets.numel() - 1
+    h = ctypes.c_void_p()
+    m = ctypes.c_int64()
+    with torch.cuda.device(px.device):
+        _lib.check(lib.pip_join_create(ctypes.byref(h), _ptr(px), _ptr(py), px.numel(), _ptr(poly_rings), n_polys,
+                                       _ptr(offsets), n_rings, _ptr(vx), _ptr(vy), vx.numel(), ctypes.byref(m),
+                                       _stream_handle(stream)))
+        try:
+            n = int(m.value)
+            out = dict(point=torch.empty(n, dtype=torch.int64, device=px.device),
+                       poly=torch.empty(n, dtype=torch.int32, device=px.device),
+                       px=torch.empty(n, dtype=torch.float64, device=px.device),
+                       py=torch.empty(n, dtype=torch.float64, device=px.device))
+            _lib.check(lib.pip_join_fill(h, _ptr(out["point"]), _ptr(out["poly"]), _ptr(out["px"]), _ptr(out["py"]),
+                                         _stream_handle(stream)))
+        finally:
+            lib.pip_join_destroy(h)
     return out
 
 

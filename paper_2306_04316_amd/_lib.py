@@ -60,6 +60,10 @@ _SIGS = {
                                           ctypes.POINTER(pip_options), _VP]),
     "pip_plan_create_rings": (ctypes.c_int, [ctypes.POINTER(_VP), _VP, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _VP,
                                              _I64, _VP, _VP, ctypes.POINTER(pip_options), _VP]),
+    "pip_join_create": (ctypes.c_int, [ctypes.POINTER(_VP), _VP, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _VP, _I64,
+                                       ctypes.POINTER(ctypes.c_int64), _VP]),
+    "pip_join_fill": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "pip_join_destroy": (ctypes.c_int, [_VP]),
     "pip_plan_execute": (ctypes.c_int, [_VP, _VP]),
     "pip_plan_stats": (ctypes.c_int, [_VP, ctypes.POINTER(pip_stats)]),
     "pip_plan_timing": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
