@@ -93,6 +93,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle timing budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the extension measurements (constraint 2, several rings, candidate pairs, y-index)")
     ap.add_argument("--probe-copy-mb", type=int, default=0,
                     help="run only the HBM calibration copy of this many MiB (for counter scaling)")
     return ap.parse_args()
@@ -155,7 +157,7 @@ class Runner:
 
     def __init__(self, P, copies, plan_opts):
         self.plans = [P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], out=d["out"],
-                             **plan_opts) for d in copies]
+                             poly_rings=d.get("poly_rings"), **plan_opts) for d in copies]
         self.timed = bool(plan_opts.get("timing"))
 
     def run(self, steps, warmup):
@@ -189,6 +191,96 @@ class Runner:
     def close(self):
         for p in self.plans:
             p.close()
+
+
+def extensions(P, W, a, cfg, dev):
+    """Parity and timing of the extensions beyond the hot path, each on its own
+    synthetic workload (two device copies, so the 256 MB last-level cache does not
+    hold a whole step's inputs)."""
+    import torch
+    import oracle
+    out = {}
+    th = host_threads()
+
+    def copies_of(w, n=2):
+        cs = []
+        for _ in range(n):
+            d = P.to_device(w, dev)
+            d["out"] = torch.empty(w.n_points, dtype=torch.uint8, device=dev)
+            cs.append(d)
+        return cs
+
+    def plan_entry(w, cs, opts, want, steps=10):
+        r = Runner(P, cs, dict(opts, timing=True, tune=0))
+        ms, _, ph, _ = r.run(steps, 2)
+        main_ms = float(np.mean(ph[:, 1]))
+        got = cs[(2 + steps - 1) % len(cs)]["out"].cpu().numpy()
+        e = {"ms_per_step_eager": ms, "main_kernel_ms": main_ms, "prep_ms": float(np.mean(ph[:, 0])),
+             "tests_per_s": w.n_tests / (ms * 1e-3), "pairs": w.n_points, "tests": w.n_tests,
+             "hbm_gbs": w.nbytes_algorithmic() / (main_ms * 1e-3) / 1e9, "config": r.plans[0].config()}
+        e["hbm_frac"] = e["hbm_gbs"] / HBM_PEAK_GBS
+        if isinstance(want, tuple):   # sampled
+            idx, ws = want
+            e["parity"] = ("bit-exact (%d sampled pairs)" % idx.size) if np.array_equal(got[idx], ws) else "MISMATCH"
+        else:
+            e["parity"] = "bit-exact (all pairs)" if np.array_equal(got, want) else \
+                "MISMATCH in %d pairs" % int(np.count_nonzero(got != want))
+        r.close()
+        return e
+
+    base = dict(mode="exact", kernel="auto", pairs_per_lane=cfg["pairs_per_lane"], lds_slots=cfg["lds_slots"],
+                persistent=0, order=0, use_graph=False)
+    # constraint 2 (the paper's second crossing test) on the footprints workload
+    progress("extension: constraint-2 predicate")
+    w = W.footprints(seed=a.seed)
+    cs = copies_of(w)
+    out["constraint2_footprints"] = plan_entry(w, cs, dict(base, predicate="intersection"),
+                                               oracle.classify_workload(w, nthreads=th, predicate=2))
+    del cs
+    # polygons of several rings
+    progress("extension: polygons with holes and detached parts")
+    w = W.holes(seed=a.seed)
+    cs = copies_of(w)
+    e = plan_entry(w, cs, dict(base), oracle.classify_workload(w, nthreads=th))
+    e.update(polygons=w.n_polys, rings=w.n_rings)
+    out["rings_holes"] = e
+    del cs
+    # candidate pairs by bounding box (raw points of the footprints workload)
+    progress("extension: candidate pairs by bounding box")
+    w = W.raw_points(W.footprints(seed=a.seed))
+    d = P.to_device(w, dev)
+    times = []
+    for rep in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = P.candidate_pairs(d["px"], d["py"], d["offsets"], d["vx"], d["vy"])
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    m = int(c["point"].numel())
+    idx = np.sort(np.random.default_rng(5).choice(w.n_points, 3000, replace=False))
+    wp, wq = oracle.bbox_join(w.px[idx], w.py[idx], w.offsets, w.vx, w.vy, nthreads=th)
+    gp, gq = c["point"].cpu().numpy(), c["poly"].cpu().numpy()
+    sel = np.isin(gp, idx)
+    order = np.lexsort((gp[sel], gq[sel]))
+    ok = np.array_equal(gq[sel][order], wq) and np.array_equal(gp[sel][order], idx[wp])
+    t = float(np.min(times[1:]))
+    nbytes = 16 * w.n_points + 16 * w.n_vertices + 8 * (w.n_polys + 1) + 28 * m
+    out["candidate_pairs"] = {"ms_wall_incl_host_sync": t * 1e3, "points": w.n_points, "polygons": w.n_polys,
+                              "pairs": m, "points_per_s": w.n_points / t,
+                              "io_gbs": nbytes / t / 1e9,
+                              "parity": "exact pair set (3000 sampled points)" if ok else "MISMATCH"}
+    del c, d
+    # y-index for one large polygon (config 3 shape)
+    progress("extension: y-index on the 10^6-vertex polygon")
+    w = W.make(3, seed=a.seed)
+    cs = copies_of(w, 1)
+    idx = np.sort(np.random.default_rng(1).choice(w.n_points, 2000, replace=False))
+    ws = oracle.classify_workload(W.subsample(w, idx), nthreads=th)
+    e = plan_entry(w, cs, dict(mode="exact", kernel="auto", index=True, use_graph=False), (idx, ws), steps=5)
+    e["note"] = "tests_per_s counts every point-edge test the method defines (the index skips most of them)"
+    out["yindex_fractal"] = e
+    del cs
+    return out
 
 
 def progress(msg: str) -> None:
@@ -310,6 +402,13 @@ def main():
         progress("cpu baseline (oracle)")
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
 
+    ext = None
+    n_copies = len(copies)
+    if not a.no_extensions and a.config == 2:
+        del copies, last, runner, rt
+        torch.cuda.empty_cache()
+        ext = extensions(P, W, a, cfg, dev)
+
     digest = kernel_digest()
     tr = PROFILED_TRAFFIC.get((a.config, a.mode, digest))
     traffic = None if tr is None else tr["fetch_bytes"] + tr["write_bytes"]
@@ -330,7 +429,7 @@ def main():
         "parity": parity,
         "config": {"workload": WORKLOAD_TEXT[a.config], "config_id": a.config, "seed": a.seed, "pairs": N,
                    "polygons": w.n_polys, "vertices": w.n_vertices, "tests": T, "mode": a.mode,
-                   "plan": cfg, "device_copies": len(copies)},
+                   "plan": cfg, "device_copies": n_copies},
         "phases_ms_eager": {"prep": float(np.mean(phase[:, 0])), "main": float(np.mean(phase[:, 1])),
                             "recheck": float(np.mean(phase[:, 2]))},
         "step_ms_events": {"mean": float(np.mean(step_ms)), "min": float(np.min(step_ms))},
@@ -339,6 +438,7 @@ def main():
                      "kernel": "main classification kernel", "kernel_ms": main_ms, "kernel_ms_source": main_src,
                      "alg_bytes_per_launch": alg_bytes, "kernel_digest": digest},
         "compare": compare,
+        "extensions": ext,
         "cpu_baseline": cpu,
         "wall_s_timed": wall,
         "gen_s": t_gen,
