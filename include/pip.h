@@ -150,9 +150,12 @@ typedef struct {
                                bit-exact results (0 disables the bound) */
     const char *tune_cache; /* plans: tuning cache file; NULL = environment variable
                                PIP_TUNE_CACHE, else no cache */
-    int32_t timing;         /* plans: 1 = record device-time events between the
-                               phases of every execution (executions then run
-                               eagerly, not as a graph) */
+    int32_t timing;         /* plans: 1 = record the phase times of every execution
+                               (markers before the preparation and after the
+                               recheck, and the main kernel's own start and end
+                               timestamps); 2 = the main kernel's timestamps only
+                               (no extra commands in the stream).  Timed plans
+                               execute eagerly, not as a graph. */
     int32_t predicate;      /* pip_predicate (the filtered mode supports PIP_PRED_SIDE only) */
     int32_t index;          /* plans, exact mode, one polygon (point_poly NULL):
                                1 = build a y-range tree over the ring's edges and
@@ -277,10 +280,12 @@ PIP_API int pip_plan_execute(pip_plan *plan, void *stream);
 PIP_API int pip_plan_stats(pip_plan *plan, pip_stats *stats);
 
 /*
- * Device time (ms) of the last execution's phases: preparation, main
- * kernel, recheck.  Needs a plan created with timing = 1 (PIP_ENOTSUP
- * otherwise).  Waits only for that execution's end (not for the stream),
- * so it can be called while later work is still queued.
+ * Device time (ms) of the last execution's phases: preparation (from its
+ * start to the main kernel's start), main kernel (its own start and end
+ * timestamps), recheck (to its end).  Needs a plan created with timing = 1,
+ * or timing = 2 (main kernel only; the other two are 0).  PIP_ENOTSUP
+ * otherwise.  Waits only for that execution's end (not for the stream), so it
+ * can be called while later work is still queued.
  */
 PIP_API int pip_plan_timing(pip_plan *plan, float *ms_prep, float *ms_main, float *ms_recheck);
 

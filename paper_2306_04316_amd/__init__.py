@@ -64,7 +64,8 @@ def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block
     o.force_recheck = 1 if force_recheck else 0
     o.bound_scale = float(bound_scale)
     o.tune_cache = tune_cache.encode() if tune_cache else None
-    o.timing = 1 if timing else 0
+    # timing: True/1 = phase times, 2 or "kernel" = the main kernel's own timestamps only
+    o.timing = 2 if (timing == 2 or timing == "kernel") else (1 if timing else 0)
     o.index = 1 if index else 0
     o.predicate = _lib.PREDICATES[predicate] if isinstance(predicate, str) else int(predicate)
     return o

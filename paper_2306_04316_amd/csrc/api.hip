@@ -22,6 +22,12 @@ std::mutex g_dev_mu;
 std::vector<DeviceInfo *> g_devs;
 }  // namespace
 
+KernelTimer &kernel_timer()
+{
+    static thread_local KernelTimer t;
+    return t;
+}
+
 int fail(int code, const char *fmt, ...)
 {
     va_list ap;

@@ -410,8 +410,7 @@ __device__ __forceinline__ void staged_item_fp64(
     }
 
     // fallback: groups of lanes sharing a polygon, rings streamed through scalar loads
-    group_walk_rows<PRED, U>(p0, x, y, q, n, offsets, n_polys, MR ? poly_rings : nullptr, MR ? n_rings : n_polys, vx,
-                             vy, nv, inside);
+    group_walk_rows<PRED, U, MR>(p0, x, y, q, n, offsets, n_polys, poly_rings, n_rings, vx, vy, nv, inside);
 }
 
 // The range as wave-uniform values (the table entries below are read from
@@ -665,11 +664,11 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 int launch_per_pair(const Problem &p, hipStream_t stream)
 {
     if (p.pred == kIntersection)
-        hipLaunchKernelGGL(k_per_pair_fp64<kIntersection>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, stream,
+        PIP_LAUNCH(k_per_pair_fp64<kIntersection>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, stream,
                            p.px, p.py, p.n_points, p.offsets, p.n_polys, p.poly_rings, p.n_rings, p.vx, p.vy,
                            p.n_vertices, p.point_poly, p.inside);
     else
-        hipLaunchKernelGGL(k_per_pair_fp64<kSide>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, stream, p.px,
+        PIP_LAUNCH(k_per_pair_fp64<kSide>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, stream, p.px,
                            p.py, p.n_points, p.offsets, p.n_polys, p.poly_rings, p.n_rings, p.vx, p.vy,
                            p.n_vertices, p.point_poly, p.inside);
     PIP_HIP_TRY(hipGetLastError());
@@ -682,10 +681,10 @@ static int launch_segmented_u(const Problem &p, hipStream_t stream, int block)
     const int64_t per_block = (int64_t)block * U;
     const dim3 grid(grid_for(p.n_points, (int)per_block)), blk(block);
     if (p.point_poly)
-        hipLaunchKernelGGL((k_segmented_fp64<PRED, true, U>), grid, blk, 0, stream, p.px, p.py, p.n_points, p.offsets,
+        PIP_LAUNCH((k_segmented_fp64<PRED, true, U>), grid, blk, 0, stream, p.px, p.py, p.n_points, p.offsets,
                            p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside);
     else
-        hipLaunchKernelGGL((k_segmented_fp64<PRED, false, U>), grid, blk, 0, stream, p.px, p.py, p.n_points,
+        PIP_LAUNCH((k_segmented_fp64<PRED, false, U>), grid, blk, 0, stream, p.px, p.py, p.n_points,
                            p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside);
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
@@ -739,7 +738,7 @@ int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_la
     if (grid <= 0)
         return PIP_OK;
 #define PIP_LAUNCH_S3(PP, UU, MM)                                                                               \
-    hipLaunchKernelGGL((k_staged_batched_fp64<PP, UU, MM>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,      \
+    PIP_LAUNCH((k_staged_batched_fp64<PP, UU, MM>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,      \
                        p.n_points, p.offsets, p.n_polys, p.poly_rings, p.n_rings, p.vx, p.vy, p.n_vertices,        \
                        p.point_poly, p.inside, max_edges, max_rings, order, n_items, pers)
 #define PIP_LAUNCH_S2(PP, UU)                                                                                   \
@@ -800,11 +799,11 @@ int launch_runs_batched(const Problem &p, hipStream_t stream, int pairs_per_lane
         return PIP_OK;
 #define PIP_LAUNCH_R(UU)                                                                                         \
     if (p.pred == kIntersection)                                                                                 \
-        hipLaunchKernelGGL((k_runs_batched_fp64<kIntersection, UU>), dim3(grid), dim3(256), shmem, stream, p.px,  \
+        PIP_LAUNCH((k_runs_batched_fp64<kIntersection, UU>), dim3(grid), dim3(256), shmem, stream, p.px,  \
                            p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly,        \
                            p.inside, order, n_items, queue);                                                       \
     else                                                                                                         \
-    hipLaunchKernelGGL((k_runs_batched_fp64<kSide, UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py, p.n_points, \
+    PIP_LAUNCH((k_runs_batched_fp64<kSide, UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py, p.n_points, \
                        p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside, order, n_items, queue)
     if (U == 1)
         PIP_LAUNCH_R(1);

@@ -397,7 +397,7 @@ int launch_filtered(const Problem &p, hipStream_t stream, int pairs_per_lane, in
     if (grid <= 0)
         return PIP_OK;
 #define PIP_LAUNCH_F(UU)                                                                                         \
-    hipLaunchKernelGGL((k_filtered_fp32<UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py, p.n_points,     \
+    PIP_LAUNCH((k_filtered_fp32<UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py, p.n_points,     \
                        p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside, max_edges,         \
                        max_rings, bound_scale, force_recheck, recheck, recheck_count, order, n_items, queue)
     if (U == 1)

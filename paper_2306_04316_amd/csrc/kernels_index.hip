@@ -262,11 +262,11 @@ int launch_runs_indexed(const Problem &p, hipStream_t s, const IndexLayout &L, u
     tr.n1 = L.n1;
     tr.n2 = L.n2;
     if (p.pred == kIntersection)
-        hipLaunchKernelGGL(k_runs_indexed_fp64<kIntersection>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, s,
+        PIP_LAUNCH(k_runs_indexed_fp64<kIntersection>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, s,
                            (const double2 *)(ws + L.o_spt), (const int32_t *)(ws + L.o_sidx), p.n_points, p.vx,
                            p.vy, (int)p.n_vertices, tr, p.inside);
     else
-        hipLaunchKernelGGL(k_runs_indexed_fp64<kSide>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, s,
+        PIP_LAUNCH(k_runs_indexed_fp64<kSide>, dim3(grid_for(p.n_points, 256)), dim3(256), 0, s,
                            (const double2 *)(ws + L.o_spt), (const int32_t *)(ws + L.o_sidx), p.n_points, p.vx,
                            p.vy, (int)p.n_vertices, tr, p.inside);
     PIP_HIP_TRY(hipGetLastError());

@@ -1,6 +1,7 @@
 // Internal declarations shared by the library's translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -26,6 +27,25 @@ void log_msg(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
         int r_ = (expr);         \
         if (r_ != PIP_OK)        \
             return r_;           \
+    } while (0)
+
+// ---------------------------------------------------------------- kernel timestamps
+// Events that the next main-kernel launch on this thread records with its own
+// dispatch (the start and end of the kernel's execution, the timestamps a
+// profiler reports), set by a timed plan execution around its main phase.
+struct KernelTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+KernelTimer &kernel_timer();
+
+// Launch a main kernel, with the thread's kernel timer when one is set.
+#define PIP_LAUNCH(kernel, grid, block, shmem, stream, ...)                                          \
+    do {                                                                                             \
+        const ::pip::KernelTimer &kt_ = ::pip::kernel_timer();                                       \
+        if (kt_.start)                                                                               \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, kt_.start, kt_.stop, 0u, __VA_ARGS__); \
+        else                                                                                         \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                     \
     } while (0)
 
 // ---------------------------------------------------------------- device facts

@@ -34,7 +34,7 @@ struct pip_plan {
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool executed = false;
-    bool timed = false;   // the last execution recorded the phase events
+    int timed = 0;   // events of the last execution: 0 none, 1 phases, 2 main kernel only
 };
 
 namespace pip {
@@ -133,14 +133,30 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
 
 // Enqueue one eager execution of the step sequence with configuration c,
 // with the plan's phase events when `timed`.
-int enqueue(pip_plan *pl, const pip_plan_config &c, hipStream_t s, bool timed)
+// timed: 0 no events; 1 markers before the preparation (ev[0]) and after the
+// recheck (ev[3]) plus the main kernel's own start and end timestamps (ev[1],
+// ev[2]); 2 the main kernel's timestamps only (no extra commands in the stream).
+int enqueue(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int timed)
 {
-    for (int ph = 0; ph < 3; ++ph) {
+    if (timed == 1)
+        PIP_HIP_TRY(hipEventRecord(pl->ev[0], s));
+    PIP_TRY(enqueue_phase(pl, c, s, kPrep));
+    if (timed && !phase_empty(pl, c, kMain)) {
+        KernelTimer &kt = kernel_timer();
+        kt.start = pl->ev[1];
+        kt.stop = pl->ev[2];
+        const int rc = enqueue_phase(pl, c, s, kMain);
+        kt = KernelTimer{};
+        PIP_TRY(rc);
+    } else {
         if (timed)
-            PIP_HIP_TRY(hipEventRecord(pl->ev[ph], s));
-        PIP_TRY(enqueue_phase(pl, c, s, ph));
+            PIP_HIP_TRY(hipEventRecord(pl->ev[1], s));
+        PIP_TRY(enqueue_phase(pl, c, s, kMain));
+        if (timed)
+            PIP_HIP_TRY(hipEventRecord(pl->ev[2], s));
     }
-    if (timed)
+    PIP_TRY(enqueue_phase(pl, c, s, kRecheck));
+    if (timed == 1)
         PIP_HIP_TRY(hipEventRecord(pl->ev[3], s));
     return PIP_OK;
 }
@@ -168,7 +184,7 @@ int build_graph(pip_plan *pl)
     if (e != hipSuccess) {
         rc = fail(PIP_EHIP, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
     } else {
-        rc = enqueue(pl, pl->cfg, cs, false);
+        rc = enqueue(pl, pl->cfg, cs, 0);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cs, &g);
         if (rc == PIP_OK && e != hipSuccess)
@@ -267,10 +283,10 @@ int time_candidate(pip_plan *pl, pip_plan_config &c, hipStream_t s, int reps, fl
 {
     PIP_TRY(resolve_grid(pl, c));
     std::vector<float> t;
-    PIP_TRY(enqueue(pl, c, s, true));
+    PIP_TRY(enqueue(pl, c, s, 1));
     PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
     for (int r = 0; r < reps; ++r) {
-        PIP_TRY(enqueue(pl, c, s, true));
+        PIP_TRY(enqueue(pl, c, s, 1));
         PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
         float a = 0.f;
         PIP_HIP_TRY(hipEventElapsedTime(&a, pl->ev[0], pl->ev[3]));
@@ -296,12 +312,12 @@ int time_launches(pip_plan *pl, hipStream_t s, int reps, float *ms_out)
         rc = fail(PIP_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
     for (int r = 0; r < 2 && rc == PIP_OK; ++r)
         rc = pl->exec ? (hipGraphLaunch(pl->exec, s) == hipSuccess ? PIP_OK : fail(PIP_EHIP, "graph launch"))
-                      : enqueue(pl, pl->cfg, s, false);
+                      : enqueue(pl, pl->cfg, s, 0);
     if (rc == PIP_OK && hipEventRecord(a, s) != hipSuccess)
         rc = fail(PIP_EHIP, "hipEventRecord failed");
     for (int r = 0; r < reps && rc == PIP_OK; ++r)
         rc = pl->exec ? (hipGraphLaunch(pl->exec, s) == hipSuccess ? PIP_OK : fail(PIP_EHIP, "graph launch"))
-                      : enqueue(pl, pl->cfg, s, false);
+                      : enqueue(pl, pl->cfg, s, 0);
     if (rc == PIP_OK && hipEventRecord(b, s) != hipSuccess)
         rc = fail(PIP_EHIP, "hipEventRecord failed");
     if (rc == PIP_OK && hipEventSynchronize(b) != hipSuccess)
@@ -385,6 +401,19 @@ int autotune(pip_plan *pl, hipStream_t s)
     return PIP_OK;
 }
 
+// Phase times of the last (timed) execution; waits for its last event only.
+int read_timing(pip_plan *pl, float *ms_prep, float *ms_main, float *ms_recheck)
+{
+    *ms_prep = *ms_recheck = 0.f;
+    PIP_HIP_TRY(hipEventSynchronize(pl->ev[pl->timed == 1 ? 3 : 2]));
+    PIP_HIP_TRY(hipEventElapsedTime(ms_main, pl->ev[1], pl->ev[2]));
+    if (pl->timed == 1) {
+        PIP_HIP_TRY(hipEventElapsedTime(ms_prep, pl->ev[0], pl->ev[1]));
+        PIP_HIP_TRY(hipEventElapsedTime(ms_recheck, pl->ev[2], pl->ev[3]));
+    }
+    return PIP_OK;
+}
+
 int check_options(const pip_options *opts, pip_options &o)
 {
     pip_options_init(&o);
@@ -404,6 +433,8 @@ int check_options(const pip_options *opts, pip_options &o)
         return fail(PIP_EINVAL, "bound_scale must be >= 0");
     if (o.index && o.mode != PIP_MODE_EXACT_FP64)
         return fail(PIP_EINVAL, "the y-index runs in the exact mode only");
+    if (o.timing < 0 || o.timing > 2)
+        return fail(PIP_EINVAL, "timing must be 0, 1 or 2");
     if (o.predicate != PIP_PRED_SIDE && o.predicate != PIP_PRED_INTERSECTION)
         return fail(PIP_EINVAL, "unknown predicate %d", o.predicate);
     if (o.predicate != PIP_PRED_SIDE && o.mode != PIP_MODE_EXACT_FP64)
@@ -594,10 +625,10 @@ int pip_plan_execute(pip_plan *pl, void *stream)
     hipStream_t s = (hipStream_t)stream;
     if (pl->exec) {
         PIP_HIP_TRY(hipGraphLaunch(pl->exec, s));
-        pl->timed = false;
+        pl->timed = 0;
     } else {
-        PIP_TRY(enqueue(pl, pl->cfg, s, pl->o.timing != 0));
-        pl->timed = pl->o.timing != 0;
+        PIP_TRY(enqueue(pl, pl->cfg, s, pl->o.timing));
+        pl->timed = pl->o.timing;
     }
     pl->executed = true;
     return PIP_OK;
@@ -612,12 +643,8 @@ int pip_plan_stats(pip_plan *pl, pip_stats *st)
     st->pairs = (uint64_t)pl->p.n_points;
     if (!pl->executed)
         return PIP_OK;
-    if (pl->timed) {
-        PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
-        PIP_HIP_TRY(hipEventElapsedTime(&st->ms_prep, pl->ev[0], pl->ev[1]));
-        PIP_HIP_TRY(hipEventElapsedTime(&st->ms_main, pl->ev[1], pl->ev[2]));
-        PIP_HIP_TRY(hipEventElapsedTime(&st->ms_recheck, pl->ev[2], pl->ev[3]));
-    }
+    if (pl->timed)
+        PIP_TRY(read_timing(pl, &st->ms_prep, &st->ms_main, &st->ms_recheck));
     if (pl->recheck) {
         unsigned cnt = 0;
         PIP_HIP_TRY(hipMemcpy(&cnt, pl->counters + kRecheckCount, sizeof cnt, hipMemcpyDeviceToHost));
@@ -635,12 +662,8 @@ int pip_plan_timing(pip_plan *pl, float *ms_prep, float *ms_main, float *ms_rech
     if (!pl->executed)
         return PIP_OK;
     if (!pl->timed)
-        return fail(PIP_ENOTSUP, "the last execution was not timed (create the plan with timing = 1)");
-    PIP_HIP_TRY(hipEventSynchronize(pl->ev[3]));
-    PIP_HIP_TRY(hipEventElapsedTime(ms_prep, pl->ev[0], pl->ev[1]));
-    PIP_HIP_TRY(hipEventElapsedTime(ms_main, pl->ev[1], pl->ev[2]));
-    PIP_HIP_TRY(hipEventElapsedTime(ms_recheck, pl->ev[2], pl->ev[3]));
-    return PIP_OK;
+        return fail(PIP_ENOTSUP, "the last execution was not timed (create the plan with timing = 1 or 2)");
+    return read_timing(pl, ms_prep, ms_main, ms_recheck);
 }
 
 int pip_plan_get_config(const pip_plan *pl, pip_plan_config *cfg)

@@ -166,9 +166,9 @@ __device__ __forceinline__ uint64_t ring_parity_compact_uniform(double x, double
 // Rows u of a workgroup item whose rings were not staged: lanes that share a
 // polygon run together (leader = first unfinished lane), each group walking
 // its ring wave-uniformly with compacted side tests.
-// Polygons of several rings XOR their rings' parities (poly_rings as in
-// poly_ring_range; NULL = one ring per polygon).
-template <int PRED, int U>
+// Polygons of several rings (MR) XOR their rings' parities (poly_rings as in
+// poly_ring_range); without MR ring q is polygon q.
+template <int PRED, int U, bool MR = false>
 __device__ __forceinline__ void group_walk_rows(int64_t p0, const double (&x)[U], const double (&y)[U],
                                                 const int (&q)[U], int64_t n, const int64_t *__restrict__ offsets,
                                                 int64_t n_polys, const int64_t *__restrict__ poly_rings,
@@ -188,13 +188,19 @@ __device__ __forceinline__ void group_walk_rows(int64_t p0, const double (&x)[U]
             const int leader = __builtin_ctzll(todo);
             const int qu = __builtin_amdgcn_readlane(qv, leader);
             const uint64_t member = todo & __builtin_amdgcn_ballot_w64(qv == qu);
-            int64_t r0, r1;
-            poly_ring_range(poly_rings, n_rings, qu, r0, r1);
             uint64_t gp = 0;
-            for (int64_t r = r0; r < r1; ++r) {
-                int64_t b = offsets[r], e = offsets[r + 1];
+            if (MR) {
+                int64_t r0, r1;
+                poly_ring_range(poly_rings, n_rings, qu, r0, r1);
+                for (int64_t r = r0; r < r1; ++r) {
+                    int64_t b = offsets[r], e = offsets[r + 1];
+                    clamp_ring(b, e, nv);
+                    gp ^= ring_parity_compact_uniform<PRED>(x[u], y[u], (member >> lane) & 1u, vx, vy, b, e);
+                }
+            } else {
+                int64_t b = offsets[qu], e = offsets[qu + 1];
                 clamp_ring(b, e, nv);
-                gp ^= ring_parity_compact_uniform<PRED>(x[u], y[u], (member >> lane) & 1u, vx, vy, b, e);
+                gp = ring_parity_compact_uniform<PRED>(x[u], y[u], (member >> lane) & 1u, vx, vy, b, e);
             }
             par |= gp & member;
             todo &= ~member;
