@@ -446,18 +446,20 @@ __device__ __forceinline__ ItemRange uniform_range(const ItemRange &R)
 // Eight waves per SIMD hide the load latency best; the side-test variants fit
 // that register budget (64 VGPRs) without spilling, the intersection-test
 // variant with its division does not and keeps the compiler's choice.
-template <int PRED, int U, bool MR>
+// The persistent and one-item-per-workgroup forms are separate kernels
+// (PERS), so each is compiled with only its own control flow and registers.
+template <int PRED, int U, bool MR, bool PERS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRED == kSide && !MR ? 8 : 1)))
 void k_staged_batched_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys, const int64_t *__restrict__ poly_rings,
     int64_t n_rings, const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
     const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
-    const int32_t *__restrict__ order, int n_items, int persistent)
+    const int32_t *__restrict__ order, int n_items)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int IP = 256 * U;
-    if (!persistent) {
+    if (!PERS) {
         const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
         const int64_t p0 = (int64_t)item * IP;
         const ItemRange R = item_range<MR>(p0, IP, n, offsets, n_polys, poly_rings, n_rings, nv, point_poly);
@@ -732,15 +734,19 @@ int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_la
     const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
     const int max_rings = staged_max_rings(U);
     const size_t shmem = staged_smem_bytes(max_edges, max_rings);
-    const int pers = persistent ? 1 : 0;
     if (!persistent)
         grid = n_items;
     if (grid <= 0)
         return PIP_OK;
+#define PIP_LAUNCH_S4(PP, UU, MM, PE)                                                                           \
+    PIP_LAUNCH((k_staged_batched_fp64<PP, UU, MM, PE>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,       \
+               p.n_points, p.offsets, p.n_polys, p.poly_rings, p.n_rings, p.vx, p.vy, p.n_vertices, p.point_poly, \
+               p.inside, max_edges, max_rings, order, n_items)
 #define PIP_LAUNCH_S3(PP, UU, MM)                                                                               \
-    PIP_LAUNCH((k_staged_batched_fp64<PP, UU, MM>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,      \
-                       p.n_points, p.offsets, p.n_polys, p.poly_rings, p.n_rings, p.vx, p.vy, p.n_vertices,        \
-                       p.point_poly, p.inside, max_edges, max_rings, order, n_items, pers)
+    if (persistent)                                                                                             \
+        PIP_LAUNCH_S4(PP, UU, MM, true);                                                                        \
+    else                                                                                                        \
+        PIP_LAUNCH_S4(PP, UU, MM, false)
 #define PIP_LAUNCH_S2(PP, UU)                                                                                   \
     if (p.poly_rings)                                                                                           \
         PIP_LAUNCH_S3(PP, UU, true);                                                                            \
@@ -759,6 +765,7 @@ int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_la
     } else {
         PIP_LAUNCH_S(2);
     }
+#undef PIP_LAUNCH_S4
 #undef PIP_LAUNCH_S3
 #undef PIP_LAUNCH_S2
 #undef PIP_LAUNCH_S
@@ -773,11 +780,14 @@ int staged_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu)
     int nb = 0;
     hipError_t e;
     if (U == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 1, false>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 1, false, true>, 256,
+                                                         shmem);
     else if (U == 4)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 4, false>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 4, false, true>, 256,
+                                                         shmem);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 2, false>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 2, false, true>, 256,
+                                                         shmem);
     if (e != hipSuccess)
         return fail(PIP_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
     *blocks_per_cu = nb < 1 ? 1 : nb;
