@@ -228,14 +228,14 @@ __device__ __forceinline__ ItemRange item_range(int64_t p0, int64_t pairs, int64
 //      shifted by one (half-open rule);
 //   2. side tests only for the lane's straddling edges, one set bit at a time.
 // Returns the lanes with an odd count.  Must be called by the whole wavefront.
+// above_prev: the above bit of the vertex before e0 in the ring (for a whole
+// ring, its last vertex).
 template <int PRED>
-__device__ __forceinline__ uint64_t staged_ring_parity(const StagedLds &L, int e0, int k, double xu, double yu,
-                                                       int max_edges, int y_alloc)
+__device__ __forceinline__ uint64_t staged_ring_parity(const StagedLds &L, int e0, int k, uint32_t above_prev,
+                                                       double xu, double yu, int max_edges, int y_alloc)
 {
     const double yq = yu + 0.0;
     uint64_t par = 0;
-    // anchor: above bit of v_{k-1}
-    uint32_t above_prev = (k > 0 && L.Y[e0 + k - 1] > yu) ? 1u : 0u;
     for (int c0 = 0; c0 < max_edges; c0 += 32) {
         if (__builtin_amdgcn_ballot_w64(k > c0) == 0)
             break;
@@ -290,7 +290,10 @@ __device__ __forceinline__ uint64_t staged_ring_parity(const StagedLds &L, int e
 // oriented n_x > 0; constraint 2 stores (a_x, a_y, d_x, d_y), d = b - a.
 // MR: polygons of several rings; the lane XORs the parities of its
 // polygon's rings (PR[j] .. PR[j+1]-1 in the staged ring table).
-template <int PRED, int U, bool MR>
+// Rings larger than the LDS edge budget are walked in tiles (see below);
+// only items with more rings or polygons than the tables hold, or with pairs
+// not sorted by polygon, take the scalar-load group walk.
+template <int PRED, int U, bool MR, bool TILES>
 __device__ __forceinline__ void staged_item_fp64(
     int64_t p0, const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys, const int64_t *__restrict__ poly_rings,
@@ -318,20 +321,22 @@ __device__ __forceinline__ void staged_item_fp64(
         }
     }
 
-    // the workgroup's range (the same for every thread, so `fits` is uniform)
+    // the workgroup's range (the same for every thread, so `tables` and `fits`
+    // are uniform)
     const int qf = R.qf, ql = R.ql;
     const int64_t vb = R.vb, ve = R.vb + R.nv;
     const int np = ql - qf + 1;   // polygons
     const int nr = R.nr;          // rings
     const int nvr = R.nv;
-    const bool fits = R.ok && nvr <= max_edges && nr <= max_rings && np <= max_rings;
+    const bool tables = R.ok && nr <= max_rings && np <= max_rings;
+    const bool fits = tables && nvr <= max_edges;
     bool mine_ok = true;
 #pragma unroll
     for (int u = 0; u < U; ++u)
         mine_ok = mine_ok && (q[u] < 0 || (q[u] >= qf && q[u] <= ql));
 
     const StagedLds L = staged_lds(smem, max_edges, max_rings);
-    if (fits) {
+    if (tables) {
         for (int r = tid; r <= nr; r += 256) {
             int64_t o = offsets[R.rf + r];
             o = o < vb ? vb : (o > ve ? ve : o);
@@ -344,6 +349,8 @@ __device__ __forceinline__ void staged_item_fp64(
                 L.PR[j] = (int)g;
             }
         }
+    }
+    if (fits) {
         for (int e = tid; e < nvr; e += 256) {
             L.XR[e] = vx[vb + e];
             L.Y[e] = vy[vb + e];
@@ -351,60 +358,104 @@ __device__ __forceinline__ void staged_item_fp64(
         if (tid < ypad)
             L.Y[nvr + tid] = 0.0;
     }
-    const bool staged = __syncthreads_and(fits && mine_ok);
+    const bool staged = __syncthreads_and(tables && mine_ok && (TILES || fits));
 
     if (staged) {
-        for (int e = tid; e < nvr; e += 256) {
-            const int r = staged_ring_of(L.T, nr, e);
-            if (r < 0)
-                continue;
-            const int e0 = L.T[r];
-            const int ep = e == e0 ? L.T[r + 1] - 1 : e - 1;
-            const double ax = L.XR[ep], ay = L.Y[ep], bx = L.XR[e], by = L.Y[e];
-            if (PRED == kIntersection) {
-                L.E[e] = make_double4(ax, ay, bx - ax, by - ay);
-            } else {
-                double nx = by - ay;
-                double ny = ax - bx;
-                if (nx < 0.0) {
-                    nx = -nx;
-                    ny = -ny;
+        // The vertex range in tiles of S = max_edges vertices: one tile when it
+        // fits (staged above with coalesced loads), else the workgroup walks it
+        // tile by tile.  Per tile: the edge records of the edges ending in the
+        // tile (and, for a tiled range, their y values, with endpoints read
+        // from global memory, cached by the previous tile's loads); then every
+        // lane runs the straddle pass and side tests over the part of its
+        // ring(s) inside the tile, starting from the above bit of the part's
+        // predecessor in the ring, and accumulates its parity across tiles.
+        const int S = max_edges;
+        uint32_t mine = 0;   // bit u: this lane's parity for row u
+        for (int t0 = 0; t0 < nvr; t0 += S) {
+            const int t1 = (!TILES || nvr - t0 < S) ? nvr : t0 + S;
+            for (int e = t0 + tid; e < t1; e += 256) {
+                const int r = staged_ring_of(L.T, nr, e);
+                if (r < 0)
+                    continue;
+                const int e0 = L.T[r];
+                const int ep = e == e0 ? L.T[r + 1] - 1 : e - 1;
+                double ax, ay, bx, by;
+                if (!TILES || fits) {
+                    ax = L.XR[ep];
+                    ay = L.Y[ep];
+                    bx = L.XR[e];
+                    by = L.Y[e];
+                } else {
+                    ax = vx[vb + ep];
+                    ay = vy[vb + ep];
+                    bx = vx[vb + e];
+                    by = vy[vb + e];
                 }
-                L.E[e] = make_double4(ax, ay, nx, ny);
+                if (PRED == kIntersection) {
+                    L.E[e - t0] = make_double4(ax, ay, bx - ax, by - ay);
+                } else {
+                    double nx = by - ay;
+                    double ny = ax - bx;
+                    if (nx < 0.0) {
+                        nx = -nx;
+                        ny = -ny;
+                    }
+                    L.E[e - t0] = make_double4(ax, ay, nx, ny);
+                }
+                if (TILES && !fits)
+                    L.Y[e - t0] = by;
             }
-        }
-        __syncthreads();
+            if (TILES && !fits && tid < ypad)
+                L.Y[(t1 - t0) + tid] = 0.0;
+            __syncthreads();
 
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = (q[u] < 0 ? qf : q[u]) - qf;
-            uint64_t par = 0;
-            if (MR) {
+            for (int u = 0; u < U; ++u) {
+                const int j = (q[u] < 0 ? qf : q[u]) - qf;
                 // the polygon's rings, in step across the wavefront (lanes
                 // whose polygon has fewer rings run the extra steps with k = 0)
-                const int r0 = L.PR[j];
-                int r1 = L.PR[j + 1];
-                r1 = r1 < r0 ? r0 : r1;
+                int r0 = j, r1 = j + 1;
+                if (MR) {
+                    r0 = L.PR[j];
+                    r1 = L.PR[j + 1];
+                    r1 = r1 < r0 ? r0 : r1;
+                }
+                uint64_t par = 0;
                 for (int step = 0;; ++step) {
                     const int rr = r0 + step;
                     const bool act = rr < r1;
-                    if (__builtin_amdgcn_ballot_w64(act) == 0)
+                    if (MR && __builtin_amdgcn_ballot_w64(act) == 0)
                         break;
                     const int rs = act ? rr : 0;
-                    const int e0 = L.T[rs];
-                    int k = act ? L.T[rs + 1] - e0 : 0;
-                    k = k < 0 ? 0 : k;
-                    par ^= staged_ring_parity<PRED>(L, e0, k, x[u], y[u], max_edges, y_alloc);
+                    const int e0 = L.T[rs], e1 = L.T[rs + 1];
+                    // the ring's part in this tile: [a, b)
+                    const int a = (TILES && e0 < t0) ? t0 : e0;
+                    const int b = (TILES && e1 > t1) ? t1 : e1;
+                    const int k = act && b > a ? b - a : 0;
+                    uint32_t prev = 0;
+                    if (k > 0) {
+                        const int pred = a == e0 ? e1 - 1 : a - 1;
+                        double yp;
+                        if (TILES && !(pred >= t0 && pred < t1))
+                            yp = vy[vb + pred];
+                        else
+                            yp = L.Y[pred - t0];
+                        prev = yp > y[u] ? 1u : 0u;
+                    }
+                    par ^= staged_ring_parity<PRED>(L, a - t0, k, prev, x[u], y[u], S, y_alloc);
+                    if (!MR)
+                        break;
                 }
-            } else {
-                const int e0 = L.T[j];
-                int k = L.T[j + 1] - e0;
-                k = k < 0 ? 0 : k;
-                par = staged_ring_parity<PRED>(L, e0, k, x[u], y[u], max_edges, y_alloc);
+                mine ^= (uint32_t)((par >> lane) & 1u) << u;
             }
+            if (TILES && t1 < nvr)
+                __syncthreads();   // the next tile overwrites Y and E
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
             const int64_t i = p0 + u * 256 + tid;
             if (i < n)
-                inside[i] = (uint8_t)((par >> lane) & 1u);
+                inside[i] = (uint8_t)((mine >> u) & 1u);
         }
         return;
     }
@@ -447,8 +498,10 @@ __device__ __forceinline__ ItemRange uniform_range(const ItemRange &R)
 // that register budget (64 VGPRs) without spilling, the intersection-test
 // variant with its division does not and keeps the compiler's choice.
 // The persistent and one-item-per-workgroup forms are separate kernels
-// (PERS), so each is compiled with only its own control flow and registers.
-template <int PRED, int U, bool MR, bool PERS>
+// (PERS), so each is compiled with only its own control flow and registers;
+// so are the forms with and without the tile walk for rings larger than the
+// LDS budget (TILES; without it such items take the scalar-load group walk).
+template <int PRED, int U, bool MR, bool PERS, bool TILES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRED == kSide && !MR ? 8 : 1)))
 void k_staged_batched_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
@@ -463,7 +516,8 @@ void k_staged_batched_fp64(
         const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
         const int64_t p0 = (int64_t)item * IP;
         const ItemRange R = item_range<MR>(p0, IP, n, offsets, n_polys, poly_rings, n_rings, nv, point_poly);
-        staged_item_fp64<PRED, U, MR>(p0, px, py, n, offsets, n_polys, poly_rings, n_rings, vx, vy, nv, point_poly,
+        staged_item_fp64<PRED, U, MR, TILES>(p0, px, py, n, offsets, n_polys, poly_rings, n_rings, vx, vy, nv,
+                                             point_poly,
                                       inside, max_edges, max_rings, smem, R);
         return;
     }
@@ -490,7 +544,7 @@ void k_staged_batched_fp64(
             const int item = __builtin_amdgcn_readfirstlane(s_item[j]);
             if (item < 0)
                 break;
-            staged_item_fp64<PRED, U, MR>((int64_t)item * IP, px, py, n, offsets, n_polys, poly_rings, n_rings, vx,
+            staged_item_fp64<PRED, U, MR, TILES>((int64_t)item * IP, px, py, n, offsets, n_polys, poly_rings, n_rings, vx,
                                           vy, nv, point_poly, inside, max_edges, max_rings, smem,
                                           uniform_range(s_range[j]));
             __syncthreads();   // the next item reuses the staging area
@@ -728,8 +782,40 @@ int staged_max_rings(int pairs_per_lane)
     return 256 * u < 128 ? 256 * u : 128;
 }
 
+template <int PRED, int U, bool MR, bool PERS, bool TILES>
+static void staged_launch_one(const Problem &p, hipStream_t stream, int grid, size_t shmem, int max_edges,
+                              int max_rings, const int32_t *order, int n_items)
+{
+    PIP_LAUNCH((k_staged_batched_fp64<PRED, U, MR, PERS, TILES>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,
+               p.n_points, p.offsets, p.n_polys, p.poly_rings, p.n_rings, p.vx, p.vy, p.n_vertices, p.point_poly,
+               p.inside, max_edges, max_rings, order, n_items);
+}
+
+template <int U>
+static void staged_dispatch(const Problem &p, hipStream_t stream, int grid, size_t shmem, int max_edges,
+                            int max_rings, const int32_t *order, int n_items, bool persistent, bool tiles)
+{
+    using F = void (*)(const Problem &, hipStream_t, int, size_t, int, int, const int32_t *, int);
+    // [predicate][several rings][persistent][tiles]
+    static const F table[2][2][2][2] = {
+        {{{staged_launch_one<kSide, U, false, false, false>, staged_launch_one<kSide, U, false, false, true>},
+          {staged_launch_one<kSide, U, false, true, false>, staged_launch_one<kSide, U, false, true, true>}},
+         {{staged_launch_one<kSide, U, true, false, false>, staged_launch_one<kSide, U, true, false, true>},
+          {staged_launch_one<kSide, U, true, true, false>, staged_launch_one<kSide, U, true, true, true>}}},
+        {{{staged_launch_one<kIntersection, U, false, false, false>,
+           staged_launch_one<kIntersection, U, false, false, true>},
+          {staged_launch_one<kIntersection, U, false, true, false>,
+           staged_launch_one<kIntersection, U, false, true, true>}},
+         {{staged_launch_one<kIntersection, U, true, false, false>,
+           staged_launch_one<kIntersection, U, true, false, true>},
+          {staged_launch_one<kIntersection, U, true, true, false>,
+           staged_launch_one<kIntersection, U, true, true, true>}}}};
+    table[p.pred == kIntersection ? 1 : 0][p.poly_rings ? 1 : 0][persistent ? 1 : 0][tiles ? 1 : 0](
+        p, stream, grid, shmem, max_edges, max_rings, order, n_items);
+}
+
 int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_lane, int max_edges,
-                          const int32_t *order, int n_items, bool persistent, int grid)
+                          const int32_t *order, int n_items, bool persistent, bool tiles, int grid)
 {
     const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
     const int max_rings = staged_max_rings(U);
@@ -738,37 +824,12 @@ int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_la
         grid = n_items;
     if (grid <= 0)
         return PIP_OK;
-#define PIP_LAUNCH_S4(PP, UU, MM, PE)                                                                           \
-    PIP_LAUNCH((k_staged_batched_fp64<PP, UU, MM, PE>), dim3(grid), dim3(256), shmem, stream, p.px, p.py,       \
-               p.n_points, p.offsets, p.n_polys, p.poly_rings, p.n_rings, p.vx, p.vy, p.n_vertices, p.point_poly, \
-               p.inside, max_edges, max_rings, order, n_items)
-#define PIP_LAUNCH_S3(PP, UU, MM)                                                                               \
-    if (persistent)                                                                                             \
-        PIP_LAUNCH_S4(PP, UU, MM, true);                                                                        \
-    else                                                                                                        \
-        PIP_LAUNCH_S4(PP, UU, MM, false)
-#define PIP_LAUNCH_S2(PP, UU)                                                                                   \
-    if (p.poly_rings)                                                                                           \
-        PIP_LAUNCH_S3(PP, UU, true);                                                                            \
-    else                                                                                                        \
-        PIP_LAUNCH_S3(PP, UU, false)
-#define PIP_LAUNCH_S(UU)                                                                                        \
-    if (p.pred == kIntersection) {                                                                              \
-        PIP_LAUNCH_S2(kIntersection, UU);                                                                       \
-    } else {                                                                                                    \
-        PIP_LAUNCH_S2(kSide, UU);                                                                               \
-    }
-    if (U == 1) {
-        PIP_LAUNCH_S(1);
-    } else if (U == 4) {
-        PIP_LAUNCH_S(4);
-    } else {
-        PIP_LAUNCH_S(2);
-    }
-#undef PIP_LAUNCH_S4
-#undef PIP_LAUNCH_S3
-#undef PIP_LAUNCH_S2
-#undef PIP_LAUNCH_S
+    if (U == 1)
+        staged_dispatch<1>(p, stream, grid, shmem, max_edges, max_rings, order, n_items, persistent, tiles);
+    else if (U == 4)
+        staged_dispatch<4>(p, stream, grid, shmem, max_edges, max_rings, order, n_items, persistent, tiles);
+    else
+        staged_dispatch<2>(p, stream, grid, shmem, max_edges, max_rings, order, n_items, persistent, tiles);
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
 }
@@ -780,13 +841,13 @@ int staged_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu)
     int nb = 0;
     hipError_t e;
     if (U == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 1, false, true>, 256,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 1, false, true, false>, 256,
                                                          shmem);
     else if (U == 4)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 4, false, true>, 256,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 4, false, true, false>, 256,
                                                          shmem);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 2, false, true>, 256,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_staged_batched_fp64<kSide, 2, false, true, false>, 256,
                                                          shmem);
     if (e != hipSuccess)
         return fail(PIP_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
@@ -850,7 +911,7 @@ int launch_staged(const Problem &p, hipStream_t stream, int pairs_per_lane, int 
     // clamped to the device's LDS per workgroup
     const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
     const int n_items = (int)((p.n_points + 256 * U - 1) / (256 * U));
-    return launch_staged_batched(p, stream, U, lds_slots, nullptr, n_items, false, 0);
+    return launch_staged_batched(p, stream, U, lds_slots, nullptr, n_items, false, true, 0);
 }
 
 int launch_validate(const Problem &p, unsigned *flags, hipStream_t stream)

@@ -53,6 +53,49 @@ __device__ __forceinline__ int item_bucket(int it, const int32_t *__restrict__ p
     return 63 - __builtin_clzll(cost | 1ull) > kBuckets - 1 ? kBuckets - 1 : 63 - __builtin_clzll(cost | 1ull);
 }
 
+// Largest vertex range of a work item (pairs sorted by polygon: the rings of
+// the polygons of its first and last pair), clamped to 2^32 - 1.
+// out[0]: the largest span; out[1 + b]: items with floor(log2(span)) = b.
+__global__ __launch_bounds__(256) void k_item_span(const int32_t *__restrict__ pp, int64_t n,
+                                                   const int64_t *__restrict__ offsets, int64_t n_polys,
+                                                   const int64_t *__restrict__ poly_rings, int64_t n_rings,
+                                                   int item_pairs, int n_items, unsigned *out)
+{
+    __shared__ unsigned h[32];
+    if (threadIdx.x < 32)
+        h[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned m = 0;
+    for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < n_items; it += gridDim.x * blockDim.x) {
+        const int64_t p0 = (int64_t)it * item_pairs;
+        const int64_t p1 = (p0 + item_pairs < n ? p0 + item_pairs : n) - 1;
+        int64_t qa = pp ? pp[p0] : 0, qb = pp ? pp[p1] : 0;
+        qa = (uint64_t)qa < (uint64_t)n_polys ? qa : 0;
+        qb = (uint64_t)qb < (uint64_t)n_polys ? qb : 0;
+        if (qa > qb) {
+            const int64_t t = qa;
+            qa = qb;
+            qb = t;
+        }
+        int64_t ra = qa, rb = qb + 1;
+        if (poly_rings) {
+            ra = poly_rings[qa];
+            rb = poly_rings[qb + 1];
+            ra = ra < 0 ? 0 : (ra > n_rings ? n_rings : ra);
+            rb = rb < ra ? ra : (rb > n_rings ? n_rings : rb);
+        }
+        const int64_t span = offsets[rb] - offsets[ra];
+        const unsigned s = span <= 0 ? 0u : (span > 0xffffffffll ? 0xffffffffu : (unsigned)span);
+        m = s > m ? s : m;
+        atomicAdd(&h[s ? 31 - __builtin_clz(s) : 0], 1u);
+    }
+    if (m)
+        atomicMax(out, m);
+    __syncthreads();
+    if (threadIdx.x < 32 && h[threadIdx.x])
+        atomicAdd(&out[1 + threadIdx.x], h[threadIdx.x]);
+}
+
 // counters[0..31] histogram, [32..63] scatter cursors (both zeroed first)
 __global__ __launch_bounds__(256) void k_item_hist(const int32_t *__restrict__ pp, int64_t n,
                                                    const int64_t *__restrict__ offsets, int64_t n_polys,
@@ -114,6 +157,18 @@ int launch_fill(unsigned *p, int n, unsigned v, hipStream_t stream)
     if (n <= 0)
         return PIP_OK;
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, stream, p, n, v);
+    PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
+
+int launch_item_span(const Problem &p, hipStream_t stream, int item_pairs, int n_items, unsigned *out)
+{
+    if (n_items <= 0)
+        return PIP_OK;
+    unsigned g = grid_for(n_items, 256);
+    g = g > 1024 ? 1024 : g;
+    hipLaunchKernelGGL(k_item_span, dim3(g), dim3(256), 0, stream, p.point_poly, p.n_points, p.offsets, p.n_polys,
+                       p.poly_rings, p.n_rings, item_pairs, n_items, out);
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
 }

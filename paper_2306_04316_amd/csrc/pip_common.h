@@ -93,8 +93,13 @@ int launch_runs_batched(const Problem &p, hipStream_t stream, int pairs_per_lane
                         int n_items, unsigned *queue, int grid);
 int staged_max_rings(int pairs_per_lane);
 int staged_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu);
+// tiles: use the form that walks rings larger than max_edges in LDS tiles
 int launch_staged_batched(const Problem &p, hipStream_t stream, int pairs_per_lane, int max_edges,
-                          const int32_t *order, int n_items, bool persistent, int grid);
+                          const int32_t *order, int n_items, bool persistent, bool tiles, int grid);
+// Vertex ranges of the work items of item_pairs pairs (all the rings of the
+// item's polygons): out[0] = the largest, out[1 + b] = items whose range has
+// floor(log2) = b (33 device words, cleared first by the caller).
+int launch_item_span(const Problem &p, hipStream_t stream, int item_pairs, int n_items, unsigned *out);
 
 // ---------------------------------------------------------------- filtered binary32 path
 size_t filtered_smem_bytes(int max_edges, int max_rings);

@@ -35,6 +35,8 @@ struct pip_plan {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool executed = false;
     int timed = 0;   // events of the last execution: 0 none, 1 phases, 2 main kernel only
+    unsigned span[33] = {0};   // vertex ranges of the 1024-pair work items at creation: max, log2 histogram
+    int64_t n_items4 = 0;
 };
 
 namespace pip {
@@ -42,7 +44,8 @@ namespace {
 
 constexpr int kQueue = 64;
 constexpr int kRecheckCount = 65;
-constexpr int kCounters = 68;
+constexpr int kSpan = 66;        // [66, 99): item span maximum and log2 histogram
+constexpr int kCounters = 100;
 
 int item_pairs_of(const pip_plan_config &c) { return 256 * c.pairs_per_lane; }
 
@@ -80,6 +83,22 @@ int resolve_grid(pip_plan *pl, pip_plan_config &c)
 // events between them, graph executions get event-record nodes instead.
 enum Phase { kPrep = 0, kMain = 1, kRecheck = 2 };
 
+// The staged kernel's tile walk (for vertex ranges beyond the LDS budget)
+// comes in a form of its own; it is used when more than 1% of the work items
+// exceed the budget (fewer take the scalar-load group walk inside the plain
+// form, which keeps the plain form's registers).  The counts are for
+// 1024-pair items, an upper bound for smaller items.
+bool use_tiles(const pip_plan *pl, int lds_slots)
+{
+    if (pl->span[0] <= (unsigned)lds_slots)
+        return false;
+    uint64_t over = 0;
+    for (int b = 0; b < 32; ++b)
+        if ((2ull << b) - 1 > (uint64_t)lds_slots)   // bucket b holds spans in [2^b, 2^(b+1))
+            over += pl->span[1 + b];
+    return over * 100 > (uint64_t)pl->n_items4;
+}
+
 bool phase_empty(const pip_plan *pl, const pip_plan_config &c, int ph)
 {
     if (pl->p.n_points == 0)
@@ -108,7 +127,7 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
                            : launch_runs_indexed(p, s, pl->index, pl->index_ws);
     const bool lpt = staged_kind(c) && c.order == 1 && p.point_poly;
     if (ph == kPrep) {
-        PIP_TRY(launch_fill(pl->counters + kQueue, kCounters - kQueue, 0u, s));
+        PIP_TRY(launch_fill(pl->counters + kQueue, kSpan - kQueue, 0u, s));
         if (lpt)
             PIP_TRY(launch_item_order(p, s, item_pairs_of(c), c.n_items, pl->bucket, pl->counters, pl->order));
         return PIP_OK;
@@ -126,7 +145,7 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
         if (c.kernel == PIP_KERNEL_RUNS)
             return launch_runs_batched(p, s, c.pairs_per_lane, order, c.n_items, queue, c.grid);
         return launch_staged_batched(p, s, c.pairs_per_lane, c.lds_slots, order, c.n_items, c.persistent != 0,
-                                     c.grid);
+                                     use_tiles(pl, c.lds_slots), c.grid);
     }
     return launch_recheck(p, s, pl->recheck, pl->counters + kRecheckCount, pl->cu_count * 8);
 }
@@ -555,6 +574,21 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
     }
     if (rc == PIP_OK)
         rc = launch_fill(pl->counters, kCounters, 0u, s);
+    // the largest vertex range of a work item (for the largest items): the
+    // staged kernel walks ranges beyond its LDS budget in tiles, in a separate
+    // form used only when some item needs it (the data may change between
+    // executions; a stale choice only changes which correct path runs)
+    if (rc == PIP_OK && n_points > 0) {
+        pl->n_items4 = (n_points + 1023) / 1024;
+        rc = launch_item_span(p, s, 1024, (int)pl->n_items4, pl->counters + kSpan);
+        if (rc == PIP_OK) {
+            e = hipMemcpyAsync(pl->span, pl->counters + kSpan, sizeof pl->span, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(s);
+            if (e != hipSuccess)
+                rc = fail(PIP_EHIP, "item span: %s", hipGetErrorString(e));
+        }
+    }
     if (rc == PIP_OK && staged_kind(c) && n_points > 0 && !c.index) {
         pip_plan_config cached = c;
         if (cache_lookup(pl, cached)) {
