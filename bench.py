@@ -54,8 +54,9 @@ WORKLOAD_TEXT = {
 # Keyed by (config, mode, kernel-source digest): an entry stops applying as soon as the kernel
 # sources change, and the benchmark then reports traffic as null.
 PROFILED_TRAFFIC: dict = {
-    # footprints, exact mode, k_staged_batched_fp64<4> (profiles/staged_footprints_exact.md)
-    (2, "exact", "c65625e52aa4"): {"fetch_bytes": 219914998, "write_bytes": 10000064},
+    # footprints, exact mode, k_staged_batched_fp64<0, 4, false, false, false>
+    # (profiles/staged_footprints_exact.md: FETCH_SIZE and WRITE_SIZE scaled by the copy calibration)
+    (2, "exact", "8daf99b42f49"): {"fetch_bytes": 221440385, "write_bytes": 10000000},
 }
 
 
