@@ -31,10 +31,6 @@
 namespace pip {
 namespace {
 
-constexpr int kScanThreads = 256;
-constexpr int kScanPer = 16;
-constexpr int kScanTile = kScanThreads * kScanPer;
-
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 struct GridParams {
@@ -49,86 +45,6 @@ __device__ __forceinline__ int cell_1d(double v, double v0, double s, int g)
     const double t = (v - v0) * s;
     // NaN and values below the origin land in cell 0, values past the end in g-1
     return t >= 0.0 ? (t < (double)g ? (int)t : g - 1) : 0;
-}
-
-// ---------------------------------------------------------------- exclusive scan (uint32 -> int64, n+1 outputs)
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
-                                                              int64_t *__restrict__ block_sums)
-{
-    __shared__ int64_t s[kScanThreads];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    int64_t acc = 0;
-    for (int k = 0; k < kScanPer; ++k) {
-        const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
-        if (i < n)
-            acc += in[i];
-    }
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = kScanThreads / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off)
-            s[threadIdx.x] += s[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        block_sums[blockIdx.x] = s[0];
-}
-
-// Block-level inclusive scan of one value per thread (LDS, Hillis-Steele).
-__device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t *s)
-{
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        const int64_t add = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0;
-        __syncthreads();
-        s[threadIdx.x] += add;
-        __syncthreads();
-    }
-    return s[threadIdx.x];
-}
-
-// One workgroup: exclusive scan of the nb block sums in place (any nb).
-__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(int64_t *__restrict__ sums, int64_t nb)
-{
-    __shared__ int64_t s[kScanThreads];
-    int64_t carry = 0;
-    for (int64_t c0 = 0; c0 < nb; c0 += kScanThreads) {
-        const int64_t i = c0 + threadIdx.x;
-        const int64_t v = i < nb ? sums[i] : 0;
-        const int64_t inc = block_inclusive_scan(v, s);
-        if (i < nb)
-            sums[i] = carry + inc - v;
-        const int64_t total = s[kScanThreads - 1];
-        __syncthreads();
-        carry += total;
-    }
-}
-
-// out[i] = block offset + exclusive prefix within the tile; out[n] = total.
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *__restrict__ in, int64_t n,
-                                                            const int64_t *__restrict__ block_off,
-                                                            int64_t *__restrict__ out)
-{
-    __shared__ int64_t s[kScanThreads];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
-    uint32_t v[kScanPer];
-    int64_t acc = 0;
-    for (int k = 0; k < kScanPer; ++k) {
-        const int64_t i = base + k;
-        v[k] = i < n ? in[i] : 0u;
-        acc += v[k];
-    }
-    const int64_t inc = block_inclusive_scan(acc, s);
-    int64_t run = block_off[blockIdx.x] + inc - acc;
-    for (int k = 0; k < kScanPer; ++k) {
-        const int64_t i = base + k;
-        if (i < n)
-            out[i] = run;
-        run += v[k];
-        if (i == n - 1)
-            out[n] = run;
-    }
 }
 
 // ---------------------------------------------------------------- 1. extent and grid
@@ -362,21 +278,6 @@ __global__ __launch_bounds__(256) void k_units(const int64_t *__restrict__ unit_
     }
 }
 
-int scan_u32(const uint32_t *in, int64_t n, int64_t *out, int64_t *block_ws, hipStream_t s)
-{
-    // block_ws: ceil(n / kScanTile) entries (at least one)
-    const int64_t nb = n > 0 ? (n + kScanTile - 1) / kScanTile : 1;
-    if (n <= 0) {
-        PIP_HIP_TRY(hipMemsetAsync(out, 0, sizeof(int64_t), s));
-        return PIP_OK;
-    }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, block_ws);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, s, block_ws, nb);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, block_ws, out);
-    PIP_HIP_TRY(hipGetLastError());
-    return PIP_OK;
-}
-
 }  // namespace
 }  // namespace pip
 
@@ -451,7 +352,7 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
     j->cells = std::max<int64_t>(1, std::min<int64_t>(n_points / 4, (int64_t)1 << 22));
     const int64_t C = j->cells, N = n_points, P = n_polys;
     const int nparts = (int)std::min<int64_t>(1024, grid_for(N, 256));
-    const int64_t scan_blocks = std::max<int64_t>(C, P) / kScanTile + 2;
+    const int64_t scan_blocks = scan_ws_entries(std::max<int64_t>(C, P));
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -505,7 +406,7 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
         if (hipGetLastError() != hipSuccess)
             rc = fail(PIP_EHIP, "join grid kernels failed to launch");
     }
-    step(scan_u32(count, C, j->cell_start, scan_ws, s));
+    step(launch_scan_u32(count, C, j->cell_start, scan_ws, s));
     if (rc == PIP_OK) {
         const unsigned gp = std::min<unsigned>(grid_for(N, 256), 8192u);
         hipLaunchKernelGGL(k_cell_scatter, dim3(gp), dim3(256), 0, s, px, py, N, cell_of, j->cell_start, cursor,
@@ -516,7 +417,7 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
         if (hipGetLastError() != hipSuccess)
             rc = fail(PIP_EHIP, "join polygon kernels failed to launch");
     }
-    step(scan_u32(rows, P, j->unit_start, scan_ws, s));
+    step(launch_scan_u32(rows, P, j->unit_start, scan_ws, s));
     int64_t U = 0;
     if (rc == PIP_OK) {
         e = hipMemcpyAsync(&U, j->unit_start + P, sizeof U, hipMemcpyDeviceToHost, s);
@@ -536,7 +437,7 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
         const size_t o_upoly = take2((size_t)U * 4);
         const size_t o_ucount = take2((size_t)U * 4);
         const size_t o_uoff = take2((size_t)(U + 1) * 8);
-        const size_t o_uscan = take2((size_t)(U / kScanTile + 2) * 8);
+        const size_t o_uscan = take2((size_t)scan_ws_entries(U) * 8);
         e = hipMalloc(&j->ws2, off2);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -554,7 +455,7 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
                                nullptr);
             if (hipGetLastError() != hipSuccess)
                 rc = fail(PIP_EHIP, "join count kernels failed to launch");
-            step(scan_u32(ucount, U, j->unit_off, (int64_t *)(w2 + o_uscan), s));
+            step(launch_scan_u32(ucount, U, j->unit_off, (int64_t *)(w2 + o_uscan), s));
             int64_t M = 0;
             if (rc == PIP_OK) {
                 e = hipMemcpyAsync(&M, j->unit_off + U, sizeof M, hipMemcpyDeviceToHost, s);

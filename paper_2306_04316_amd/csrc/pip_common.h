@@ -112,7 +112,9 @@ int launch_recheck(const Problem &p, hipStream_t stream, const int32_t *list, co
 // ---------------------------------------------------------------- y-index for one large ring
 struct IndexLayout {
     int n0 = 0, n1 = 0, n2 = 0;   // tree nodes per level
-    size_t o_b0 = 0, o_b1 = 0, o_b2 = 0, o_root = 0, o_hist = 0, o_cursor = 0, o_base = 0, o_spt = 0, o_sidx = 0;
+    int nb = 0;                   // point chunks of the coarse sorting pass
+    size_t o_b0 = 0, o_b1 = 0, o_b2 = 0, o_root = 0, o_hist = 0, o_cursor = 0, o_base = 0, o_txy = 0, o_tidx = 0,
+           o_spt = 0, o_sidx = 0;
     size_t bytes = 0;             // workspace bytes
 };
 IndexLayout index_layout(int64_t n_points, int64_t k);
@@ -124,6 +126,10 @@ int launch_fill(unsigned *p, int n, unsigned v, hipStream_t stream);
 int launch_item_order(const Problem &p, hipStream_t stream, int item_pairs, int n_items, uint8_t *bucket,
                       unsigned *counters, int32_t *order);
 int launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t stream);
+// Exclusive scan of n uint32 counts into out[0..n] (int64; out[n] = total);
+// block_ws holds scan_ws_entries(n) int64 entries.  Kernels only.
+int64_t scan_ws_entries(int64_t n);
+int launch_scan_u32(const uint32_t *in, int64_t n, int64_t *out, int64_t *block_ws, hipStream_t stream);
 int launch_validate(const Problem &p, unsigned *flags, hipStream_t stream);
 
 enum : unsigned { VALIDATE_ERANGE = 1u, VALIDATE_EDOM = 2u };
