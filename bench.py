@@ -21,7 +21,6 @@ speed on this host's cores.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
