@@ -252,3 +252,26 @@ def test_plan_index_rejects_pair_index(P):
     with pytest.raises(P.PipError) as e:
         P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], index=True)
     assert e.value.code == -1
+
+
+# ---------------------------------------------------------------- the benchmark's own launch configuration
+@pytest.mark.parametrize("config", [2, 4, 5])
+def test_bench_configuration_full(P, config):
+    """Full-size workloads with the plan built exactly as the benchmark builds it
+    (autotuning with the shipped cache): every pair of the last of several
+    executions against the oracle."""
+    import os
+    import torch
+    cache = os.path.join(os.path.dirname(P.__file__), "tune_cache.txt")
+    w = W.make(config)
+    note(f"bench configuration, workload {config}: N={w.n_points}")
+    d = to_dev(w)
+    pl = P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], mode="exact", tune=1,
+                tune_cache=cache)
+    note(f"config {pl.config()}")
+    for _ in range(3):
+        pl.execute()
+    torch.cuda.synchronize()
+    got = pl.out.cpu().numpy()
+    pl.close()
+    assert_same_mask(got, oracle.classify_workload(w), f"bench configuration {config}", w.px, w.py, w.point_poly)
