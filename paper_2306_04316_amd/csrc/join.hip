@@ -13,18 +13,20 @@
 //      n/4 cells over it, row-major, cell (x) = floor((x - x0) * sx) clamped
 //      -- monotone in x, so a box [a, b] maps to the cell range
 //      [cell(a), cell(b)] that holds every point with a <= x <= b;
-//   2. counting sort of the points by cell (histogram, scan, scatter), so
-//      the points of cells cx0..cx1 of one grid row are one contiguous run;
+//   2. counting sort of the points by cell (two levels with LDS counters and
+//      LDS-staged writes, sort_staged.h), so the points of cells cx0..cx1 of
+//      one grid row are one contiguous run;
 //   3. per polygon (one wavefront each): its box and cell range; its rows
 //      become work units (a unit = one polygon x one grid row);
 //   4. per unit (one wavefront): the lanes test the run's points against
 //      the box; count pass, scan, then the fill pass writes the pairs with
 //      ballot prefix positions.
 // Within a polygon the pairs come in grid order (row, then the cell sort's
-// order, which depends on atomics): the set is exact, the order inside a
+// order, which depends on LDS atomics): the set is exact, the order inside a
 // polygon is not specified.
 #include "pip_common.h"
 #include "ring_walk.h"
+#include "sort_staged.h"
 
 #include <algorithm>
 
@@ -126,33 +128,21 @@ __global__ __launch_bounds__(256) void k_extent_final(const double4 *__restrict_
 }
 
 // ---------------------------------------------------------------- 2. points sorted by cell
-__global__ __launch_bounds__(256) void k_cell_hist(const double *__restrict__ px, const double *__restrict__ py,
-                                                   int64_t n, const GridParams *__restrict__ gp,
-                                                   uint32_t *__restrict__ cell_of, uint32_t *__restrict__ count)
-{
-    const GridParams G = *gp;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const int cx = cell_1d(px[i], G.x0, G.sx, G.gx);
-        const int cy = cell_1d(py[i], G.y0, G.sy, G.gy);
-        const uint32_t c = (uint32_t)cy * (uint32_t)G.gx + (uint32_t)cx;
-        cell_of[i] = c;
-        atomicAdd(&count[c], 1u);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_cell_scatter(const double *__restrict__ px, const double *__restrict__ py,
-                                                      int64_t n, const uint32_t *__restrict__ cell_of,
-                                                      const int64_t *__restrict__ cell_start,
-                                                      uint32_t *__restrict__ cursor, int32_t *__restrict__ spt,
-                                                      double2 *__restrict__ sxy)
-{
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const uint32_t c = cell_of[i];
-        const int64_t pos = cell_start[c] + atomicAdd(&cursor[c], 1u);
-        spt[pos] = (int32_t)i;
-        sxy[pos] = make_double2(px[i], py[i]);
-    }
-}
+// The grid cell of a point as the sort key (cells of at most 2^22, as the
+// join sizes the grid: 2048 coarse digits of 2048 fine digits).
+struct CellKey {
+    const GridParams *g;
+    struct Ready {
+        GridParams G;
+        __device__ __forceinline__ int operator()(double x, double y) const
+        {
+            return cell_1d(y, G.y0, G.sy, G.gy) * G.gx + cell_1d(x, G.x0, G.sx, G.gx);
+        }
+    };
+    __device__ __forceinline__ Ready ready() const { return Ready{*g}; }
+};
+constexpr int kCellCoarse = 2048;
+constexpr int kCellFine = 2048;
 
 // ---------------------------------------------------------------- 3. polygon boxes and their rows
 struct PolyCells {
@@ -348,11 +338,13 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
         return PIP_OK;
     }
 
-    // about four points per cell, at most 2^22 cells
-    j->cells = std::max<int64_t>(1, std::min<int64_t>(n_points / 4, (int64_t)1 << 22));
+    // about four points per cell, at most 2^22 cells (the sort's key range)
+    j->cells = std::max<int64_t>(1, std::min<int64_t>(n_points / 4, (int64_t)kCellCoarse * kCellFine));
     const int64_t C = j->cells, N = n_points, P = n_polys;
     const int nparts = (int)std::min<int64_t>(1024, grid_for(N, 256));
-    const int64_t scan_blocks = scan_ws_entries(std::max<int64_t>(C, P));
+    const int nb = (int)((N + kSortChunk - 1) / kSortChunk);
+    const int64_t tn = (int64_t)kCellCoarse * nb;
+    const int64_t scan_blocks = scan_ws_entries(std::max<int64_t>(tn, P));
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -361,10 +353,11 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
     };
     const size_t o_grid = take(sizeof(GridParams));
     const size_t o_part = take((size_t)nparts * sizeof(double4));
-    const size_t o_cellof = take((size_t)N * 4);
-    const size_t o_count = take((size_t)C * 4);
-    const size_t o_cursor = take((size_t)C * 4);
-    const size_t o_cstart = take((size_t)(C + 1) * 8);
+    const size_t o_table = take((size_t)tn * 4);
+    const size_t o_toff = take((size_t)(tn + 1) * 8);
+    const size_t o_txy = take((size_t)N * 16);
+    const size_t o_tidx = take((size_t)N * 4);
+    const size_t o_cstart = take(((size_t)kCellCoarse * kCellFine + 1) * 8);
     const size_t o_spt = take((size_t)N * 4);
     const size_t o_sxy = take((size_t)N * 16);
     const size_t o_pc = take((size_t)P * sizeof(PolyCells));
@@ -380,9 +373,8 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
     unsigned char *w = (unsigned char *)j->ws;
     j->grid = (GridParams *)(w + o_grid);
     double4 *part = (double4 *)(w + o_part);
-    uint32_t *cell_of = (uint32_t *)(w + o_cellof);
-    uint32_t *count = (uint32_t *)(w + o_count);
-    uint32_t *cursor = (uint32_t *)(w + o_cursor);
+    uint32_t *table = (uint32_t *)(w + o_table);
+    int64_t *toff = (int64_t *)(w + o_toff);
     j->cell_start = (int64_t *)(w + o_cstart);
     j->spt = (int32_t *)(w + o_spt);
     j->sxy = (double2 *)(w + o_sxy);
@@ -396,21 +388,17 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
         if (rc == PIP_OK)
             rc = r;
     };
-    step(launch_fill(count, (int)C, 0u, s));
-    step(launch_fill(cursor, (int)C, 0u, s));
     if (rc == PIP_OK) {
         hipLaunchKernelGGL(k_extent_partial, dim3(nparts), dim3(256), 0, s, px, py, N, part);
         hipLaunchKernelGGL(k_extent_final, dim3(1), dim3(256), 0, s, part, nparts, C, j->grid);
-        const unsigned gp = std::min<unsigned>(grid_for(N, 256), 8192u);
-        hipLaunchKernelGGL(k_cell_hist, dim3(gp), dim3(256), 0, s, px, py, N, j->grid, cell_of, count);
         if (hipGetLastError() != hipSuccess)
             rc = fail(PIP_EHIP, "join grid kernels failed to launch");
     }
-    step(launch_scan_u32(count, C, j->cell_start, scan_ws, s));
+    // points sorted by cell; cell_start[c] = first position of cell c
+    step(launch_sort_staged<CellKey, kCellCoarse, kCellFine>(px, py, N, CellKey{j->grid}, nb, table, toff, scan_ws,
+                                                              (double2 *)(w + o_txy), (int32_t *)(w + o_tidx),
+                                                              j->sxy, j->spt, j->cell_start, s));
     if (rc == PIP_OK) {
-        const unsigned gp = std::min<unsigned>(grid_for(N, 256), 8192u);
-        hipLaunchKernelGGL(k_cell_scatter, dim3(gp), dim3(256), 0, s, px, py, N, cell_of, j->cell_start, cursor,
-                           j->spt, j->sxy);
         const unsigned gq = std::min<unsigned>(grid_for(P, 4), 65536u);
         hipLaunchKernelGGL(k_poly_cells, dim3(gq), dim3(256), 0, s, offsets, P, poly_rings, p.n_rings, vx, vy,
                            n_vertices, j->grid, j->pc, rows);

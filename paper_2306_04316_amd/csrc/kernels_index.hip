@@ -15,6 +15,7 @@
 
 #include "pip_common.h"
 #include "ring_walk.h"
+#include "sort_staged.h"
 
 namespace pip {
 namespace {
@@ -85,203 +86,22 @@ __device__ __forceinline__ int ybucket(double y, double lo, double scale)
     return !(f >= 0.0) ? 0 : (f >= (double)(kYBuckets - 1) ? kYBuckets - 1 : (int)f);
 }
 
-// Counting sort of the points by y bucket in two levels, without a global
-// atomic per point and with coalesced writes: the coarse digit (bucket / 64)
-// first -- each workgroup counts a chunk of points in LDS, the (digit, chunk)
-// table is scanned, then the workgroup writes its chunk out in pieces sorted
-// by digit in LDS, so every digit's points leave as one contiguous run --
-// then one workgroup per coarse digit sorts its run by the fine digit
-// (bucket % 64) the same way.  The order inside a bucket is not specified
-// (the tree walk does not depend on it).
+// The points are counting-sorted by y bucket in two levels (sort_staged.h):
+// 1024 coarse digits of 64 fine digits each.
+struct YKey {
+    const double2 *root;
+    struct Ready {
+        double lo, scale;
+        __device__ __forceinline__ int operator()(double, double y) const { return ybucket(y, lo, scale); }
+    };
+    __device__ __forceinline__ Ready ready() const
+    {
+        const double lo = root->x, hi = root->y;
+        return Ready{lo, hi > lo ? (double)kYBuckets / (hi - lo) : 0.0};
+    }
+};
 constexpr int kCoarse = 1024;
 constexpr int kFine = kYBuckets / kCoarse;
-constexpr int kChunk = 16384;   // points per workgroup in the coarse passes
-constexpr int kPiece = 1024;    // points sorted in LDS at a time (4 per thread)
-
-// Digits of up to kPiece points (4 per thread, digit -1 = no point) are counted,
-// placed in digit order in LDS and written at cur[digit] onwards (cur advanced).
-// `nd` digits; cnt, cur: LDS arrays of nd entries.
-template <int ND>
-__device__ __forceinline__ void write_piece_sorted(const double (&x)[4], const double (&y)[4], const int32_t (&id)[4],
-                                                   const int (&dg)[4], uint32_t *cnt, uint32_t *cur,
-                                                   double2 *sxy, int32_t *sid, uint16_t *sdg,
-                                                   double2 *__restrict__ oxy, int32_t *__restrict__ oid)
-{
-    const int t = threadIdx.x;
-    for (int d = t; d < ND; d += 256)
-        cnt[d] = 0;
-    __syncthreads();
-    uint32_t rk[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        rk[k] = dg[k] >= 0 ? atomicAdd(&cnt[dg[k]], 1u) : 0u;
-    __syncthreads();
-    // exclusive prefix of cnt over ND digits (ND / 256 per thread, then across threads)
-    constexpr int PER = ND / 256 > 0 ? ND / 256 : 1;
-    __shared__ uint32_t part[256];
-    uint32_t loc[PER], sum = 0;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int d = t * PER + k;
-        loc[k] = d < ND ? cnt[d] : 0u;
-        sum += loc[k];
-    }
-    part[t] = sum;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const uint32_t a = t >= o ? part[t - o] : 0u;
-        __syncthreads();
-        part[t] += a;
-        __syncthreads();
-    }
-    uint32_t run = part[t] - sum;
-    const uint32_t total = part[255];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int d = t * PER + k;
-        if (d < ND)
-            cnt[d] = run;   // cnt now holds the digit's first slot
-        run += loc[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (dg[k] >= 0) {
-            const uint32_t slot = cnt[dg[k]] + rk[k];
-            sxy[slot] = make_double2(x[k], y[k]);
-            sid[slot] = id[k];
-            sdg[slot] = (uint16_t)dg[k];
-        }
-    }
-    __syncthreads();
-    for (uint32_t slot = t; slot < total; slot += 256) {
-        const int d = sdg[slot];
-        const uint32_t g = cur[d] + (slot - cnt[d]);
-        oxy[g] = sxy[slot];
-        oid[g] = sid[slot];
-    }
-    __syncthreads();
-    // advance the cursors by this piece's counts (first slot of the next digit minus this one's)
-    for (int d = t; d < ND; d += 256) {
-        const uint32_t end = d + 1 < ND ? cnt[d + 1] : total;
-        cur[d] += end - cnt[d];
-    }
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(256) void k_ycoarse_hist(const double *__restrict__ py, int64_t n,
-                                                      const double2 *__restrict__ root, int nb,
-                                                      uint32_t *__restrict__ table)
-{
-    __shared__ uint32_t h[kCoarse];
-    const double lo = root->x, hi = root->y;
-    const double scale = hi > lo ? (double)kYBuckets / (hi - lo) : 0.0;
-    for (int c = threadIdx.x; c < kCoarse; c += 256)
-        h[c] = 0;
-    __syncthreads();
-    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-    const int64_t c1 = c0 + kChunk < n ? c0 + kChunk : n;
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += 256)
-        atomicAdd(&h[ybucket(py[i], lo, scale) / kFine], 1u);
-    __syncthreads();
-    for (int c = threadIdx.x; c < kCoarse; c += 256)
-        table[(int64_t)c * nb + blockIdx.x] = h[c];
-}
-
-__global__ __launch_bounds__(256) void k_ycoarse_scatter(const double *__restrict__ px,
-                                                         const double *__restrict__ py, int64_t n,
-                                                         const double2 *__restrict__ root, int nb,
-                                                         const int64_t *__restrict__ off,
-                                                         double2 *__restrict__ txy, int32_t *__restrict__ tidx)
-{
-    __shared__ uint32_t cnt[kCoarse], cur[kCoarse];   // positions fit 32 bits (fewer than 2^31 points)
-    __shared__ double2 sxy[kPiece];
-    __shared__ int32_t sid[kPiece];
-    __shared__ uint16_t sdg[kPiece];
-    const double lo = root->x, hi = root->y;
-    const double scale = hi > lo ? (double)kYBuckets / (hi - lo) : 0.0;
-    for (int c = threadIdx.x; c < kCoarse; c += 256)
-        cur[c] = (uint32_t)off[(int64_t)c * nb + blockIdx.x];
-    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-    const int64_t c1 = c0 + kChunk < n ? c0 + kChunk : n;
-    for (int64_t p0 = c0; p0 < c1; p0 += kPiece) {
-        double x[4], y[4];
-        int32_t id[4];
-        int dg[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int64_t i = p0 + k * 256 + threadIdx.x;
-            dg[k] = -1;
-            x[k] = y[k] = 0.0;
-            id[k] = 0;
-            if (i < c1) {
-                x[k] = px[i];
-                y[k] = py[i];
-                id[k] = (int32_t)i;
-                dg[k] = ybucket(y[k], lo, scale) / kFine;
-            }
-        }
-        write_piece_sorted<kCoarse>(x, y, id, dg, cnt, cur, sxy, sid, sdg, txy, tidx);
-    }
-}
-
-// One workgroup per coarse digit c: its run [off[c*nb], off[(c+1)*nb]).
-__global__ __launch_bounds__(256) void k_yfine(const double2 *__restrict__ txy, const int32_t *__restrict__ tidx,
-                                               const double2 *__restrict__ root, int nb,
-                                               const int64_t *__restrict__ off, double2 *__restrict__ spt,
-                                               int32_t *__restrict__ sidx)
-{
-    __shared__ uint32_t cnt[kFine], cur[kFine];
-    __shared__ double2 sxy[kPiece];
-    __shared__ int32_t sid[kPiece];
-    __shared__ uint16_t sdg[kPiece];
-    __shared__ uint32_t part[256];
-    const double lo = root->x, hi = root->y;
-    const double scale = hi > lo ? (double)kYBuckets / (hi - lo) : 0.0;
-    const int c = blockIdx.x;
-    const int64_t s = off[(int64_t)c * nb];
-    const int64_t e = off[(int64_t)(c + 1) * nb];   // c + 1 = kCoarse: the total
-    const int t = threadIdx.x;
-    // the run's fine counts, then their exclusive prefix as the write cursors
-    if (t < kFine)
-        cur[t] = 0;
-    __syncthreads();
-    for (int64_t i = s + t; i < e; i += 256)
-        atomicAdd(&cur[ybucket(txy[i].y, lo, scale) % kFine], 1u);
-    __syncthreads();
-    const uint32_t v = t < kFine ? cur[t] : 0u;
-    part[t] = v;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const uint32_t a = t >= o ? part[t - o] : 0u;
-        __syncthreads();
-        part[t] += a;
-        __syncthreads();
-    }
-    if (t < kFine)
-        cur[t] = (uint32_t)s + part[t] - v;
-    __syncthreads();
-    for (int64_t p0 = s; p0 < e; p0 += kPiece) {
-        double x[4], y[4];
-        int32_t id[4];
-        int dg[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int64_t i = p0 + k * 256 + t;
-            dg[k] = -1;
-            x[k] = y[k] = 0.0;
-            id[k] = 0;
-            if (i < e) {
-                const double2 q = txy[i];
-                x[k] = q.x;
-                y[k] = q.y;
-                id[k] = tidx[i];
-                dg[k] = ybucket(y[k], lo, scale) % kFine;
-            }
-        }
-        write_piece_sorted<kFine>(x, y, id, dg, cnt, cur, sxy, sid, sdg, spt, sidx);
-    }
-}
 
 struct Tree {
     const double2 *b0, *b1, *b2;
@@ -361,7 +181,7 @@ IndexLayout index_layout(int64_t n_points, int64_t k)
     L.o_b2 = take((size_t)(L.n2 > 0 ? L.n2 : 1) * 16);
     L.o_root = take(16);
     const int64_t np = n_points > 0 ? n_points : 1;
-    L.nb = (int)((np + kChunk - 1) / kChunk);
+    L.nb = (int)((np + kSortChunk - 1) / kSortChunk);
     const int64_t tn = (int64_t)kCoarse * L.nb;
     L.o_hist = take((size_t)tn * 4);                       // (coarse digit, chunk) counts
     L.o_cursor = take((size_t)(tn + 1) * 8);               // their exclusive scan
@@ -391,14 +211,10 @@ int launch_index_prep(const Problem &p, hipStream_t s, const IndexLayout &L, uns
     hipLaunchKernelGGL(k_bounds_up, dim3(grid_for(L.n1, 256)), dim3(256), 0, s, b0, L.n0, b1, L.n1);
     hipLaunchKernelGGL(k_bounds_up, dim3(grid_for(L.n2, 256)), dim3(256), 0, s, b1, L.n1, b2, L.n2);
     hipLaunchKernelGGL(k_bounds_root, dim3(1), dim3(256), 0, s, b2, L.n2, root);
-    hipLaunchKernelGGL(k_ycoarse_hist, dim3(L.nb), dim3(256), 0, s, p.py, p.n_points, root, L.nb, table);
-    PIP_HIP_TRY(hipGetLastError());
-    PIP_TRY(launch_scan_u32(table, (int64_t)kCoarse * L.nb, off, scan_ws, s));
-    hipLaunchKernelGGL(k_ycoarse_scatter, dim3(L.nb), dim3(256), 0, s, p.px, p.py, p.n_points, root, L.nb, off,
-                       (double2 *)(ws + L.o_txy), (int32_t *)(ws + L.o_tidx));
-    hipLaunchKernelGGL(k_yfine, dim3(kCoarse), dim3(256), 0, s, (const double2 *)(ws + L.o_txy),
-                       (const int32_t *)(ws + L.o_tidx), root, L.nb, off, (double2 *)(ws + L.o_spt),
-                       (int32_t *)(ws + L.o_sidx));
+    PIP_TRY((launch_sort_staged<YKey, kCoarse, kFine>(p.px, p.py, p.n_points, YKey{root}, L.nb, table, off, scan_ws,
+                                                     (double2 *)(ws + L.o_txy), (int32_t *)(ws + L.o_tidx),
+                                                     (double2 *)(ws + L.o_spt), (int32_t *)(ws + L.o_sidx), nullptr,
+                                                     s)));
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
 }
