@@ -229,15 +229,32 @@ def extensions(P, W, a, cfg, dev):
             cs.append(d)
         return cs
 
-    def plan_entry(w, cs, opts, want, steps=10):
+    def roofline(kernel, alg_bytes, ms, note=None):
+        gbs = alg_bytes / (ms * 1e-3) / 1e9
+        r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+             "traffic": None, "kernel": kernel, "kernel_ms": ms, "alg_bytes_per_launch": alg_bytes}
+        if note:
+            r["note"] = note
+        return r
+
+    def oracle_timed(fn, *args, **kw):
+        t0 = time.perf_counter()
+        r = fn(*args, **kw)
+        return r, time.perf_counter() - t0
+
+    def cpu_entry(work, unit, secs, sample):
+        return {"value": work / secs, "unit": unit, "cores": th, "kind": "oracle",
+                "sample": f"{sample}, {secs:.3f} s"}
+
+    def plan_entry(w, cs, opts, want, steps=10, kernel="main classification kernel", note=None):
         r = Runner(P, cs, dict(opts, timing=True, tune=0))
         ms, _, ph, _ = r.run(steps, 2)
         main_ms = float(np.mean(ph[:, 1]))
         got = cs[(2 + steps - 1) % len(cs)]["out"].cpu().numpy()
         e = {"ms_per_step_eager": ms, "main_kernel_ms": main_ms, "prep_ms": float(np.mean(ph[:, 0])),
              "tests_per_s": w.n_tests / (ms * 1e-3), "pairs": w.n_points, "tests": w.n_tests,
-             "hbm_gbs": w.nbytes_algorithmic() / (main_ms * 1e-3) / 1e9, "config": r.plans[0].config()}
-        e["hbm_frac"] = e["hbm_gbs"] / HBM_PEAK_GBS
+             "config": r.plans[0].config(),
+             "roofline": roofline(kernel, w.nbytes_algorithmic(), main_ms, note)}
         if isinstance(want, tuple):   # sampled
             idx, ws = want
             e["parity"] = ("bit-exact (%d sampled pairs)" % idx.size) if np.array_equal(got[idx], ws) else "MISMATCH"
@@ -253,15 +270,19 @@ def extensions(P, W, a, cfg, dev):
     progress("extension: constraint-2 predicate")
     w = W.footprints(seed=a.seed)
     cs = copies_of(w)
-    out["constraint2_footprints"] = plan_entry(w, cs, dict(base, predicate="intersection"),
-                                               oracle.classify_workload(w, nthreads=th, predicate=2))
+    want, secs = oracle_timed(oracle.classify_workload, w, nthreads=th, predicate=2)
+    e = plan_entry(w, cs, dict(base, predicate="intersection"), want)
+    e["cpu_baseline"] = cpu_entry(w.n_tests, "tests/s", secs, f"the whole workload ({w.n_points} pairs), one pass")
+    out["constraint2_footprints"] = e
     del cs
     # polygons of several rings
     progress("extension: polygons with holes and detached parts")
     w = W.holes(seed=a.seed)
     cs = copies_of(w)
-    e = plan_entry(w, cs, dict(base), oracle.classify_workload(w, nthreads=th))
+    want, secs = oracle_timed(oracle.classify_workload, w, nthreads=th)
+    e = plan_entry(w, cs, dict(base), want)
     e.update(polygons=w.n_polys, rings=w.n_rings)
+    e["cpu_baseline"] = cpu_entry(w.n_tests, "tests/s", secs, f"the whole workload ({w.n_points} pairs), one pass")
     out["rings_holes"] = e
     del cs
     # candidate pairs by bounding box (raw points of the footprints workload)
@@ -277,7 +298,7 @@ def extensions(P, W, a, cfg, dev):
         times.append(time.perf_counter() - t0)
     m = int(c["point"].numel())
     idx = np.sort(np.random.default_rng(5).choice(w.n_points, 3000, replace=False))
-    wp, wq = oracle.bbox_join(w.px[idx], w.py[idx], w.offsets, w.vx, w.vy, nthreads=th)
+    (wp, wq), secs = oracle_timed(oracle.bbox_join, w.px[idx], w.py[idx], w.offsets, w.vx, w.vy, nthreads=th)
     gp, gq = c["point"].cpu().numpy(), c["poly"].cpu().numpy()
     sel = np.isin(gp, idx)
     order = np.lexsort((gp[sel], gq[sel]))
@@ -286,17 +307,24 @@ def extensions(P, W, a, cfg, dev):
     nbytes = 16 * w.n_points + 16 * w.n_vertices + 8 * (w.n_polys + 1) + 28 * m
     out["candidate_pairs"] = {"ms_wall_incl_host_sync": t * 1e3, "points": w.n_points, "polygons": w.n_polys,
                               "pairs": m, "points_per_s": w.n_points / t,
-                              "io_gbs": nbytes / t / 1e9,
-                              "parity": "exact pair set (3000 sampled points)" if ok else "MISMATCH"}
+                              "roofline": roofline("the whole join (every kernel, allocations and two host "
+                                                   "synchronisations, wall time)", nbytes, t * 1e3),
+                              "parity": "exact pair set (3000 sampled points)" if ok else "MISMATCH",
+                              "cpu_baseline": cpu_entry(idx.size, "points/s", secs,
+                                                        f"{idx.size} sampled points against every polygon's box")}
     del c, d
     # y-index for one large polygon (config 3 shape)
     progress("extension: y-index on the 10^6-vertex polygon")
     w = W.make(3, seed=a.seed)
     cs = copies_of(w, 1)
     idx = np.sort(np.random.default_rng(1).choice(w.n_points, 2000, replace=False))
-    ws = oracle.classify_workload(W.subsample(w, idx), nthreads=th)
-    e = plan_entry(w, cs, dict(mode="exact", kernel="auto", index=True, use_graph=False), (idx, ws), steps=5)
+    ws, secs = oracle_timed(oracle.classify_workload, W.subsample(w, idx), nthreads=th)
+    e = plan_entry(w, cs, dict(mode="exact", kernel="auto", index=True, use_graph=False), (idx, ws), steps=5,
+                   kernel="indexed runs kernel",
+                   note="issue-bound tree walk and leaf edge tests; the bytes it must move are few")
     e["note"] = "tests_per_s counts every point-edge test the method defines (the index skips most of them)"
+    e["cpu_baseline"] = cpu_entry(idx.size * w.n_vertices, "tests/s", secs,
+                                  f"{idx.size} sampled pairs against the whole ring")
     out["yindex_fractal"] = e
     del cs
     return out

@@ -224,18 +224,22 @@ __device__ __forceinline__ ItemRange item_range(int64_t p0, int64_t pairs, int64
 // Crossing parity of every lane's point against its staged ring: edges
 // e0 .. e0+k-1 (k = 0: nothing).  Two phases per 32-vertex chunk:
 //   1. straddle pass: above_j = (y_j > p_y) for every vertex (one compare,
-//      exact), shifted into a 32-bit word; straddle bits = above XOR above
-//      shifted by one (half-open rule);
-//   2. side tests only for the lane's straddling edges, one set bit at a time.
-// Returns the lanes with an odd count.  Must be called by the whole wavefront.
+//      exact), shifted into a 32-bit word, vertex j of the chunk at bit 31-j;
+//      straddle bits = above XOR above shifted by one (half-open rule);
+//   2. side tests only for the lane's straddling edges, lowest set bit first
+//      (the order of the tests does not matter: only their count's parity).
+// Returns the lane's parity (0 or 1).  Must be called by the whole wavefront.
 // above_prev: the above bit of the vertex before e0 in the ring (for a whole
-// ring, its last vertex).
+// ring, its last vertex); with own_prev set (a whole ring of at most 32
+// vertices) it is taken from the straddle pass itself, where the last
+// vertex's bit lies at 32-k.
 template <int PRED>
-__device__ __forceinline__ uint64_t staged_ring_parity(const StagedLds &L, int e0, int k, uint32_t above_prev,
-                                                       double xu, double yu, int max_edges, int y_alloc)
+__device__ __forceinline__ uint32_t staged_ring_parity(const StagedLds &L, int e0, int k, uint32_t above_prev,
+                                                       bool own_prev, double xu, double yu, int max_edges,
+                                                       int y_alloc)
 {
     const double yq = yu + 0.0;
-    uint64_t par = 0;
+    uint32_t cnt = 0;
     for (int c0 = 0; c0 < max_edges; c0 += 32) {
         if (__builtin_amdgcn_ballot_w64(k > c0) == 0)
             break;
@@ -256,17 +260,22 @@ __device__ __forceinline__ uint64_t staged_ring_parity(const StagedLds &L, int e
                 above = shift_in_above(above, yq, yr[t + tt]);
         }
         above = t < 32 ? above << (32 - t) : above;
+        if (c0 == 0 && own_prev)
+            above_prev = (above >> ((32 - k) & 31)) & 1u;
         uint32_t strad = above ^ ((above >> 1) | (above_prev << 31));
+        // keep the bits of the lane's rem = k - c0 chunk vertices (none when
+        // rem <= 0, all when rem >= 32): the top rem bits
         const int rem = k - c0;
-        if (rem < 32)
-            strad &= rem <= 0 ? 0u : ~(0xffffffffu >> rem);
+        const int rc = rem < 0 ? 0 : (rem > 32 ? 32 : rem);
+        strad &= (uint32_t)(0xffffffff00000000ull >> rc);
         above_prev = rem >= 32 ? (above & 1u) : above_prev;
-        // phase 2: side tests for this lane's straddling edges only
-        const double4 *er = L.E + e0 + c0;
+        // phase 2: side tests for this lane's straddling edges only; bit b
+        // is the edge ending at chunk vertex 31 - b
+        const int elast = e0 + c0 + 31;
         while (strad != 0) {
-            const int j = __builtin_clz(strad);
-            strad ^= 0x80000000u >> j;
-            const double4 rec = er[j];
+            const int b = __builtin_ctz(strad);
+            strad &= strad - 1u;
+            const double4 rec = L.E[elast - b];
             bool cr;
             if (PRED == kIntersection) {
                 const double lam = (yu - rec.y) / rec.w;
@@ -278,10 +287,10 @@ __device__ __forceinline__ uint64_t staged_ring_parity(const StagedLds &L, int e
                 const double sv = t1 * rec.z + t2 * rec.w;
                 cr = sv <= 0.0;
             }
-            par ^= __builtin_amdgcn_ballot_w64(cr);
+            cnt += cr ? 1u : 0u;
         }
     }
-    return par;
+    return cnt & 1u;
 }
 
 // Classify the 256*U pairs starting at p0 (one workgroup, 256 threads).
@@ -302,7 +311,6 @@ __device__ __forceinline__ void staged_item_fp64(
     unsigned char *smem, const ItemRange R)
 {
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
     const int ypad = 64;
     const int y_alloc = max_edges + ypad;
     double x[U], y[U];
@@ -420,7 +428,7 @@ __device__ __forceinline__ void staged_item_fp64(
                     r1 = L.PR[j + 1];
                     r1 = r1 < r0 ? r0 : r1;
                 }
-                uint64_t par = 0;
+                uint32_t par = 0;
                 for (int step = 0;; ++step) {
                     const int rr = r0 + step;
                     const bool act = rr < r1;
@@ -432,8 +440,11 @@ __device__ __forceinline__ void staged_item_fp64(
                     const int a = (TILES && e0 < t0) ? t0 : e0;
                     const int b = (TILES && e1 > t1) ? t1 : e1;
                     const int k = act && b > a ? b - a : 0;
+                    // the above bit of the part's predecessor: from the pass itself
+                    // for a whole ring within one chunk, else read
+                    const bool own = a == e0 && b == e1 && k <= 32;
                     uint32_t prev = 0;
-                    if (k > 0) {
+                    if (k > 0 && !own) {
                         const int pred = a == e0 ? e1 - 1 : a - 1;
                         double yp;
                         if (TILES && !(pred >= t0 && pred < t1))
@@ -442,11 +453,11 @@ __device__ __forceinline__ void staged_item_fp64(
                             yp = L.Y[pred - t0];
                         prev = yp > y[u] ? 1u : 0u;
                     }
-                    par ^= staged_ring_parity<PRED>(L, a - t0, k, prev, x[u], y[u], S, y_alloc);
+                    par ^= staged_ring_parity<PRED>(L, a - t0, k, prev, own, x[u], y[u], S, y_alloc);
                     if (!MR)
                         break;
                 }
-                mine ^= (uint32_t)((par >> lane) & 1u) << u;
+                mine ^= par << u;
             }
             if (TILES && t1 < nvr)
                 __syncthreads();   // the next tile overwrites Y and E
