@@ -55,7 +55,7 @@ WORKLOAD_TEXT = {
 PROFILED_TRAFFIC: dict = {
     # footprints, exact mode, k_staged_batched_fp64<0, 4, false, false, false>
     # (profiles/staged_footprints_exact.md: FETCH_SIZE and WRITE_SIZE scaled by the copy calibration)
-    (2, "exact", "88ddb8d61a62"): {"fetch_bytes": 221440129, "write_bytes": 10000000},
+    (2, "exact", "95d4e7ee4f04"): {"fetch_bytes": 221436802, "write_bytes": 10000000},
 }
 
 
