@@ -302,32 +302,48 @@ __device__ __forceinline__ uint32_t staged_ring_parity(const StagedLds &L, int e
 // Rings larger than the LDS edge budget are walked in tiles (see below);
 // only items with more rings or polygons than the tables hold, or with pairs
 // not sorted by polygon, take the scalar-load group walk.
+// The thread's pairs of the item starting at p0 (row u: pair p0 + 256u + tid),
+// read once and streamed past the caches.  q = -1 past the end.
+template <int U>
+struct ItemRows {
+    double x[U], y[U];
+    int q[U];
+};
+
+template <int U>
+__device__ __forceinline__ ItemRows<U> load_rows(int64_t p0, const double *__restrict__ px,
+                                                 const double *__restrict__ py, int64_t n,
+                                                 const int32_t *__restrict__ point_poly)
+{
+    ItemRows<U> P;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = p0 + u * 256 + threadIdx.x;
+        P.x[u] = 0.0;
+        P.y[u] = 0.0;
+        P.q[u] = -1;
+        if (i < n) {
+            P.x[u] = __builtin_nontemporal_load(px + i);
+            P.y[u] = __builtin_nontemporal_load(py + i);
+            P.q[u] = point_poly ? __builtin_nontemporal_load(point_poly + i) : 0;
+        }
+    }
+    return P;
+}
+
 template <int PRED, int U, bool MR, bool TILES>
 __device__ __forceinline__ void staged_item_fp64(
-    int64_t p0, const double *__restrict__ px, const double *__restrict__ py, int64_t n,
-    const int64_t *__restrict__ offsets, int64_t n_polys, const int64_t *__restrict__ poly_rings,
-    int64_t n_rings, const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
-    const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
+    int64_t p0, const ItemRows<U> &P, int64_t n, const int64_t *__restrict__ offsets, int64_t n_polys,
+    const int64_t *__restrict__ poly_rings, int64_t n_rings, const double *__restrict__ vx,
+    const double *__restrict__ vy, int64_t nv, uint8_t *__restrict__ inside, int max_edges, int max_rings,
     unsigned char *smem, const ItemRange R)
 {
     const int tid = threadIdx.x;
     const int ypad = 64;
     const int y_alloc = max_edges + ypad;
-    double x[U], y[U];
-    int q[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t i = p0 + u * 256 + tid;
-        x[u] = 0.0;
-        y[u] = 0.0;
-        q[u] = -1;
-        if (i < n) {
-            // read once: streamed past the caches
-            x[u] = __builtin_nontemporal_load(px + i);
-            y[u] = __builtin_nontemporal_load(py + i);
-            q[u] = point_poly ? __builtin_nontemporal_load(point_poly + i) : 0;
-        }
-    }
+    const double(&x)[U] = P.x;
+    const double(&y)[U] = P.y;
+    const int(&q)[U] = P.q;
 
     // the workgroup's range (the same for every thread, so `tables` and `fits`
     // are uniform)
@@ -338,14 +354,33 @@ __device__ __forceinline__ void staged_item_fp64(
     const int nvr = R.nv;
     const bool tables = R.ok && nr <= max_rings && np <= max_rings;
     const bool fits = tables && nvr <= max_edges;
-    bool mine_ok = true;
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-        mine_ok = mine_ok && (q[u] < 0 || (q[u] >= qf && q[u] <= ql));
 
     const StagedLds L = staged_lds(smem, max_edges, max_rings);
+    // First round of the ring table and of the vertices: one entry of each
+    // per thread, their loads issued together (one memory round trip); larger
+    // tables and ranges continue in the loops below.
+    {
+        const bool hr = tables && tid <= nr;
+        const bool hv = fits && tid < nvr;
+        int64_t o = 0;
+        double ax = 0.0, ay = 0.0;
+        if (hr)
+            o = offsets[R.rf + tid];
+        if (hv) {
+            ax = vx[vb + tid];
+            ay = vy[vb + tid];
+        }
+        if (hr) {
+            o = o < vb ? vb : (o > ve ? ve : o);
+            L.T[tid] = (int)(o - vb);
+        }
+        if (hv) {
+            L.XR[tid] = ax;
+            L.Y[tid] = ay;
+        }
+    }
     if (tables) {
-        for (int r = tid; r <= nr; r += 256) {
+        for (int r = tid + 256; r <= nr; r += 256) {
             int64_t o = offsets[R.rf + r];
             o = o < vb ? vb : (o > ve ? ve : o);
             L.T[r] = (int)(o - vb);
@@ -359,13 +394,19 @@ __device__ __forceinline__ void staged_item_fp64(
         }
     }
     if (fits) {
-        for (int e = tid; e < nvr; e += 256) {
+        for (int e = tid + 256; e < nvr; e += 256) {
             L.XR[e] = vx[vb + e];
             L.Y[e] = vy[vb + e];
         }
         if (tid < ypad)
             L.Y[nvr + tid] = 0.0;
     }
+    // every pair's polygon inside the staged range (the pairs' own loads are
+    // first waited for here, after the staging loads went out)
+    bool mine_ok = true;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        mine_ok = mine_ok && (q[u] < 0 || (q[u] >= qf && q[u] <= ql));
     const bool staged = __syncthreads_and(tables && mine_ok && (TILES || fits));
 
     if (staged) {
@@ -526,10 +567,11 @@ void k_staged_batched_fp64(
     if (!PERS) {
         const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
         const int64_t p0 = (int64_t)item * IP;
+        // the pairs' loads go out first, so they overlap the range lookups
+        const ItemRows<U> P = load_rows<U>(p0, px, py, n, point_poly);
         const ItemRange R = item_range<MR>(p0, IP, n, offsets, n_polys, poly_rings, n_rings, nv, point_poly);
-        staged_item_fp64<PRED, U, MR, TILES>(p0, px, py, n, offsets, n_polys, poly_rings, n_rings, vx, vy, nv,
-                                             point_poly,
-                                      inside, max_edges, max_rings, smem, R);
+        staged_item_fp64<PRED, U, MR, TILES>(p0, P, n, offsets, n_polys, poly_rings, n_rings, vx, vy, nv, inside,
+                                             max_edges, max_rings, smem, R);
         return;
     }
     __shared__ ItemRange s_range[64];
@@ -555,9 +597,10 @@ void k_staged_batched_fp64(
             const int item = __builtin_amdgcn_readfirstlane(s_item[j]);
             if (item < 0)
                 break;
-            staged_item_fp64<PRED, U, MR, TILES>((int64_t)item * IP, px, py, n, offsets, n_polys, poly_rings, n_rings, vx,
-                                          vy, nv, point_poly, inside, max_edges, max_rings, smem,
-                                          uniform_range(s_range[j]));
+            const int64_t p0 = (int64_t)item * IP;
+            const ItemRows<U> P = load_rows<U>(p0, px, py, n, point_poly);
+            staged_item_fp64<PRED, U, MR, TILES>(p0, P, n, offsets, n_polys, poly_rings, n_rings, vx, vy, nv,
+                                                 inside, max_edges, max_rings, smem, uniform_range(s_range[j]));
             __syncthreads();   // the next item reuses the staging area
         }
     }
