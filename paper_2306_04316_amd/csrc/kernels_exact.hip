@@ -302,6 +302,23 @@ __device__ __forceinline__ uint32_t staged_ring_parity(const StagedLds &L, int e
 // Rings larger than the LDS edge budget are walked in tiles (see below);
 // only items with more rings or polygons than the tables hold, or with pairs
 // not sorted by polygon, take the scalar-load group walk.
+// The staged record of edge (a, b): constraint 1 stores (a_x, a_y, n_x, n_y)
+// with the normal n = (b_y - a_y, a_x - b_x) negated when n_x < 0, constraint
+// 2 stores (a_x, a_y, d_x, d_y), d = b - a; binary64, as the rule states.
+template <int PRED>
+__device__ __forceinline__ double4 edge_record(double ax, double ay, double bx, double by)
+{
+    if (PRED == kIntersection)
+        return make_double4(ax, ay, bx - ax, by - ay);
+    double nx = by - ay;
+    double ny = ax - bx;
+    if (nx < 0.0) {
+        nx = -nx;
+        ny = -ny;
+    }
+    return make_double4(ax, ay, nx, ny);
+}
+
 // The thread's pairs of the item starting at p0 (row u: pair p0 + 256u + tid),
 // read once and streamed past the caches.  q = -1 past the end.
 template <int U>
@@ -422,37 +439,31 @@ __device__ __forceinline__ void staged_item_fp64(
         uint32_t mine = 0;   // bit u: this lane's parity for row u
         for (int t0 = 0; t0 < nvr; t0 += S) {
             const int t1 = (!TILES || nvr - t0 < S) ? nvr : t0 + S;
-            for (int e = t0 + tid; e < t1; e += 256) {
-                const int r = staged_ring_of(L.T, nr, e);
-                if (r < 0)
-                    continue;
-                const int e0 = L.T[r];
-                const int ep = e == e0 ? L.T[r + 1] - 1 : e - 1;
-                double ax, ay, bx, by;
-                if (!TILES || fits) {
-                    ax = L.XR[ep];
-                    ay = L.Y[ep];
-                    bx = L.XR[e];
-                    by = L.Y[e];
-                } else {
-                    ax = vx[vb + ep];
-                    ay = vy[vb + ep];
-                    bx = vx[vb + e];
-                    by = vy[vb + e];
+            if (!TILES || fits) {
+                // the whole range is staged: every vertex's record takes its
+                // stored predecessor, then each ring's first record is redone
+                // with the ring's last vertex (no search for a vertex's ring)
+                for (int e = tid; e < nvr; e += 256) {
+                    const int ep = e > 0 ? e - 1 : 0;
+                    L.E[e] = edge_record<PRED>(L.XR[ep], L.Y[ep], L.XR[e], L.Y[e]);
                 }
-                if (PRED == kIntersection) {
-                    L.E[e - t0] = make_double4(ax, ay, bx - ax, by - ay);
-                } else {
-                    double nx = by - ay;
-                    double ny = ax - bx;
-                    if (nx < 0.0) {
-                        nx = -nx;
-                        ny = -ny;
-                    }
-                    L.E[e - t0] = make_double4(ax, ay, nx, ny);
+                __syncthreads();
+                for (int r = tid; r < nr; r += 256) {
+                    const int e0 = L.T[r], e1 = L.T[r + 1];
+                    if (e0 < e1)
+                        L.E[e0] = edge_record<PRED>(L.XR[e1 - 1], L.Y[e1 - 1], L.XR[e0], L.Y[e0]);
                 }
-                if (TILES && !fits)
+            } else {
+                for (int e = t0 + tid; e < t1; e += 256) {
+                    const int r = staged_ring_of(L.T, nr, e);
+                    if (r < 0)
+                        continue;
+                    const int e0 = L.T[r];
+                    const int ep = e == e0 ? L.T[r + 1] - 1 : e - 1;
+                    const double by = vy[vb + e];
+                    L.E[e - t0] = edge_record<PRED>(vx[vb + ep], vy[vb + ep], vx[vb + e], by);
                     L.Y[e - t0] = by;
+                }
             }
             if (TILES && !fits && tid < ypad)
                 L.Y[(t1 - t0) + tid] = 0.0;
