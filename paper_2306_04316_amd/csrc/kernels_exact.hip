@@ -120,7 +120,9 @@ __global__ __launch_bounds__(256) void k_segmented_fp64(
 //   E  : per edge j = (v_{j-1}, v_j) of its ring, the record (a_x, a_y, n_x, n_y)
 //        with the normal n = (b_y - a_y, a_x - b_x) negated when n_x < 0,
 //        computed in binary64 exactly as the rule states (so the side value
-//        below is the rule's, bit for bit).
+//        below is the rule's, bit for bit).  Every vertex's record is first
+//        built from the vertex stored before it; then each ring's first
+//        record is rebuilt from the ring's last vertex (closing edge).
 // Each lane then runs two phases per 32-vertex chunk of its own ring:
 //   1. straddle pass: above_j = (y_j > p_y) for every vertex (one compare,
 //      exact), shifted into a 32-bit word; straddle bits = above XOR above
@@ -547,8 +549,9 @@ __device__ __forceinline__ ItemRange uniform_range(const ItemRange &R)
 }
 
 // Batched form.  Without `persistent`, workgroup b takes item order[b] (or b)
-// and finds its polygon range itself: pair ids, then offsets, then vertices,
-// three dependent loads before any work.
+// and finds its polygon range itself: pair ids, then offsets, then the ring
+// table and vertices, three dependent loads before any work; the pairs' own
+// loads are issued first so that they travel alongside that chain.
 // With `persistent`, a grid sized to the resident capacity walks the item
 // list with a fixed stride (workgroup b: list positions b, b + G, b + 2G, ..).
 // Before each block of 64 of its items, 64 lanes look up all 64 polygon
