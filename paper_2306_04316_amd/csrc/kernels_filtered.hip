@@ -1,8 +1,10 @@
 // Binary32 filtered evaluation with a proven error bound, plus the binary64
 // recheck of the pairs the filter cannot decide.
 //
-// Per workgroup item (256*U consecutive pairs, sorted by polygon) the rings
-// are staged in LDS re-centred on their bounding-box centre c:
+// Per workgroup item (256*U consecutive pairs, sorted by polygon) the rings'
+// binary64 vertices are first copied to LDS in one coalesced round with the
+// ring table; from there one wavefront per ring derives, re-centred on the
+// ring's bounding-box centre c:
 //   YF : fl32(fl64(y_j - c_y)) per vertex (straddle pass)
 //   EF : (XI, YI, NX, NY) = fl32 of fl64(a - c) and of the rule's binary64
 //        normal (negated when its x part is negative), per edge
@@ -82,9 +84,11 @@ __device__ __forceinline__ void append_recheck(uint64_t mask, int64_t i, int32_t
 size_t filtered_smem_bytes(int max_edges, int max_rings)
 {
     // T int[max_rings+1] | ring table 32 B per ring | YF float[max_edges+max_rings+64] | EF float4[max_edges]
+    // | XD, YD double[max_edges] (the staged binary64 vertices)
     size_t o = (((size_t)(max_rings + 1) * 4 + 15) & ~(size_t)15);
     o += (size_t)max_rings * 32;
     o += ((((size_t)max_edges + max_rings + 64) * 4 + 15) & ~(size_t)15);
+    o += (size_t)max_edges * 16;
     o += (size_t)max_edges * 16;
     return o;
 }
@@ -127,6 +131,8 @@ __device__ __forceinline__ void filtered_item(
             q[u] = point_poly ? __builtin_nontemporal_load(point_poly + i) : 0;
         }
     }
+    // the workgroup's range (uniform): pair ids, then offsets, while the
+    // pairs' own loads are in flight
     const int64_t plast = (p0 + 256 * U < n ? p0 + 256 * U : n) - 1;
     int qf = 0, ql = 0;
     if (point_poly) {
@@ -141,18 +147,8 @@ __device__ __forceinline__ void filtered_item(
         clamp_ring(vb, ve, nv);
     }
     const int nr = ql - qf + 1;
-    bool mine_ok = true;
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-        mine_ok = mine_ok && (q[u] < 0 || (q[u] >= qf && q[u] <= ql));
-    const bool staged = __syncthreads_and(range_ok && ve - vb <= max_edges && nr <= max_rings && mine_ok);
-
-    if (!staged) {
-        // Rings too large for the workgroup's LDS (or unsorted pairs): these
-        // pairs take the exact binary64 wave-uniform walk instead.
-        group_walk_rows<kSide, U>(p0, x, y, q, n, offsets, n_polys, nullptr, n_polys, vx, vy, nv, inside);
-        return;
-    }
+    const int nvr = (int)(ve - vb);
+    const bool fits = range_ok && nvr <= max_edges && nr <= max_rings;
 
     int *T = (int *)smem;
     size_t o = (((size_t)(max_rings + 1) * 4 + 15) & ~(size_t)15);
@@ -161,13 +157,37 @@ __device__ __forceinline__ void filtered_item(
     float *YF = (float *)(smem + o);
     o += ((((size_t)max_edges + max_rings + 64) * 4 + 15) & ~(size_t)15);
     float4 *EF = (float4 *)(smem + o);
+    o += (size_t)max_edges * 16;
+    double *XD = (double *)(smem + o);
+    double *YD = XD + max_edges;
 
-    for (int r = tid; r <= nr; r += 256) {
-        int64_t ov = offsets[qf + r];
-        ov = ov < vb ? vb : (ov > ve ? ve : ov);
-        T[r] = (int)(ov - vb);
+    // the ring table and the binary64 vertices in one round of loads
+    if (fits) {
+        for (int r = tid; r <= nr; r += 256) {
+            int64_t ov = offsets[qf + r];
+            ov = ov < vb ? vb : (ov > ve ? ve : ov);
+            T[r] = (int)(ov - vb);
+        }
+        for (int e = tid; e < nvr; e += 256) {
+            XD[e] = vx[vb + e];
+            YD[e] = vy[vb + e];
+        }
     }
-    __syncthreads();
+    bool mine_ok = true;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        mine_ok = mine_ok && (q[u] < 0 || (q[u] >= qf && q[u] <= ql));
+    const bool staged = __syncthreads_and(fits && mine_ok);
+
+    if (!staged) {
+        // Rings too large for the workgroup's LDS (or unsorted pairs): these
+        // pairs take the exact binary64 wave-uniform walk instead.
+        group_walk_rows<kSide, U>(p0, x, y, q, n, offsets, n_polys, nullptr, n_polys, vx, vy, nv, inside);
+        return;
+    }
+
+    // per ring (one wavefront each): centre, radius and binary32 records,
+    // from the staged vertices
     int kmax_local = 0;
     for (int r = wid; r < nr; r += 4) {
         const int e0 = T[r];
@@ -175,8 +195,8 @@ __device__ __forceinline__ void filtered_item(
         e1 = e1 < e0 ? e0 : e1;
         const int k = e1 - e0;
         kmax_local = k > kmax_local ? k : kmax_local;
-        const double *__restrict__ rx = vx + vb + e0;
-        const double *__restrict__ ry = vy + vb + e0;
+        const double *rx = XD + e0;
+        const double *ry = YD + e0;
         // bounding box -> centre, radius
         double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
         bool ok = true;
