@@ -18,12 +18,15 @@ constexpr int kSortChunk = 16384;   // points per workgroup in pass 1
 constexpr int kSortPiece = 1024;    // points ordered in LDS at a time (4 per thread)
 
 // In-place exclusive prefix of a[0..ND) (LDS), by a workgroup of 256 threads;
-// returns the total.  part: LDS scratch of 256 words.
+// returns the total.  Each thread sums its ND/256 entries, the wavefronts
+// scan those sums with lane shuffles, and one exchange of the four wavefront
+// totals through part (LDS, 4 words) completes it: two barriers in all.
 template <int ND>
 __device__ __forceinline__ uint32_t lds_exclusive_scan(uint32_t *a, uint32_t *part)
 {
     constexpr int PER = ND / 256 > 0 ? ND / 256 : 1;
     const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
     uint32_t loc[PER], sum = 0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -31,16 +34,22 @@ __device__ __forceinline__ uint32_t lds_exclusive_scan(uint32_t *a, uint32_t *pa
         loc[k] = d < ND ? a[d] : 0u;
         sum += loc[k];
     }
-    part[t] = sum;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const uint32_t v = t >= o ? part[t - o] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o, 64);
+        incl += lane >= o ? v : 0u;
     }
-    uint32_t run = part[t] - sum;
-    const uint32_t total = part[255];
+    if (lane == 63)
+        part[w] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum, total = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t p = part[i];
+        run += i < w ? p : 0u;
+        total += p;
+    }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int d = t * PER + k;
@@ -107,8 +116,20 @@ __global__ __launch_bounds__(256) void k_sort_coarse_hist(const double *__restri
     __syncthreads();
     const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
     const int64_t c1 = c0 + kSortChunk < n ? c0 + kSortChunk : n;
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += 256)
-        atomicAdd(&h[kf(px[i], py[i]) / NF], 1u);
+    // four points per thread per round, their loads issued together
+    for (int64_t b = c0; b < c1; b += 1024) {
+        double x[4], y[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = b + k * 256 + threadIdx.x;
+            x[k] = i < c1 ? px[i] : 0.0;
+            y[k] = i < c1 ? py[i] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (b + k * 256 + threadIdx.x < c1)
+                atomicAdd(&h[kf(x[k], y[k]) / NF], 1u);
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < NC; c += 256)
         table[(int64_t)c * nb + blockIdx.x] = h[c];
@@ -121,7 +142,7 @@ __global__ __launch_bounds__(256) void k_sort_coarse_scatter(const double *__res
                                                              double2 *__restrict__ txy, int32_t *__restrict__ tidx)
 {
     __shared__ uint32_t cnt[NC], cur[NC];   // positions fit 32 bits (fewer than 2^31 points)
-    __shared__ uint32_t part[256];
+    __shared__ uint32_t part[4];
     __shared__ double2 sxy[kSortPiece];
     __shared__ int32_t sid[kSortPiece];
     __shared__ uint16_t sdg[kSortPiece];
@@ -130,24 +151,37 @@ __global__ __launch_bounds__(256) void k_sort_coarse_scatter(const double *__res
         cur[c] = (uint32_t)off[(int64_t)c * nb + blockIdx.x];
     const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
     const int64_t c1 = c0 + kSortChunk < n ? c0 + kSortChunk : n;
+    // pieces of 1024 points; the next piece's loads are issued before the
+    // current piece is ordered and written
+    double x[4], y[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = c0 + k * 256 + threadIdx.x;
+        x[k] = i < c1 ? px[i] : 0.0;
+        y[k] = i < c1 ? py[i] : 0.0;
+    }
     for (int64_t p0 = c0; p0 < c1; p0 += kSortPiece) {
-        double x[4], y[4];
         int32_t id[4];
         int dg[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int64_t i = p0 + k * 256 + threadIdx.x;
-            dg[k] = -1;
-            x[k] = y[k] = 0.0;
-            id[k] = 0;
-            if (i < c1) {
-                x[k] = px[i];
-                y[k] = py[i];
-                id[k] = (int32_t)i;
-                dg[k] = kf(x[k], y[k]) / NF;
-            }
+            id[k] = (int32_t)i;
+            dg[k] = i < c1 ? (int)(kf(x[k], y[k]) / NF) : -1;
+        }
+        double nx[4], ny[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = p0 + kSortPiece + k * 256 + threadIdx.x;
+            nx[k] = i < c1 ? px[i] : 0.0;
+            ny[k] = i < c1 ? py[i] : 0.0;
         }
         write_piece_sorted<NC>(x, y, id, dg, cnt, cur, part, sxy, sid, sdg, txy, tidx);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[k] = nx[k];
+            y[k] = ny[k];
+        }
     }
 }
 
@@ -160,7 +194,7 @@ __global__ __launch_bounds__(256) void k_sort_fine(const double2 *__restrict__ t
                                                    int64_t *__restrict__ key_start)
 {
     __shared__ uint32_t cnt[NF], cur[NF];
-    __shared__ uint32_t part[256];
+    __shared__ uint32_t part[4];
     __shared__ double2 sxy[kSortPiece];
     __shared__ int32_t sid[kSortPiece];
     __shared__ uint16_t sdg[kSortPiece];
@@ -173,9 +207,17 @@ __global__ __launch_bounds__(256) void k_sort_fine(const double2 *__restrict__ t
     for (int d = t; d < NF; d += 256)
         cur[d] = 0;
     __syncthreads();
-    for (int64_t i = s + t; i < e; i += 256) {
-        const double2 q = txy[i];
-        atomicAdd(&cur[kf(q.x, q.y) % NF], 1u);
+    for (int64_t b = s; b < e; b += 1024) {
+        double2 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = b + k * 256 + t;
+            v[k] = i < e ? txy[i] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (b + k * 256 + t < e)
+                atomicAdd(&cur[kf(v[k].x, v[k].y) % NF], 1u);
     }
     __syncthreads();
     lds_exclusive_scan<NF>(cur, part);
@@ -187,25 +229,32 @@ __global__ __launch_bounds__(256) void k_sort_fine(const double2 *__restrict__ t
     if (key_start && c == NC - 1 && t == 0)
         key_start[(int64_t)NC * NF] = e;
     __syncthreads();
+    double2 v[4];
+    int32_t id[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = s + k * 256 + t;
+        v[k] = i < e ? txy[i] : make_double2(0.0, 0.0);
+        id[k] = i < e ? tidx[i] : 0;
+    }
     for (int64_t p0 = s; p0 < e; p0 += kSortPiece) {
         double x[4], y[4];
-        int32_t id[4];
         int dg[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int64_t i = p0 + k * 256 + t;
-            dg[k] = -1;
-            x[k] = y[k] = 0.0;
-            id[k] = 0;
-            if (i < e) {
-                const double2 q = txy[i];
-                x[k] = q.x;
-                y[k] = q.y;
-                id[k] = tidx[i];
-                dg[k] = kf(x[k], y[k]) % NF;
-            }
+            x[k] = v[k].x;
+            y[k] = v[k].y;
+            dg[k] = p0 + k * 256 + t < e ? (int)(kf(x[k], y[k]) % NF) : -1;
         }
-        write_piece_sorted<NF>(x, y, id, dg, cnt, cur, part, sxy, sid, sdg, oxy, oidx);
+        int32_t cid[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            cid[k] = id[k];
+            const int64_t i = p0 + kSortPiece + k * 256 + t;
+            v[k] = i < e ? txy[i] : make_double2(0.0, 0.0);
+            id[k] = i < e ? tidx[i] : 0;
+        }
+        write_piece_sorted<NF>(x, y, cid, dg, cnt, cur, part, sxy, sid, sdg, oxy, oidx);
     }
 }
 
