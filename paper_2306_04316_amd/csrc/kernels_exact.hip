@@ -426,7 +426,8 @@ __device__ __forceinline__ void staged_item_fp64(
 #pragma unroll
     for (int u = 0; u < U; ++u)
         mine_ok = mine_ok && (q[u] < 0 || (q[u] >= qf && q[u] <= ql));
-    const bool staged = __syncthreads_and(tables && mine_ok && (TILES || fits));
+    __shared__ int s_all[4];
+    const bool staged = block_all(tables && mine_ok && (TILES || fits), s_all);
 
     if (staged) {
         // The vertex range in tiles of S = max_edges vertices: one tile when it
@@ -560,15 +561,16 @@ __device__ __forceinline__ ItemRange uniform_range(const ItemRange &R)
 // trip instead of three.  There is no shared counter to contend for: the
 // stride is fixed, and the heaviest-first order (if given) deals the costly
 // items out evenly.
-// Eight waves per SIMD hide the load latency best; the side-test variants fit
-// that register budget (64 VGPRs) without spilling, the intersection-test
-// variant with its division does not and keeps the compiler's choice.
+// Eight waves per SIMD hide the load latency best; the one-item side-test
+// variants fit that register budget (64 VGPRs) without spilling; the
+// intersection-test variant (its division) and the persistent form (its
+// item table) do not, and keep the compiler's choice rather than spill.
 // The persistent and one-item-per-workgroup forms are separate kernels
 // (PERS), so each is compiled with only its own control flow and registers;
 // so are the forms with and without the tile walk for rings larger than the
 // LDS budget (TILES; without it such items take the scalar-load group walk).
 template <int PRED, int U, bool MR, bool PERS, bool TILES>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRED == kSide && !MR ? 8 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRED == kSide && !MR && !PERS ? 8 : 1)))
 void k_staged_batched_fp64(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys, const int64_t *__restrict__ poly_rings,

@@ -177,7 +177,8 @@ __device__ __forceinline__ void filtered_item(
 #pragma unroll
     for (int u = 0; u < U; ++u)
         mine_ok = mine_ok && (q[u] < 0 || (q[u] >= qf && q[u] <= ql));
-    const bool staged = __syncthreads_and(fits && mine_ok);
+    __shared__ int s_all[4];
+    const bool staged = block_all(fits && mine_ok, s_all);
 
     if (!staged) {
         // Rings too large for the workgroup's LDS (or unsorted pairs): these

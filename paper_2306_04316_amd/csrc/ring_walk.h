@@ -93,6 +93,20 @@ __device__ __forceinline__ uint32_t shift_in_above(uint32_t w, double yq, double
     return __builtin_amdgcn_alignbit(w, hi, 31);
 }
 
+// True on every thread when v is true on every thread of the 256-thread
+// workgroup; also a workgroup barrier.  Each wavefront reduces with one
+// ballot and posts its verdict to flags (LDS, 4 words, rewritten on every
+// call, so nothing needs clearing); one barrier later every thread reads the
+// four.  A caller that calls it again must pass another barrier in between.
+__device__ __forceinline__ bool block_all(bool v, int *flags)
+{
+    const bool w = __builtin_amdgcn_ballot_w64(!v) == 0;
+    if ((threadIdx.x & 63) == 0)
+        flags[threadIdx.x >> 6] = w ? 1 : 0;
+    __syncthreads();
+    return (flags[0] & flags[1] & flags[2] & flags[3]) != 0;
+}
+
 // One 32-edge chunk of a wave-uniform ring with compacted side tests: edges
 // c0 .. c0+m-1 (m <= 32), i.e. vertices v_{c0-1} -> v_{c0} onwards.  The ring's
 // y values stream through scalar loads into each lane's 32-bit "above" word
