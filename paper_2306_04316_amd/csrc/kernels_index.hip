@@ -108,18 +108,41 @@ struct Tree {
     int n0, n1, n2;
 };
 
-// Lanes whose point lies in [lo, hi) may have straddling edges in the node.
-__device__ __forceinline__ bool node_hit(double y, double2 bnd, uint32_t &prev)
+// The nodes g0 .. g0+cnt-1 (cnt <= 64) of one tree level that may hold a
+// straddling edge for some lane: lane j loads node g0+j and tests its [lo, hi)
+// against the wavefront's y range [ylo, yhi] (a superset of the lanes'
+// exact tests: a node whose range misses it has every lane's y below lo or
+// at or above hi, so none of its edges straddles).  Returns the hit mask;
+// the lane keeps its node's bounds in `mine`.
+__device__ __forceinline__ uint64_t group_hits(const double2 *__restrict__ b, int g0, int cnt, double ylo, double yhi,
+                                               double2 &mine)
 {
-    const bool below = y < bnd.x;
-    const bool in = !below && y < bnd.y;
-    const bool any = __builtin_amdgcn_ballot_w64(in) != 0;
-    if (!any)
-        prev = below ? 1u : 0u;
-    return any;
+    const int lane = threadIdx.x & 63;
+    bool h = false;
+    mine = make_double2(0.0, 0.0);
+    if (lane < cnt) {
+        mine = b[g0 + lane];
+        h = mine.x <= yhi && mine.y > ylo;
+    }
+    return __builtin_amdgcn_ballot_w64(h);
 }
 
-// Rows of 64 y-ordered points against the one ring, walked through the tree.
+// Above bit of the last vertex of a skipped node (bounds held by lane j of
+// `mine`): every lane's y lies below its lo (all above) or at or above its hi.
+__device__ __forceinline__ uint32_t prev_after_skip(double y, const double2 &mine, int j)
+{
+    const uint64_t bits = (uint64_t)__double_as_longlong(mine.x);
+    const uint32_t lo_lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bits, j);
+    const uint32_t lo_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bits >> 32), j);
+    const double lo = __longlong_as_double((long long)(((uint64_t)lo_hi << 32) | lo_lo));
+    return y < lo ? 1u : 0u;
+}
+
+// Rows of 64 y-ordered points against the one ring, walked through the tree:
+// at each level a wavefront tests up to 64 sibling nodes with one vector load
+// and one ballot, then descends into the hit ones in ring order; before a hit
+// node whose predecessor was skipped (and after a skipped last node) each
+// lane's "above" bit is set from the skipped node's bounds.
 template <int PRED>
 __global__ __launch_bounds__(256) void k_runs_indexed_fp64(const double2 *__restrict__ spt,
                                                            const int32_t *__restrict__ sidx, int64_t n,
@@ -140,20 +163,54 @@ __global__ __launch_bounds__(256) void k_runs_indexed_fp64(const double2 *__rest
     if (k > 0) {
         const double yq = p.y + 0.0;
         uint32_t prev = shift_in_above(0u, yq, ry[k - 1]);
-        for (int g2 = 0; g2 < tr.n2; ++g2) {
-            if (!node_hit(p.y, tr.b2[g2], prev))
-                continue;
-            const int g1e = 32 * g2 + 32 < tr.n1 ? 32 * g2 + 32 : tr.n1;
-            for (int g1 = 32 * g2; g1 < g1e; ++g1) {
-                if (!node_hit(p.y, tr.b1[g1], prev))
-                    continue;
-                const int ce = 32 * g1 + 32 < tr.n0 ? 32 * g1 + 32 : tr.n0;
-                for (int c = 32 * g1; c < ce; ++c) {
-                    if (!node_hit(p.y, tr.b0[c], prev))
-                        continue;
-                    par ^= chunk_parity_uniform<PRED>(p.x, p.y, yq, member, rx, ry, k, 32 * c, prev);
+        double ylo = member ? p.y : INFINITY, yhi = member ? p.y : -INFINITY;
+        for (int o = 32; o > 0; o >>= 1) {
+            ylo = fmin(ylo, __shfl_xor(ylo, o, 64));
+            yhi = fmax(yhi, __shfl_xor(yhi, o, 64));
+        }
+        for (int a2 = 0; a2 < tr.n2; a2 += 64) {
+            const int c2 = tr.n2 - a2 < 64 ? tr.n2 - a2 : 64;
+            double2 m2;
+            uint64_t h2 = group_hits(tr.b2, a2, c2, ylo, yhi, m2);
+            int v2 = -1;   // last visited node of the group
+            while (h2) {
+                const int j2 = __builtin_ctzll(h2);
+                h2 &= h2 - 1;
+                if (j2 > 0 && v2 != j2 - 1)
+                    prev = prev_after_skip(p.y, m2, j2 - 1);
+                const int s1 = 32 * (a2 + j2);
+                const int c1 = tr.n1 - s1 < 32 ? tr.n1 - s1 : 32;
+                double2 m1;
+                uint64_t h1 = group_hits(tr.b1, s1, c1, ylo, yhi, m1);
+                int v1 = -1;
+                while (h1) {
+                    const int j1 = __builtin_ctzll(h1);
+                    h1 &= h1 - 1;
+                    if (j1 > 0 && v1 != j1 - 1)
+                        prev = prev_after_skip(p.y, m1, j1 - 1);
+                    const int s0 = 32 * (s1 + j1);
+                    const int c0 = tr.n0 - s0 < 32 ? tr.n0 - s0 : 32;
+                    double2 m0;
+                    uint64_t h0 = group_hits(tr.b0, s0, c0, ylo, yhi, m0);
+                    int v0 = -1;
+                    while (h0) {
+                        const int j0 = __builtin_ctzll(h0);
+                        h0 &= h0 - 1;
+                        if (j0 > 0 && v0 != j0 - 1)
+                            prev = prev_after_skip(p.y, m0, j0 - 1);
+                        par ^= chunk_parity_uniform<PRED>(p.x, p.y, yq, member, rx, ry, k, 32 * (s0 + j0), prev);
+                        v0 = j0;
+                    }
+                    if (v0 != c0 - 1)
+                        prev = prev_after_skip(p.y, m0, c0 - 1);
+                    v1 = j1;
                 }
+                if (v1 != c1 - 1)
+                    prev = prev_after_skip(p.y, m1, c1 - 1);
+                v2 = j2;
             }
+            if (v2 != c2 - 1)
+                prev = prev_after_skip(p.y, m2, c2 - 1);
         }
     }
     if (member)
