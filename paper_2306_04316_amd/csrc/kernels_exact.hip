@@ -520,8 +520,8 @@ __device__ __forceinline__ void staged_item_fp64(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = p0 + u * 256 + tid;
-            if (i < n)   // written once, not read back: streamed past the caches
-                __builtin_nontemporal_store((uint8_t)((mine >> u) & 1u), inside + i);
+            if (i < n)
+                inside[i] = (uint8_t)((mine >> u) & 1u);
         }
         return;
     }
