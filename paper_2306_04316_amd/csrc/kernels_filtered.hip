@@ -62,20 +62,41 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Append the lanes in `mask` (their pair indices i) to the recheck list.
-__device__ __forceinline__ void append_recheck(uint64_t mask, int64_t i, int32_t *list, unsigned *count)
+// The item's undecided pairs join the recheck list with one global atomic per
+// item (not one per wavefront and row: with many undecided pairs those
+// same-address atomics serialise): every wavefront reserves its share in an
+// LDS counter, thread 0 reserves the item's total in the list, then every
+// lane writes its own entries.  rows[u] is the wavefront's ballot of row u.
+// Must be called by the whole workgroup; s_cnt, s_base: LDS words, s_cnt
+// zeroed (and a barrier passed) since the last call.
+template <int U>
+__device__ __forceinline__ void append_recheck_item(const uint64_t (&rows)[U], int64_t p0, int32_t *list,
+                                                    unsigned *count, unsigned *s_cnt, unsigned *s_base)
 {
     const int lane = threadIdx.x & 63;
-    if (mask == 0)
-        return;
-    unsigned base = 0;
-    const int leader = __builtin_ctzll(mask);
-    if (lane == leader)
-        base = atomicAdd(count, (unsigned)__builtin_popcountll(mask));
-    base = __builtin_amdgcn_readlane(base, leader);
-    if ((mask >> lane) & 1u) {
-        const unsigned below = (unsigned)__builtin_popcountll(mask & ((1ull << lane) - 1ull));
-        list[base + below] = (int32_t)i;
+    unsigned mine = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        mine += (unsigned)__builtin_popcountll(rows[u]);
+    unsigned wbase = 0;
+    if (lane == 0 && mine)
+        wbase = atomicAdd(s_cnt, mine);
+    wbase = __builtin_amdgcn_readfirstlane(wbase);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned tot = *s_cnt;
+        *s_base = tot ? atomicAdd(count, tot) : 0u;
+    }
+    __syncthreads();
+    unsigned at = *s_base + wbase;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint64_t m = rows[u];
+        if ((m >> lane) & 1u) {
+            const unsigned below = (unsigned)__builtin_popcountll(m & ((1ull << lane) - 1ull));
+            list[at + below] = (int32_t)(p0 + u * 256 + threadIdx.x);
+        }
+        at += (unsigned)__builtin_popcountll(m);
     }
 }
 
@@ -247,8 +268,11 @@ __device__ __forceinline__ void filtered_item(
         YF[ytot + tid] = 0.0f;
     // block max of ring sizes (loop bound of the straddle pass)
     __shared__ int s_kmax;
-    if (tid == 0)
+    __shared__ unsigned s_rcnt, s_rbase;   // the item's undecided pairs, their list position
+    if (tid == 0) {
         s_kmax = 0;
+        s_rcnt = 0;
+    }
     __syncthreads();
     if (lane == 0)
         atomicMax(&s_kmax, kmax_local);
@@ -257,6 +281,7 @@ __device__ __forceinline__ void filtered_item(
 
     const float ks = kBoundK * bound_scale;
     const float eta = kEta4 * bound_scale;
+    uint64_t amb_rows[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t i = p0 + u * 256 + tid;
@@ -317,11 +342,11 @@ __device__ __forceinline__ void filtered_item(
         }
         amb = amb || zmin == 0.0f;
         const bool valid = i < n;
-        const uint64_t ambm = __builtin_amdgcn_ballot_w64(valid && amb);
+        amb_rows[u] = __builtin_amdgcn_ballot_w64(valid && amb);
         if (valid && !amb)
             inside[i] = (uint8_t)((par >> lane) & 1u);
-        append_recheck(ambm, i, recheck, recheck_count);
     }
+    append_recheck_item<U>(amb_rows, p0, recheck, recheck_count, &s_rcnt, &s_rbase);
 }
 
 template <int U>
