@@ -304,6 +304,71 @@ __device__ __forceinline__ uint32_t staged_ring_parity(const StagedLds &L, int e
 // Rings larger than the LDS edge budget are walked in tiles (see below);
 // only items with more rings or polygons than the tables hold, or with pairs
 // not sorted by polygon, take the scalar-load group walk.
+// Crossing parity of every lane's point against all rings of its polygon in
+// one pass, when the polygon's rings (rings r0 .. r1-1 of the staged table,
+// back to back from staged vertex e0, k <= 32 vertices in all) lie in one
+// chunk.  The straddle pass runs along the stored order; the bit of each
+// ring's first edge is then corrected to compare the ring's first vertex with
+// its own last vertex (its closing edge) instead of the previous ring's last
+// vertex.  The records of those closing edges are the ones staged at the
+// rings' first vertices, so the side tests are the per-ring walk's.  Returns
+// the lane's parity, the XOR over the rings.  Whole wavefront; T_base: the
+// staged position of the tile (or range) start.
+template <int PRED>
+__device__ __forceinline__ uint32_t staged_poly_parity1(const StagedLds &L, int e0, int k, int r0, int r1,
+                                                        int T_base, double xu, double yu, int y_alloc)
+{
+    const double yq = yu + 0.0;
+    uint32_t above = 0;
+    const double *yr = L.Y + (e0 < y_alloc - 32 ? e0 : y_alloc - 32);
+    int t = 0;
+    for (; t < 32; t += 4) {
+        if (__builtin_amdgcn_ballot_w64(k > t) == 0)
+            break;
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+            above = shift_in_above(above, yq, yr[t + tt]);
+    }
+    above = t < 32 ? above << (32 - t) : above;
+    uint32_t strad = above ^ (above >> 1);   // the first vertex's predecessor: fixed below
+    for (int step = 0;; ++step) {
+        const int rr = r0 + step;
+        const bool act = rr < r1;
+        if (__builtin_amdgcn_ballot_w64(act) == 0)
+            break;
+        if (act) {
+            const int s = L.T[rr] - T_base - e0, e = L.T[rr + 1] - T_base - e0;   // ring rr: [s, e)
+            if (e > s && s >= 0 && e <= k) {
+                const uint32_t last = (above >> (31 - (e - 1))) & 1u;
+                const uint32_t before = s > 0 ? (above >> (32 - s)) & 1u : 0u;
+                strad ^= (before ^ last) << (31 - s);
+            }
+        }
+    }
+    const int kc = k < 0 ? 0 : (k > 32 ? 32 : k);
+    strad &= (uint32_t)(0xffffffff00000000ull >> kc);
+    uint32_t cnt = 0;
+    const int elast = e0 + 31;
+    while (strad != 0) {
+        const int b = __builtin_ctz(strad);
+        strad &= strad - 1u;
+        const double4 rec = L.E[elast - b];
+        bool cr;
+        if (PRED == kIntersection) {
+            const double lam = (yu - rec.y) / rec.w;
+            const double xn = rec.x + lam * rec.z;
+            cr = xn >= xu;
+        } else {
+            const double t1 = xu - rec.x;
+            const double t2 = yu - rec.y;
+            const double sv = t1 * rec.z + t2 * rec.w;
+            cr = sv <= 0.0;
+        }
+        cnt += cr ? 1u : 0u;
+    }
+    return cnt & 1u;
+}
+
 // The staged record of edge (a, b): constraint 1 stores (a_x, a_y, n_x, n_y)
 // with the normal n = (b_y - a_y, a_x - b_x) negated when n_x < 0, constraint
 // 2 stores (a_x, a_y, d_x, d_y), d = b - a; binary64, as the rule states.
@@ -484,6 +549,16 @@ __device__ __forceinline__ void staged_item_fp64(
                     r1 = r1 < r0 ? r0 : r1;
                 }
                 uint32_t par = 0;
+                if (MR) {
+                    // all of the polygon's rings in one chunk of this tile: one pass
+                    const int pa = L.T[r0], pb = L.T[r1];
+                    const bool one = pb >= pa && pb - pa <= 32 && pa >= t0 && pb <= t1;
+                    if (__builtin_amdgcn_ballot_w64(!one) == 0) {
+                        par = staged_poly_parity1<PRED>(L, pa - t0, pb - pa, r0, r1, t0, x[u], y[u], y_alloc);
+                        mine ^= par << u;
+                        continue;
+                    }
+                }
                 for (int step = 0;; ++step) {
                     const int rr = r0 + step;
                     const bool act = rr < r1;
