@@ -55,7 +55,7 @@ WORKLOAD_TEXT = {
 PROFILED_TRAFFIC: dict = {
     # footprints, exact mode, k_staged_batched_fp64<0, 4, false, false, false>
     # (profiles/staged_footprints_exact.md: FETCH_SIZE and WRITE_SIZE scaled by the copy calibration)
-    (2, "exact", "f56316594ae9"): {"fetch_bytes": 220032621, "write_bytes": 10000000},
+    (2, "exact", "76c8ae46ea49"): {"fetch_bytes": 220030829, "write_bytes": 10000000},
 }
 
 
