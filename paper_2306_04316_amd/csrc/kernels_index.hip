@@ -108,23 +108,22 @@ struct Tree {
     int n0, n1, n2;
 };
 
-// The nodes g0 .. g0+cnt-1 (cnt <= 64) of one tree level that may hold a
-// straddling edge for some lane: lane j loads node g0+j and tests its [lo, hi)
-// against the wavefront's y range [ylo, yhi] (a superset of the lanes'
-// exact tests: a node whose range misses it has every lane's y below lo or
-// at or above hi, so none of its edges straddles).  Returns the hit mask;
-// the lane keeps its node's bounds in `mine`.
-__device__ __forceinline__ uint64_t group_hits(const double2 *__restrict__ b, int g0, int cnt, double ylo, double yhi,
-                                               double2 &mine)
+// The bounds of nodes g0 .. g0+cnt-1 (cnt <= 64) of one tree level, node
+// g0+j in lane j (zeros past cnt).  Issued ahead of their use (see below).
+__device__ __forceinline__ double2 group_load(const double2 *__restrict__ b, int g0, int cnt)
 {
     const int lane = threadIdx.x & 63;
-    bool h = false;
-    mine = make_double2(0.0, 0.0);
-    if (lane < cnt) {
-        mine = b[g0 + lane];
-        h = mine.x <= yhi && mine.y > ylo;
-    }
-    return __builtin_amdgcn_ballot_w64(h);
+    return lane < cnt ? b[g0 + lane] : make_double2(0.0, 0.0);
+}
+
+// Which of those nodes may hold a straddling edge for some lane: the node's
+// [lo, hi) against the wavefront's y range [ylo, yhi] (a superset of the
+// lanes' exact tests: a node whose range misses it has every lane's y below
+// lo or at or above hi, so none of its edges straddles).
+__device__ __forceinline__ uint64_t group_mask(const double2 &mine, int cnt, double ylo, double yhi)
+{
+    const int lane = threadIdx.x & 63;
+    return __builtin_amdgcn_ballot_w64(lane < cnt && mine.x <= yhi && mine.y > ylo);
 }
 
 // Above bit of the last vertex of a skipped node (bounds held by lane j of
@@ -136,6 +135,76 @@ __device__ __forceinline__ uint32_t prev_after_skip(double y, const double2 &min
     const uint32_t lo_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bits >> 32), j);
     const double lo = __longlong_as_double((long long)(((uint64_t)lo_hi << 32) | lo_lo));
     return y < lo ? 1u : 0u;
+}
+
+constexpr int kLeafBatch = 4;   // leaves staged per wavefront at a time
+constexpr int kLeafSlot = 40;   // doubles per staged leaf and coordinate (33 used)
+
+// Stage up to kLeafBatch hit leaves of one level-0 group (leaf ids c[b],
+// b < nb) in the wavefront's LDS slice: leaf b's vertices c0-1 .. c0+m-1
+// (c0 = 32 c[b], the ring's last vertex before vertex 0) at slot b.  All
+// loads are issued before any is stored, so a batch costs one memory round
+// trip.
+__device__ __forceinline__ void stage_leaves(const double *__restrict__ rx, const double *__restrict__ ry, int k,
+                                             const int (&c)[kLeafBatch], int nb, double *sx, double *sy)
+{
+    const int lane = threadIdx.x & 63;
+    double lx[kLeafBatch], ly[kLeafBatch];
+#pragma unroll
+    for (int b = 0; b < kLeafBatch; ++b) {
+        lx[b] = 0.0;
+        ly[b] = 0.0;
+        const int c0 = 32 * c[b];
+        const int m = k - c0 < 32 ? k - c0 : 32;
+        if (b < nb && lane <= m) {
+            const int j = c0 - 1 + lane;
+            const int jj = j < 0 ? k - 1 : j;
+            lx[b] = rx[jj];
+            ly[b] = ry[jj];
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < kLeafBatch; ++b) {
+        const int c0 = 32 * c[b];
+        const int m = k - c0 < 32 ? k - c0 : 32;
+        if (b < nb && lane <= m) {
+            sx[b * kLeafSlot + lane] = lx[b];
+            sy[b * kLeafSlot + lane] = ly[b];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One staged 32-edge leaf (edges ending at vertices c0 .. c0+m-1, m <= 32;
+// sx, sy: its slot, entry 0 = vertex c0-1) for the wavefront's points: the
+// straddle pass and each lane's side tests read the slot.  `prev`: the above
+// bit of vertex c0-1 on entry, of the leaf's last vertex on exit.
+template <int PRED>
+__device__ __forceinline__ uint64_t leaf_parity_lds(double x, double y, double yq, bool member, int m, uint32_t &prev,
+                                                    const double *sx, const double *sy)
+{
+    uint32_t above = 0;
+    int t = 0;
+    for (; t < m; t += 4) {
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+            above = shift_in_above(above, yq, sy[1 + (t + tt < m ? t + tt : m - 1)]);
+    }
+    above = t < 32 ? above << (32 - t) : above;
+    uint32_t strad = above ^ ((above >> 1) | (prev << 31));
+    strad &= (uint32_t)(0xffffffff00000000ull >> m);
+    prev = (above >> (32 - m)) & 1u;
+    strad = member ? strad : 0u;
+    uint64_t par = 0;
+    while (strad != 0) {
+        const int j = __builtin_clz(strad);   // edge (vertex c0+j-1, vertex c0+j)
+        strad ^= 0x80000000u >> j;
+        const bool b_above = (above >> (31 - j)) & 1u;
+        par ^= __builtin_amdgcn_ballot_w64(straddle_crosses<PRED>(x, y, sx[j], sy[j], sx[j + 1], sy[j + 1], b_above));
+    }
+    return par;
 }
 
 // Rows of 64 y-ordered points against the one ring, walked through the tree:
@@ -159,10 +228,16 @@ __global__ __launch_bounds__(256) void k_runs_indexed_fp64(const double2 *__rest
         p = spt[i];
         idx = sidx[i];
     }
+    __shared__ double s_leaf[4][2][kLeafBatch * kLeafSlot];   // per wavefront: staged leaves' x and y
+    double *sx = s_leaf[threadIdx.x >> 6][0], *sy = s_leaf[threadIdx.x >> 6][1];
+    // the top level's bounds and the ring's last y do not depend on the points:
+    // their loads go out with the points'
+    double2 m2 = group_load(tr.b2, 0, tr.n2 < 64 ? tr.n2 : 64);
+    const double ylast = k > 0 ? ry[k - 1] : 0.0;
     uint64_t par = 0;
     if (k > 0) {
         const double yq = p.y + 0.0;
-        uint32_t prev = shift_in_above(0u, yq, ry[k - 1]);
+        uint32_t prev = shift_in_above(0u, yq, ylast);
         double ylo = member ? p.y : INFINITY, yhi = member ? p.y : -INFINITY;
         for (int o = 32; o > 0; o >>= 1) {
             ylo = fmin(ylo, __shfl_xor(ylo, o, 64));
@@ -170,36 +245,79 @@ __global__ __launch_bounds__(256) void k_runs_indexed_fp64(const double2 *__rest
         }
         for (int a2 = 0; a2 < tr.n2; a2 += 64) {
             const int c2 = tr.n2 - a2 < 64 ? tr.n2 - a2 : 64;
-            double2 m2;
-            uint64_t h2 = group_hits(tr.b2, a2, c2, ylo, yhi, m2);
+            uint64_t h2 = group_mask(m2, c2, ylo, yhi);
+            // the children of the next hit node are loaded while the current
+            // one's subtree is walked (one level at a time, in ring order)
+            int s1n = 0, c1n = 0;
+            double2 m1n = make_double2(0.0, 0.0);
+            if (h2) {
+                s1n = 32 * (a2 + __builtin_ctzll(h2));
+                c1n = tr.n1 - s1n < 32 ? tr.n1 - s1n : 32;
+                m1n = group_load(tr.b1, s1n, c1n);
+            }
             int v2 = -1;   // last visited node of the group
             while (h2) {
                 const int j2 = __builtin_ctzll(h2);
                 h2 &= h2 - 1;
                 if (j2 > 0 && v2 != j2 - 1)
                     prev = prev_after_skip(p.y, m2, j2 - 1);
-                const int s1 = 32 * (a2 + j2);
-                const int c1 = tr.n1 - s1 < 32 ? tr.n1 - s1 : 32;
-                double2 m1;
-                uint64_t h1 = group_hits(tr.b1, s1, c1, ylo, yhi, m1);
+                const int s1 = s1n, c1 = c1n;
+                const double2 m1 = m1n;
+                if (h2) {
+                    s1n = 32 * (a2 + __builtin_ctzll(h2));
+                    c1n = tr.n1 - s1n < 32 ? tr.n1 - s1n : 32;
+                    m1n = group_load(tr.b1, s1n, c1n);
+                }
+                uint64_t h1 = group_mask(m1, c1, ylo, yhi);
+                int s0n = 0, c0n = 0;
+                double2 m0n = make_double2(0.0, 0.0);
+                if (h1) {
+                    s0n = 32 * (s1 + __builtin_ctzll(h1));
+                    c0n = tr.n0 - s0n < 32 ? tr.n0 - s0n : 32;
+                    m0n = group_load(tr.b0, s0n, c0n);
+                }
                 int v1 = -1;
                 while (h1) {
                     const int j1 = __builtin_ctzll(h1);
                     h1 &= h1 - 1;
                     if (j1 > 0 && v1 != j1 - 1)
                         prev = prev_after_skip(p.y, m1, j1 - 1);
-                    const int s0 = 32 * (s1 + j1);
-                    const int c0 = tr.n0 - s0 < 32 ? tr.n0 - s0 : 32;
-                    double2 m0;
-                    uint64_t h0 = group_hits(tr.b0, s0, c0, ylo, yhi, m0);
+                    const int s0 = s0n, c0 = c0n;
+                    const double2 m0 = m0n;
+                    if (h1) {
+                        s0n = 32 * (s1 + __builtin_ctzll(h1));
+                        c0n = tr.n0 - s0n < 32 ? tr.n0 - s0n : 32;
+                        m0n = group_load(tr.b0, s0n, c0n);
+                    }
+                    uint64_t h0 = group_mask(m0, c0, ylo, yhi);
                     int v0 = -1;
                     while (h0) {
-                        const int j0 = __builtin_ctzll(h0);
-                        h0 &= h0 - 1;
-                        if (j0 > 0 && v0 != j0 - 1)
-                            prev = prev_after_skip(p.y, m0, j0 - 1);
-                        par ^= chunk_parity_uniform<PRED>(p.x, p.y, yq, member, rx, ry, k, 32 * (s0 + j0), prev);
-                        v0 = j0;
+                        // the next (up to) kLeafBatch hit leaves, staged together
+                        int ids[kLeafBatch], cs[kLeafBatch];
+                        int nb = 0;
+#pragma unroll
+                        for (int b = 0; b < kLeafBatch; ++b) {
+                            ids[b] = 0;
+                            if (h0) {
+                                ids[b] = __builtin_ctzll(h0);
+                                h0 &= h0 - 1;
+                                nb = b + 1;
+                            }
+                            cs[b] = s0 + ids[b];
+                        }
+                        stage_leaves(rx, ry, k, cs, nb, sx, sy);
+                        for (int b = 0; b < nb; ++b) {
+                            const int j0 = ids[b];
+                            if (j0 > 0 && v0 != j0 - 1)
+                                prev = prev_after_skip(p.y, m0, j0 - 1);
+                            const int lc0 = 32 * cs[b];
+                            const int m = k - lc0 < 32 ? k - lc0 : 32;
+                            par ^= leaf_parity_lds<PRED>(p.x, p.y, yq, member, m, prev, sx + b * kLeafSlot,
+                                                         sy + b * kLeafSlot);
+                            v0 = j0;
+                        }
+                        // every lane is done with the slice before the next batch rewrites it
+                        __builtin_amdgcn_wave_barrier();
                     }
                     if (v0 != c0 - 1)
                         prev = prev_after_skip(p.y, m0, c0 - 1);
@@ -211,6 +329,9 @@ __global__ __launch_bounds__(256) void k_runs_indexed_fp64(const double2 *__rest
             }
             if (v2 != c2 - 1)
                 prev = prev_after_skip(p.y, m2, c2 - 1);
+            // the next group of top-level nodes (rings of more than 2^21 vertices)
+            if (a2 + 64 < tr.n2)
+                m2 = group_load(tr.b2, a2 + 64, tr.n2 - a2 - 64 < 64 ? tr.n2 - a2 - 64 : 64);
         }
     }
     if (member)
