@@ -331,7 +331,10 @@ PIP_API int pip_join_create(pip_join **out, const double *px, const double *py, 
 PIP_API int pip_join_fill(pip_join *join, int64_t *pair_point, int32_t *pair_poly,
                   double *pair_px, double *pair_py, void *stream);
 
-/* Waits for the device, then releases the join's workspace.  NULL is a no-op. */
+/* Waits for the device, then releases the join's workspace.  NULL is a no-op.
+ * The workspace comes from a device-memory pool of the library's own (one per
+ * device), which keeps released memory for later joins instead of returning
+ * it to the driver (at most what the joins alive at one time held). */
 PIP_API int pip_join_destroy(pip_join *join);
 
 /*
