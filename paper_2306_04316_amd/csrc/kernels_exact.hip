@@ -130,9 +130,12 @@ __global__ __launch_bounds__(256) void k_segmented_fp64(
 //   2. side tests only for its straddling edges, taken one set bit at a time:
 //      s = (p_x - a_x) * n_x + (p_y - a_y) * n_y, crossing iff s <= 0.
 // Only about 2 of a footprint's edges straddle a given point, so phase 2 is
-// short; phase 1 costs two vector instructions per vertex.
-// A workgroup whose rings do not fit (or whose pairs are not sorted) falls
-// back to the scalar-load group walk.
+// short; phase 1 costs two vector instructions per vertex.  A polygon of
+// several rings that together fit one chunk takes a single pass over all of
+// them (staged_poly_parity1); otherwise its rings are walked one by one.
+// A vertex range larger than the LDS budget is walked in tiles (the TILES
+// form); in the plain form such an item, like one whose pairs are not sorted
+// by polygon, takes the scalar-load group walk.
 struct StagedLds {
     int *T;    // ring starts, relative to the range start
     int *PR;   // polygons of several rings: first ring of each polygon (relative)
