@@ -275,3 +275,24 @@ def test_bench_configuration_full(P, config):
     got = pl.out.cpu().numpy()
     pl.close()
     assert_same_mask(got, oracle.classify_workload(w), f"bench configuration {config}", w.px, w.py, w.point_poly)
+
+
+def test_plan_index_more_than_64_top_nodes(P):
+    """A ring of 2.2 million vertices has 68 top-level nodes, more than one
+    wavefront tests at once: the walk's second group of top nodes, sampled."""
+    rng = np.random.default_rng(31)
+    k = 2_200_000
+    t = np.sort(rng.uniform(0, 2 * np.pi, k))
+    r = 1.0 + 0.05 * rng.uniform(-1, 1, k)
+    vx, vy = r * np.cos(t), r * np.sin(t)
+    n = 20_000
+    px = rng.uniform(-1.1, 1.1, n)
+    py = rng.uniform(-1.1, 1.1, n)
+    py[:200] = vy[rng.integers(0, k, 200)]
+    w = W.Workload("big-ring", px, py, np.array([0, k], dtype=np.int64), vx, vy, None, {})
+    note("index ring of 2.2M vertices")
+    got, st, cfg = plan_run(P, w, index=True)
+    assert cfg["index"] == 1
+    idx = np.sort(rng.choice(n, 600, replace=False))
+    s = W.subsample(w, idx)
+    assert_same_mask(got[idx], oracle.classify_workload(s), "index 2.2M-vertex ring (sampled)", s.px, s.py)

@@ -154,3 +154,47 @@ def test_rings_rejections(P):
     with pytest.raises(P.PipError) as e:
         P.classify_rings(d["px"], d["py"], bad, d["offsets"], d["vx"], d["vy"], d["point_poly"], validate=True)
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("predicate", ["side", "intersection"])
+@pytest.mark.parametrize("lds", [64, 256])
+def test_rings_one_pass_boundary(P, predicate, lds):
+    """Polygons whose rings together hold 31, 32 and 33 vertices (one-pass path
+    on both sides of the chunk size), rings of 1-3 vertices among them, and
+    points on and level with vertices: one pass or ring by ring, same bits."""
+    rng = np.random.default_rng(21)
+    vx, vy, roff, prings, px, py, pp = [], [], [0], [0], [], [], []
+    q = 0
+    for total in (31, 32, 33, 30, 32, 34):
+        sizes = []
+        left = total
+        while left > 0:
+            s = int(min(left, rng.integers(1, 12)))
+            sizes.append(s)
+            left -= s
+        cx = 5.0 * q
+        for r, s in enumerate(sizes):
+            t = np.sort(rng.uniform(0, 2 * np.pi, s))
+            rad = rng.uniform(0.3, 1.0, s) * (1.0 if r == 0 else 0.4)
+            x, y = cx + rad * np.cos(t), rad * np.sin(t)
+            vx += list(x)
+            vy += list(y)
+            roff.append(roff[-1] + s)
+        prings.append(prings[-1] + len(sizes))
+        m = 700
+        qx = rng.uniform(cx - 1.1, cx + 1.1, m)
+        qy = rng.uniform(-1.1, 1.1, m)
+        lo, hi = roff[prings[q]], roff[prings[q + 1]]
+        j = rng.integers(lo, hi, m // 5)
+        qy[: m // 5] = np.array(vy)[j]                          # level with vertices
+        qx[: m // 10] = np.array(vx)[j[: m // 10]]              # on vertices
+        px.append(qx)
+        py.append(qy)
+        pp.append(np.full(m, q, dtype=np.int32))
+        q += 1
+    w = W.Workload("rings-one-pass", np.concatenate(px), np.concatenate(py), np.array(roff, dtype=np.int64),
+                   np.array(vx), np.array(vy), np.concatenate(pp), {}, poly_rings=np.array(prings, dtype=np.int64))
+    note(f"rings one pass predicate={predicate} lds={lds}")
+    want = oracle.classify_workload(w, predicate=pred_num(predicate))
+    got = run_classify(P, w, kernel="staged", lds_slots=lds, predicate=predicate)
+    assert_same_mask(got, want, f"rings one pass {predicate} lds={lds}", w.px, w.py, w.point_poly)
