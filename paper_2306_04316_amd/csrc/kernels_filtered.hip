@@ -48,20 +48,6 @@ __device__ __forceinline__ bool normal_ok(double v)
     return a == 0.0 || (a >= kTiny && a <= kLim);
 }
 
-__device__ __forceinline__ double wave_min(double v)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ double wave_max(double v)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 // The item's undecided pairs join the recheck list with one global atomic per
 // item (not one per wavefront and row: with many undecided pairs those
 // same-address atomics serialise): every wavefront reserves its share in an
@@ -111,6 +97,7 @@ size_t filtered_smem_bytes(int max_edges, int max_rings)
     o += ((((size_t)max_edges + max_rings + 64) * 4 + 15) & ~(size_t)15);
     o += (size_t)max_edges * 16;
     o += (size_t)max_edges * 16;
+    o += (size_t)max_rings * 36;   // per ring: four bounding-box keys and a flag
     return o;
 }
 
@@ -121,6 +108,37 @@ struct RingInfo {
     float m;        // bound on |v - c| (rounded up), or -1 when the ring is not filterable
     int pad[3];
 };
+
+// Order-preserving unsigned key of a binary64 value (finite inputs): unsigned
+// comparison of keys is the floating-point order, so LDS integer atomics give
+// exact minima and maxima.
+__device__ __forceinline__ unsigned long long order_key(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double from_order_key(unsigned long long k)
+{
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+// Ring of staged vertex e: the r with T[r] <= e < T[r+1]; -1 when the table is
+// not sorted around e (offsets not monotone: unspecified results, accesses in
+// bounds).
+__device__ __forceinline__ int ring_of_vertex(const int *T, int nr, int e)
+{
+    int lo = 0, hi = nr;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (T[mid] <= e)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return (T[lo] <= e && e < T[lo + 1]) ? lo : -1;
+}
 
 template <int U>
 __device__ __forceinline__ void filtered_item(
@@ -133,7 +151,6 @@ __device__ __forceinline__ void filtered_item(
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wid = tid >> 6;
     const int ypad = 64;
     const int y_alloc = max_edges + max_rings + ypad;
 
@@ -181,9 +198,25 @@ __device__ __forceinline__ void filtered_item(
     o += (size_t)max_edges * 16;
     double *XD = (double *)(smem + o);
     double *YD = XD + max_edges;
+    o += (size_t)max_edges * 16;
+    unsigned long long *KB = (unsigned long long *)(smem + o);   // per ring: x min, x max, y min, y max keys
+    int *BAD = (int *)(KB + 4 * (size_t)max_rings);              // per ring: a normal out of the filter's range
+    __shared__ int s_kmax;
+    __shared__ unsigned s_rcnt, s_rbase;   // the item's undecided pairs, their list position
 
     // the ring table and the binary64 vertices in one round of loads
+    if (tid == 0) {
+        s_kmax = 0;
+        s_rcnt = 0;
+    }
     if (fits) {
+        for (int r = tid; r < nr; r += 256) {
+            KB[4 * r + 0] = ~0ull;
+            KB[4 * r + 1] = 0ull;
+            KB[4 * r + 2] = ~0ull;
+            KB[4 * r + 3] = 0ull;
+            BAD[r] = 0;
+        }
         for (int r = tid; r <= nr; r += 256) {
             int64_t ov = offsets[qf + r];
             ov = ov < vb ? vb : (ov > ve ? ve : ov);
@@ -208,74 +241,71 @@ __device__ __forceinline__ void filtered_item(
         return;
     }
 
-    // per ring (one wavefront each): centre, radius and binary32 records,
-    // from the staged vertices
-    int kmax_local = 0;
-    for (int r = wid; r < nr; r += 4) {
+    // Per ring: bounding box (LDS atomics on order keys, one thread per
+    // vertex), then centre, radius bound and eligibility (one thread per
+    // ring), then the binary32 records (one thread per vertex).  A vertex's
+    // ring comes from a binary search of T; its predecessor in the ring is the
+    // ring's last vertex for the ring's first vertex.
+    for (int e = tid; e < nvr; e += 256) {
+        const int r = ring_of_vertex(T, nr, e);
+        if (r < 0)
+            continue;
+        const double a = XD[e], b = YD[e];
+        atomicMin(&KB[4 * r + 0], order_key(a));
+        atomicMax(&KB[4 * r + 1], order_key(a));
+        atomicMin(&KB[4 * r + 2], order_key(b));
+        atomicMax(&KB[4 * r + 3], order_key(b));
+        const int ep = e == T[r] ? T[r + 1] - 1 : e - 1;
+        const double nx = b - YD[ep], ny = XD[ep] - a;   // the normal before orientation: the same magnitudes
+        if (!(normal_ok(nx) && normal_ok(ny)))
+            BAD[r] = 1;
+    }
+    __syncthreads();
+    for (int r = tid; r < nr; r += 256) {
         const int e0 = T[r];
         int e1 = T[r + 1];
         e1 = e1 < e0 ? e0 : e1;
         const int k = e1 - e0;
-        kmax_local = k > kmax_local ? k : kmax_local;
-        const double *rx = XD + e0;
-        const double *ry = YD + e0;
-        // bounding box -> centre, radius
-        double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
-        bool ok = true;
-        for (int j = lane; j < k; j += 64) {
-            const double a = rx[j], b = ry[j];
-            xmn = fmin(xmn, a);
-            xmx = fmax(xmx, a);
-            ymn = fmin(ymn, b);
-            ymx = fmax(ymx, b);
+        double cx = 0.0, cy = 0.0, m = 0.0;
+        if (k > 0) {
+            const double xmn = from_order_key(KB[4 * r + 0]), xmx = from_order_key(KB[4 * r + 1]);
+            const double ymn = from_order_key(KB[4 * r + 2]), ymx = from_order_key(KB[4 * r + 3]);
+            cx = 0.5 * xmn + 0.5 * xmx;
+            cy = 0.5 * ymn + 0.5 * ymx;
+            m = fmax(fmax(fabs(xmn - cx), fabs(xmx - cx)), fmax(fabs(ymn - cy), fabs(ymx - cy)));
         }
-        xmn = wave_min(xmn);
-        xmx = wave_max(xmx);
-        ymn = wave_min(ymn);
-        ymx = wave_max(ymx);
-        const double cx = k > 0 ? 0.5 * xmn + 0.5 * xmx : 0.0;
-        const double cy = k > 0 ? 0.5 * ymn + 0.5 * ymx : 0.0;
-        const double m = k > 0 ? fmax(fmax(fabs(xmn - cx), fabs(xmx - cx)), fmax(fabs(ymn - cy), fabs(ymx - cy)))
-                               : 0.0;
-        const int yb = e0 + r;
-        for (int j = lane; j < k; j += 64) {
-            const int jp = j == 0 ? k - 1 : j - 1;
-            const double ax = rx[jp], ay = ry[jp], bx = rx[j], by = ry[j];
-            double nx = by - ay;
-            double ny = ax - bx;
-            if (nx < 0.0) {
-                nx = -nx;
-                ny = -ny;
-            }
-            ok = ok && normal_ok(nx) && normal_ok(ny);
-            EF[e0 + j] = make_float4((float)(ax - cx), (float)(ay - cy), (float)nx, (float)ny);
-            const float yv = (float)(by - cy);
-            YF[yb + 1 + j] = yv;
-            if (j == k - 1)
-                YF[yb] = yv;
+        const bool ring_ok = !BAD[r] && k > 0 && m <= kLim;
+        RingInfo ri;
+        ri.cx = cx;
+        ri.cy = cy;
+        ri.m = ring_ok ? __double2float_ru(m) : -1.0f;
+        R[r] = ri;
+        atomicMax(&s_kmax, k);
+    }
+    __syncthreads();
+    for (int e = tid; e < nvr; e += 256) {
+        const int r = ring_of_vertex(T, nr, e);
+        if (r < 0)
+            continue;
+        const int e0 = T[r], e1 = T[r + 1];
+        const int ep = e == e0 ? e1 - 1 : e - 1;
+        const double cx = R[r].cx, cy = R[r].cy;
+        const double ax = XD[ep], ay = YD[ep], bx = XD[e], by = YD[e];
+        double nx = by - ay;
+        double ny = ax - bx;
+        if (nx < 0.0) {
+            nx = -nx;
+            ny = -ny;
         }
-        const bool ring_ok = __builtin_amdgcn_ballot_w64(!ok) == 0 && k > 0 && m <= kLim;
-        if (lane == 0) {
-            RingInfo ri;
-            ri.cx = cx;
-            ri.cy = cy;
-            ri.m = ring_ok ? __double2float_ru(m) : -1.0f;
-            R[r] = ri;
-        }
+        EF[e] = make_float4((float)(ax - cx), (float)(ay - cy), (float)nx, (float)ny);
+        const float yv = (float)(by - cy);
+        YF[e + r + 1] = yv;
+        if (e == e1 - 1)
+            YF[e0 + r] = yv;
     }
     const int ytot = (int)(ve - vb) + nr;
     if (tid < ypad)
         YF[ytot + tid] = 0.0f;
-    // block max of ring sizes (loop bound of the straddle pass)
-    __shared__ int s_kmax;
-    __shared__ unsigned s_rcnt, s_rbase;   // the item's undecided pairs, their list position
-    if (tid == 0) {
-        s_kmax = 0;
-        s_rcnt = 0;
-    }
-    __syncthreads();
-    if (lane == 0)
-        atomicMax(&s_kmax, kmax_local);
     __syncthreads();
     const int kmax_b = s_kmax;
 
