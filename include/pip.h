@@ -129,7 +129,7 @@ typedef struct {
     int32_t pairs_per_lane; /* tuning, segmented kernel: pairs per lane (1, 2, 4, 8); 0 = default */
     int32_t block;          /* tuning: threads per workgroup (64, 128, 256); 0 = default */
     int32_t lds_slots;      /* tuning, staged kernel: edges a workgroup can stage in
-                               LDS (48 bytes each exact, 36 filtered; at most 2048);
+                               LDS (48 bytes each exact, 37 filtered; at most 2048);
                                0 = default */
     int32_t persistent;     /* plans: 1 = a resident grid walks the work items
                                (staged exact kernel: fixed stride, polygon ranges

@@ -3,7 +3,7 @@
 //
 // Per workgroup item (256*U consecutive pairs, sorted by polygon) the rings'
 // binary64 vertices are first copied to LDS in one coalesced round with the
-// ring table; from there one wavefront per ring derives, re-centred on the
+// ring table; from there one thread per vertex derives, re-centred on the
 // ring's bounding-box centre c:
 //   YF : fl32(fl64(y_j - c_y)) per vertex (straddle pass)
 //   EF : (XI, YI, NX, NY) = fl32 of fl64(a - c) and of the rule's binary64
@@ -14,6 +14,10 @@
 // For a pair, P = fl32(fl64(p - c)).  Straddle: rounding is monotone, so a
 // strict binary32 order between P_y and a vertex's YF implies the same
 // strict binary64 order between p_y and y_v; equal values are undecided.
+// The order is read from the sign bits of both differences, P_y - YF and
+// YF - P_y: with no negative zeros among the operands, both are +0 exactly
+// when the values are equal (or when a flushed subnormal difference makes
+// them so: undecided as well).
 // Side: S = fl32(fl32(P_x - XI) * NX + fl32(P_y - YI) * NY).  With M >= every
 // re-centred coordinate of the pair (point and ring) and u = 2^-24,
 //   |S - E| <= 10.03 u M (|NX| + |NY|) + 4 eta (|NX| + |NY| + 1),
@@ -91,13 +95,15 @@ __device__ __forceinline__ void append_recheck_item(const uint64_t (&rows)[U], i
 size_t filtered_smem_bytes(int max_edges, int max_rings)
 {
     // T int[max_rings+1] | ring table 32 B per ring | YF float[max_edges+max_rings+64] | EF float4[max_edges]
-    // | XD, YD double[max_edges] (the staged binary64 vertices)
+    // | XD, YD double[max_edges] (the staged binary64 vertices) | per ring: four bounding-box keys and a
+    // flag | RID: each staged vertex's ring, one byte
     size_t o = (((size_t)(max_rings + 1) * 4 + 15) & ~(size_t)15);
     o += (size_t)max_rings * 32;
     o += ((((size_t)max_edges + max_rings + 64) * 4 + 15) & ~(size_t)15);
     o += (size_t)max_edges * 16;
     o += (size_t)max_edges * 16;
-    o += (size_t)max_rings * 36;   // per ring: four bounding-box keys and a flag
+    o += (size_t)max_rings * 36;
+    o += ((size_t)max_edges + 15) & ~(size_t)15;
     return o;
 }
 
@@ -201,6 +207,7 @@ __device__ __forceinline__ void filtered_item(
     o += (size_t)max_edges * 16;
     unsigned long long *KB = (unsigned long long *)(smem + o);   // per ring: x min, x max, y min, y max keys
     int *BAD = (int *)(KB + 4 * (size_t)max_rings);              // per ring: a normal out of the filter's range
+    signed char *RID = (signed char *)(BAD + max_rings);         // per vertex: its ring (max_rings <= 128), or -1
     __shared__ int s_kmax;
     __shared__ unsigned s_rcnt, s_rbase;   // the item's undecided pairs, their list position
 
@@ -242,12 +249,14 @@ __device__ __forceinline__ void filtered_item(
     }
 
     // Per ring: bounding box (LDS atomics on order keys, one thread per
-    // vertex), then centre, radius bound and eligibility (one thread per
-    // ring), then the binary32 records (one thread per vertex).  A vertex's
-    // ring comes from a binary search of T; its predecessor in the ring is the
-    // ring's last vertex for the ring's first vertex.
+    // vertex; the vertex's ring from a binary search of T, kept for the next
+    // pass), then per vertex its binary32 records, each thread deriving the
+    // ring's centre from the keys itself; the thread of a ring's first vertex
+    // also stores the ring's centre, radius bound and eligibility.  A
+    // vertex's predecessor is the ring's last vertex for its first vertex.
     for (int e = tid; e < nvr; e += 256) {
         const int r = ring_of_vertex(T, nr, e);
+        RID[e] = (signed char)r;
         if (r < 0)
             continue;
         const double a = XD[e], b = YD[e];
@@ -260,36 +269,36 @@ __device__ __forceinline__ void filtered_item(
         if (!(normal_ok(nx) && normal_ok(ny)))
             BAD[r] = 1;
     }
-    __syncthreads();
     for (int r = tid; r < nr; r += 256) {
-        const int e0 = T[r];
-        int e1 = T[r + 1];
-        e1 = e1 < e0 ? e0 : e1;
-        const int k = e1 - e0;
-        double cx = 0.0, cy = 0.0, m = 0.0;
-        if (k > 0) {
-            const double xmn = from_order_key(KB[4 * r + 0]), xmx = from_order_key(KB[4 * r + 1]);
-            const double ymn = from_order_key(KB[4 * r + 2]), ymx = from_order_key(KB[4 * r + 3]);
-            cx = 0.5 * xmn + 0.5 * xmx;
-            cy = 0.5 * ymn + 0.5 * ymx;
-            m = fmax(fmax(fabs(xmn - cx), fabs(xmx - cx)), fmax(fabs(ymn - cy), fabs(ymx - cy)));
+        if (T[r + 1] <= T[r]) {   // no vertex: never filtered
+            RingInfo ri;
+            ri.cx = 0.0;
+            ri.cy = 0.0;
+            ri.m = -1.0f;
+            R[r] = ri;
         }
-        const bool ring_ok = !BAD[r] && k > 0 && m <= kLim;
-        RingInfo ri;
-        ri.cx = cx;
-        ri.cy = cy;
-        ri.m = ring_ok ? __double2float_ru(m) : -1.0f;
-        R[r] = ri;
-        atomicMax(&s_kmax, k);
     }
     __syncthreads();
     for (int e = tid; e < nvr; e += 256) {
-        const int r = ring_of_vertex(T, nr, e);
+        const int r = RID[e];
         if (r < 0)
             continue;
         const int e0 = T[r], e1 = T[r + 1];
+        const double xmn = from_order_key(KB[4 * r + 0]), xmx = from_order_key(KB[4 * r + 1]);
+        const double ymn = from_order_key(KB[4 * r + 2]), ymx = from_order_key(KB[4 * r + 3]);
+        const double cx = 0.5 * xmn + 0.5 * xmx;
+        const double cy = 0.5 * ymn + 0.5 * ymx;
+        if (e == e0) {
+            const double m = fmax(fmax(fabs(xmn - cx), fabs(xmx - cx)), fmax(fabs(ymn - cy), fabs(ymx - cy)));
+            const bool ring_ok = !BAD[r] && m <= kLim;
+            RingInfo ri;
+            ri.cx = cx;
+            ri.cy = cy;
+            ri.m = ring_ok ? __double2float_ru(m) : -1.0f;
+            R[r] = ri;
+            atomicMax(&s_kmax, e1 - e0);
+        }
         const int ep = e == e0 ? e1 - 1 : e - 1;
-        const double cx = R[r].cx, cy = R[r].cy;
         const double ax = XD[ep], ay = YD[ep], bx = XD[e], by = YD[e];
         double nx = by - ay;
         double ny = ax - bx;
@@ -298,7 +307,9 @@ __device__ __forceinline__ void filtered_item(
             ny = -ny;
         }
         EF[e] = make_float4((float)(ax - cx), (float)(ay - cy), (float)nx, (float)ny);
-        const float yv = (float)(by - cy);
+        // +0.0f: no negative zero, so that equal binary32 values give two zero
+        // differences below, whatever their signs
+        const float yv = (float)(by - cy) + 0.0f;
         YF[e + r + 1] = yv;
         if (e == e1 - 1)
             YF[e0 + r] = yv;
@@ -328,12 +339,14 @@ __device__ __forceinline__ void filtered_item(
         const float kmt = ks * mp + eta;
         const float PYq = PY + 0.0f;
         uint64_t par = 0;
-        float zmin = k > 0 ? fabsf(PYq - YF[yb]) : 1.0f;
         uint32_t above_prev = (k > 0 && (__float_as_uint(PYq - YF[yb]) >> 31)) ? 1u : 0u;
+        uint32_t zero = 0;   // ring vertices whose binary32 y equals the point's (undecided order)
         for (int c0 = 0; c0 < kmax_b; c0 += 32) {
             if (__builtin_amdgcn_ballot_w64(k > c0) == 0)
                 break;
-            uint32_t above = 0;
+            // sign bits of P_y - y_v (the vertex is above) and of y_v - P_y
+            // (below); neither is set exactly when the two are equal
+            uint32_t above = 0, below = 0;
             const int ybase = yb + 1 + c0;
             const float *yp = YF + (ybase < y_alloc - 32 ? ybase : y_alloc - 32);
             int t = 0;
@@ -342,17 +355,19 @@ __device__ __forceinline__ void filtered_item(
                     break;
 #pragma unroll
                 for (int tt = 0; tt < 4; ++tt) {
-                    const float d = PYq - yp[t + tt];
-                    const bool inside_ring = c0 + t + tt < k;
-                    zmin = inside_ring ? fminf(zmin, fabsf(d)) : zmin;
-                    above = __builtin_amdgcn_alignbit(above, __float_as_uint(d), 31);
+                    const float yv = yp[t + tt];
+                    above = __builtin_amdgcn_alignbit(above, __float_as_uint(PYq - yv), 31);
+                    below = __builtin_amdgcn_alignbit(below, __float_as_uint(yv - PYq), 31);
                 }
             }
-            above = t < 32 ? above << (32 - t) : above;
-            uint32_t strad = above ^ ((above >> 1) | (above_prev << 31));
+            if (t < 32) {
+                above <<= 32 - t;
+                below <<= 32 - t;
+            }
             const int rem = k - c0;
-            if (rem < 32)
-                strad &= rem <= 0 ? 0u : ~(0xffffffffu >> rem);
+            const uint32_t keep = rem <= 0 ? 0u : (rem >= 32 ? ~0u : ~(0xffffffffu >> rem));
+            zero |= ~(above | below) & keep;
+            uint32_t strad = (above ^ ((above >> 1) | (above_prev << 31))) & keep;
             above_prev = rem >= 32 ? (above & 1u) : above_prev;
             const float4 *er = EF + e0 + c0;
             while (strad != 0) {
@@ -370,7 +385,7 @@ __device__ __forceinline__ void filtered_item(
                 par ^= __builtin_amdgcn_ballot_w64(sv <= 0.0f);
             }
         }
-        amb = amb || zmin == 0.0f;
+        amb = amb || zero != 0;
         const bool valid = i < n;
         amb_rows[u] = __builtin_amdgcn_ballot_w64(valid && amb);
         if (valid && !amb)

@@ -93,6 +93,39 @@ def test_filtered_force_recheck(P):
     assert st["rechecked_pairs"] >= 0.5 * w.n_points
 
 
+def test_filtered_levels_equal_in_binary32(P):
+    """Points level with a vertex to within a binary64 ulp or two, far from the
+    vertex in x: after re-centring their binary32 y equals the vertex's, so the
+    straddle order is undecided and every such pair must be rechecked."""
+    base = 1.0e6
+    rel = [(0.0, 0.0), (4.0, 0.3), (4.5, 1.7), (2.0, 1.1), (0.5, 2.9), (-0.5, 1.4)]
+    vx = np.array([base + a for a, _ in rel])
+    vy = np.array([base + b for _, b in rel])
+    px, py = [], []
+    for yv in vy:
+        for d in (-3.5e-10, -1.2e-10, 0.0, 1.2e-10, 3.5e-10):
+            for xr in (-2.0, 1.0, 2.5, 6.0):
+                px.append(base + xr)
+                py.append(yv + d)
+    px, py = np.array(px), np.array(py)
+    w = W.Workload("levels", px, py, np.array([0, len(vx)], dtype=np.int64), vx, vy, None, {})
+    # binary32 y of the points and vertices re-centred on the box's centre
+    cy = 0.5 * vy.min() + 0.5 * vy.max()
+    level = np.isin(np.float32(py - cy), np.float32(vy - cy))
+    assert level.sum() >= len(vy) * 12
+    st, _ = check_plan(P, w, "levels", mode="filtered")
+    assert st["rechecked_pairs"] >= int(level.sum())
+    rx = np.array([-0.0, 1e-300, 1e-300, -0.0])
+    ry = np.array([-0.0, -0.0, 1e-300, 1e-300])
+    tx = np.array([0.0, -0.0, 5e-301, 1e-300, 2e-300, 0.0, -1e-300])
+    ty = np.array([0.0, -0.0, 5e-301, 5e-301, 5e-301, 1e-300, -1e-300])
+    bx = np.array([-1e300, 1e300, 1e300, -1e300])
+    by = np.array([-1e300, -1e300, 1e300, 1e300])
+    for ringx, ringy, name in ((rx, ry, "tiny square"), (bx, by, "huge square")):
+        w = W.Workload(name, tx, ty, np.array([0, 4], dtype=np.int64), ringx, ringy, None, {})
+        check_plan(P, w, name, mode="filtered")
+
+
 def test_filtered_negative_control(P):
     """With the error bound switched off (bound_scale=0) the binary32 filter alone
     must get some stress pairs wrong: the recheck is load-bearing."""
