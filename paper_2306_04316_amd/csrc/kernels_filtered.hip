@@ -14,10 +14,10 @@
 // For a pair, P = fl32(fl64(p - c)).  Straddle: rounding is monotone, so a
 // strict binary32 order between P_y and a vertex's YF implies the same
 // strict binary64 order between p_y and y_v; equal values are undecided.
-// The order is read from the sign bits of both differences, P_y - YF and
-// YF - P_y: with no negative zeros among the operands, both are +0 exactly
-// when the values are equal (or when a flushed subnormal difference makes
-// them so: undecided as well).
+// The order is the sign bit of the difference P_y - YF, which is nonzero
+// for unequal values (gradual underflow; a flushed subnormal difference is
+// zero, so undecided as well); a zero difference of either sign marks the
+// pair undecided.
 // Side: S = fl32(fl32(P_x - XI) * NX + fl32(P_y - YI) * NY).  With M >= every
 // re-centred coordinate of the pair (point and ring) and u = 2^-24,
 //   |S - E| <= 10.03 u M (|NX| + |NY|) + 4 eta (|NX| + |NY| + 1),
@@ -58,7 +58,8 @@ __device__ __forceinline__ bool normal_ok(double v)
 // LDS counter, thread 0 reserves the item's total in the list, then every
 // lane writes its own entries.  rows[u] is the wavefront's ballot of row u.
 // Must be called by the whole workgroup; s_cnt, s_base: LDS words, s_cnt
-// zeroed (and a barrier passed) since the last call.
+// zeroed (and a barrier passed) since the last call.  An item with no
+// undecided pair passes one barrier and touches no global memory.
 template <int U>
 __device__ __forceinline__ void append_recheck_item(const uint64_t (&rows)[U], int64_t p0, int32_t *list,
                                                     unsigned *count, unsigned *s_cnt, unsigned *s_base)
@@ -73,10 +74,11 @@ __device__ __forceinline__ void append_recheck_item(const uint64_t (&rows)[U], i
         wbase = atomicAdd(s_cnt, mine);
     wbase = __builtin_amdgcn_readfirstlane(wbase);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned tot = *s_cnt;
-        *s_base = tot ? atomicAdd(count, tot) : 0u;
-    }
+    const unsigned tot = *s_cnt;   // the same for every thread: most items end here
+    if (tot == 0)
+        return;
+    if (threadIdx.x == 0)
+        *s_base = atomicAdd(count, tot);
     __syncthreads();
     unsigned at = *s_base + wbase;
 #pragma unroll
@@ -156,7 +158,6 @@ __device__ __forceinline__ void filtered_item(
     unsigned char *smem)
 {
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
     const int ypad = 64;
     const int y_alloc = max_edges + max_rings + ypad;
 
@@ -217,6 +218,11 @@ __device__ __forceinline__ void filtered_item(
         s_rcnt = 0;
     }
     if (fits) {
+        // YF starts as quiet NaNs: the straddle pass's minimum of |P_y - YF|
+        // runs over every slot a lane reads, also past its ring (padding,
+        // slots of rings without vertices), and a NaN leaves it unchanged
+        for (int j = tid; j < y_alloc; j += 256)
+            YF[j] = __int_as_float(0x7fc00000);
         for (int r = tid; r < nr; r += 256) {
             KB[4 * r + 0] = ~0ull;
             KB[4 * r + 1] = 0ull;
@@ -307,16 +313,11 @@ __device__ __forceinline__ void filtered_item(
             ny = -ny;
         }
         EF[e] = make_float4((float)(ax - cx), (float)(ay - cy), (float)nx, (float)ny);
-        // +0.0f: no negative zero, so that equal binary32 values give two zero
-        // differences below, whatever their signs
-        const float yv = (float)(by - cy) + 0.0f;
+        const float yv = (float)(by - cy);
         YF[e + r + 1] = yv;
         if (e == e1 - 1)
             YF[e0 + r] = yv;
     }
-    const int ytot = (int)(ve - vb) + nr;
-    if (tid < ypad)
-        YF[ytot + tid] = 0.0f;
     __syncthreads();
     const int kmax_b = s_kmax;
 
@@ -337,16 +338,18 @@ __device__ __forceinline__ void filtered_item(
         bool amb = ri.m < 0.0f || !(fabs(xr) <= kLim) || !(fabs(yr) <= kLim) || force_recheck;
         const float mp = fmaxf(ri.m, fmaxf(fabsf(PX), fabsf(PY)));
         const float kmt = ks * mp + eta;
-        const float PYq = PY + 0.0f;
-        uint64_t par = 0;
-        uint32_t above_prev = (k > 0 && (__float_as_uint(PYq - YF[yb]) >> 31)) ? 1u : 0u;
-        uint32_t zero = 0;   // ring vertices whose binary32 y equals the point's (undecided order)
+        const float y_last = YF[yb];   // the ring's last vertex: the first edge's start
+        uint32_t cnt = 0;
+        uint32_t above_prev = (k > 0 && (__float_as_uint(PY - y_last) >> 31)) ? 1u : 0u;
+        // smallest |P_y - YF| over the vertices read: zero when some vertex of
+        // the ring has the point's binary32 y (undecided order); slots past
+        // the ring hold NaN (ignored) or another ring's values (a zero there
+        // only sends the pair to the recheck)
+        float zmin = fabsf(PY - y_last);
         for (int c0 = 0; c0 < kmax_b; c0 += 32) {
             if (__builtin_amdgcn_ballot_w64(k > c0) == 0)
                 break;
-            // sign bits of P_y - y_v (the vertex is above) and of y_v - P_y
-            // (below); neither is set exactly when the two are equal
-            uint32_t above = 0, below = 0;
+            uint32_t above = 0;   // sign bits of P_y - y_v: vertex above the point
             const int ybase = yb + 1 + c0;
             const float *yp = YF + (ybase < y_alloc - 32 ? ybase : y_alloc - 32);
             int t = 0;
@@ -355,25 +358,22 @@ __device__ __forceinline__ void filtered_item(
                     break;
 #pragma unroll
                 for (int tt = 0; tt < 4; ++tt) {
-                    const float yv = yp[t + tt];
-                    above = __builtin_amdgcn_alignbit(above, __float_as_uint(PYq - yv), 31);
-                    below = __builtin_amdgcn_alignbit(below, __float_as_uint(yv - PYq), 31);
+                    const float d = PY - yp[t + tt];
+                    zmin = fminf(zmin, fabsf(d));
+                    above = __builtin_amdgcn_alignbit(above, __float_as_uint(d), 31);
                 }
             }
-            if (t < 32) {
-                above <<= 32 - t;
-                below <<= 32 - t;
-            }
+            above = t < 32 ? above << (32 - t) : above;
             const int rem = k - c0;
             const uint32_t keep = rem <= 0 ? 0u : (rem >= 32 ? ~0u : ~(0xffffffffu >> rem));
-            zero |= ~(above | below) & keep;
             uint32_t strad = (above ^ ((above >> 1) | (above_prev << 31))) & keep;
             above_prev = rem >= 32 ? (above & 1u) : above_prev;
-            const float4 *er = EF + e0 + c0;
+            // bit b: the edge ending at chunk vertex 31 - b
+            const int elast = e0 + c0 + 31;
             while (strad != 0) {
-                const int j = __builtin_clz(strad);
-                strad ^= 0x80000000u >> j;
-                const float4 rec = er[j];
+                const int b = __builtin_ctz(strad);
+                strad &= strad - 1u;
+                const float4 rec = EF[elast - b];
                 const float t1 = PX - rec.x;
                 const float t2 = PY - rec.y;
                 const float p1 = t1 * rec.z;
@@ -382,14 +382,14 @@ __device__ __forceinline__ void filtered_item(
                 const float nsum = fabsf(rec.z) + fabsf(rec.w);
                 const float bnd = kmt * nsum + eta;
                 amb = amb || !(fabsf(sv) > bnd);
-                par ^= __builtin_amdgcn_ballot_w64(sv <= 0.0f);
+                cnt += sv <= 0.0f ? 1u : 0u;
             }
         }
-        amb = amb || zero != 0;
+        amb = amb || zmin == 0.0f;
         const bool valid = i < n;
         amb_rows[u] = __builtin_amdgcn_ballot_w64(valid && amb);
         if (valid && !amb)
-            inside[i] = (uint8_t)((par >> lane) & 1u);
+            inside[i] = (uint8_t)(cnt & 1u);
     }
     append_recheck_item<U>(amb_rows, p0, recheck, recheck_count, &s_rcnt, &s_rbase);
 }
