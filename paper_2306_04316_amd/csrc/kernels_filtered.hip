@@ -394,11 +394,14 @@ __device__ __forceinline__ void filtered_item(
     append_recheck_item<U>(amb_rows, p0, recheck, recheck_count, &s_rcnt, &s_rbase);
 }
 
-// Eight waves per SIMD: the register cap spills a few words (cold values),
-// which costs less than the occupancy it buys (74 against 80 us on the
-// footprints at six waves).
-template <int U>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_filtered_fp32(
+// One workgroup per item (QUEUE false: workgroup b takes item order[b], or
+// b), or a resident grid taking items from an atomic counter (QUEUE true).
+// The two forms are separate kernels, each compiled with only its own
+// control flow and registers.  The one-item form runs at eight waves per
+// SIMD: at that register budget it keeps its pair loads in flight while the
+// ring table and vertices are staged (no spill reload waits on them).
+template <int U, bool QUEUE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUEUE ? 1 : 8))) void k_filtered_fp32(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
     const int64_t *__restrict__ offsets, int64_t n_polys,
     const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
@@ -407,13 +410,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     const int32_t *__restrict__ order, int n_items, unsigned *queue)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_item;
-    if (!queue) {
+    if (!QUEUE) {
         const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
         filtered_item<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside,
                          max_edges, max_rings, bound_scale, force_recheck, recheck, recheck_count, smem);
         return;
     }
+    __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0)
             s_item = (int)atomicAdd(queue, 1u);
@@ -490,16 +493,26 @@ int launch_filtered(const Problem &p, hipStream_t stream, int pairs_per_lane, in
         grid = n_items;
     if (grid <= 0)
         return PIP_OK;
-#define PIP_LAUNCH_F(UU)                                                                                         \
-    PIP_LAUNCH((k_filtered_fp32<UU>), dim3(grid), dim3(256), shmem, stream, p.px, p.py, p.n_points,     \
-                       p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside, max_edges,         \
-                       max_rings, bound_scale, force_recheck, recheck, recheck_count, order, n_items, queue)
-    if (U == 1)
-        PIP_LAUNCH_F(1);
-    else if (U == 4)
-        PIP_LAUNCH_F(4);
-    else
-        PIP_LAUNCH_F(2);
+#define PIP_LAUNCH_F(UU, QQ)                                                                                     \
+    PIP_LAUNCH((k_filtered_fp32<UU, QQ>), dim3(grid), dim3(256), shmem, stream, p.px, p.py, p.n_points,             \
+               p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside, max_edges, max_rings,       \
+               bound_scale, force_recheck, recheck, recheck_count, order, n_items, queue)
+    if (U == 1) {
+        if (queue)
+            PIP_LAUNCH_F(1, true);
+        else
+            PIP_LAUNCH_F(1, false);
+    } else if (U == 4) {
+        if (queue)
+            PIP_LAUNCH_F(4, true);
+        else
+            PIP_LAUNCH_F(4, false);
+    } else {
+        if (queue)
+            PIP_LAUNCH_F(2, true);
+        else
+            PIP_LAUNCH_F(2, false);
+    }
 #undef PIP_LAUNCH_F
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
@@ -513,11 +526,11 @@ int filtered_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu)
     int nb = 0;
     hipError_t e;
     if (U == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_filtered_fp32<1>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_filtered_fp32<1, true>, 256, shmem);
     else if (U == 4)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_filtered_fp32<4>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_filtered_fp32<4, true>, 256, shmem);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_filtered_fp32<2>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_filtered_fp32<2, true>, 256, shmem);
     if (e != hipSuccess)
         return fail(PIP_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
     *blocks_per_cu = nb < 1 ? 1 : nb;
