@@ -7,7 +7,8 @@
 // ring's bounding-box centre c:
 //   YF : fl32(fl64(y_j - c_y)) per vertex (straddle pass)
 //   EF : (XI, YI, NX, NY) = fl32 of fl64(a - c) and of the rule's binary64
-//        normal (negated when its x part is negative), per edge
+//        normal n (negated when its x part is negative) scaled by
+//        fl64(1 / s), s = fl64(n_x + |n_y|), per edge
 // and per ring: c (binary64), M_ring = an upper bound of |v - c| over the
 // ring (rounded up to binary32), and an eligibility flag.
 //
@@ -18,19 +19,24 @@
 // for unequal values (gradual underflow; a flushed subnormal difference is
 // zero, so undecided as well); a zero difference of either sign marks the
 // pair undecided.
-// Side: S = fl32(fl32(P_x - XI) * NX + fl32(P_y - YI) * NY).  With M >= every
-// re-centred coordinate of the pair (point and ring) and u = 2^-24,
-//   |S - E| <= 10.03 u M (|NX| + |NY|) + 4 eta (|NX| + |NY| + 1),
-// where E = t1 n_x + t2 n_y is the exact value on the binary64 inputs and
-// normals and eta = 2^-126 covers flushed subnormals; the binary64 value the
-// rule computes differs from E by at most 6.02 * 2^-53 M (|n_x| + |n_y|).
-// Hence |S| > B = 12 u M (|NX| + |NY|) + 4 eta (|NX| + |NY| + 1) guarantees
-// that the rule's binary64 side value is nonzero with the sign of S (the 12
-// also covers the rounding of B itself and of M).  The bound needs every
-// nonzero |n| component in [2^-60, 2^60] and |p - c|, |v - c| <= 2^60 (no
-// binary32 overflow or underflow of normals); rings or points outside that
-// range are not filtered.  A pair with any undecided straddle or side test
-// is appended to a list and re-run in binary64 in the rule's order.
+// Side: S = fl32(fl32(P_x - XI) * NX + fl32(P_y - YI) * NY).  Every edge
+// that can straddle has s > 0, and NX, NY have relative error at most
+// u (1 + 2^-27) against n_x / s, n_y / s (u = 2^-24: the conversion, plus two
+// binary64 roundings), so |NX| + |NY| <= N1 = 1 + 2^-22.  The sign to find
+// is that of E = t1 n_x + t2 n_y, the exact value on the binary64 inputs and
+// normals, which is the sign of E / s.  With M >= every re-centred
+// coordinate of the pair (point and ring),
+//   |S - E / s| <= 10.03 u M (|NX| + |NY|) + 4 eta (|NX| + |NY| + 1),
+// where eta = 2^-126 covers flushed subnormals.  If |S| > B = 12 u M N1 +
+// 4 eta (N1 + 1), one threshold per pair, then |E| > 1.97 u M s, while the
+// binary64 value the rule computes differs from E by at most
+// 6.02 * 2^-53 M (|n_x| + |n_y|): that value is nonzero with the sign of S
+// (the 12 also covers the rounding of B itself and of M).  The bound needs every nonzero |n|
+// component in [2^-60, 2^60] (no overflow of s; scaled components stay at
+// or above 2^-121, so none underflows in binary32) and |p - c|, |v - c| <=
+// 2^60; rings or points outside that range are not filtered.  A pair with
+// any undecided straddle or side test is appended to a list and re-run in
+// binary64 in the rule's order.
 //
 // This translation unit must be compiled with -ffp-contract=off: the bound
 // assumes separately rounded binary32 products and sums.
@@ -43,6 +49,7 @@ namespace {
 
 constexpr float kBoundK = 12.0f * 5.9604644775390625e-8f;   // 12 * 2^-24
 constexpr float kEta4 = 4.0f * 1.1754943508222875e-38f;       // 4 * 2^-126
+constexpr float kN1 = 1.0f + 2.384185791015625e-7f;            // 1 + 2^-22 >= |NX| + |NY|
 constexpr double kLim = 1.152921504606846976e18;              // 2^60
 constexpr double kTiny = 8.673617379884035e-19;               // 2^-60
 
@@ -312,7 +319,10 @@ __device__ __forceinline__ void filtered_item(
             nx = -nx;
             ny = -ny;
         }
-        EF[e] = make_float4((float)(ax - cx), (float)(ay - cy), (float)nx, (float)ny);
+        // scaled to |n_x| + |n_y| = 1 (s > 0 for every edge that can straddle)
+        const double sn = nx + fabs(ny);
+        const double rs = sn > 0.0 ? 1.0 / sn : 0.0;
+        EF[e] = make_float4((float)(ax - cx), (float)(ay - cy), (float)(nx * rs), (float)(ny * rs));
         const float yv = (float)(by - cy);
         YF[e + r + 1] = yv;
         if (e == e1 - 1)
@@ -337,9 +347,9 @@ __device__ __forceinline__ void filtered_item(
         const float PX = (float)xr, PY = (float)yr;
         bool amb = ri.m < 0.0f || !(fabs(xr) <= kLim) || !(fabs(yr) <= kLim) || force_recheck;
         const float mp = fmaxf(ri.m, fmaxf(fabsf(PX), fabsf(PY)));
-        const float kmt = ks * mp + eta;
+        const float bnd = (ks * mp + eta) * kN1 + eta;   // B, the pair's threshold
         const float y_last = YF[yb];   // the ring's last vertex: the first edge's start
-        uint32_t cnt = 0;
+        uint32_t sgn = 0;   // bit 31: parity of the side values below zero
         uint32_t above_prev = (k > 0 && (__float_as_uint(PY - y_last) >> 31)) ? 1u : 0u;
         // smallest |P_y - YF| over the vertices read: zero when some vertex of
         // the ring has the point's binary32 y (undecided order); slots past
@@ -366,30 +376,31 @@ __device__ __forceinline__ void filtered_item(
             above = t < 32 ? above << (32 - t) : above;
             const int rem = k - c0;
             const uint32_t keep = rem <= 0 ? 0u : (rem >= 32 ? ~0u : ~(0xffffffffu >> rem));
-            uint32_t strad = (above ^ ((above >> 1) | (above_prev << 31))) & keep;
+            // reversed: bit b is the edge ending at chunk vertex b
+            uint32_t strad = __builtin_bitreverse32((above ^ ((above >> 1) | (above_prev << 31))) & keep);
             above_prev = rem >= 32 ? (above & 1u) : above_prev;
-            // bit b: the edge ending at chunk vertex 31 - b
-            const int elast = e0 + c0 + 31;
+            const float4 *er = EF + e0 + c0;
             while (strad != 0) {
                 const int b = __builtin_ctz(strad);
                 strad &= strad - 1u;
-                const float4 rec = EF[elast - b];
+                const float4 rec = er[b];
                 const float t1 = PX - rec.x;
                 const float t2 = PY - rec.y;
                 const float p1 = t1 * rec.z;
                 const float p2 = t2 * rec.w;
                 const float sv = p1 + p2;
-                const float nsum = fabsf(rec.z) + fabsf(rec.w);
-                const float bnd = kmt * nsum + eta;
                 amb = amb || !(fabsf(sv) > bnd);
-                cnt += sv <= 0.0f ? 1u : 0u;
+                // the edge counts when the side value is <= 0; a zero value
+                // is undecided (|sv| > bnd fails), so for every decided pair
+                // that is the sign bit
+                sgn ^= __float_as_uint(sv);
             }
         }
         amb = amb || zmin == 0.0f;
         const bool valid = i < n;
         amb_rows[u] = __builtin_amdgcn_ballot_w64(valid && amb);
         if (valid && !amb)
-            inside[i] = (uint8_t)(cnt & 1u);
+            inside[i] = (uint8_t)(sgn >> 31);
     }
     append_recheck_item<U>(amb_rows, p0, recheck, recheck_count, &s_rcnt, &s_rbase);
 }
