@@ -56,22 +56,54 @@ PROFILED_TRAFFIC: dict = {
     # footprints, exact mode, k_staged_batched_fp64<0, 4, false, false, false>
     # (profiles/staged_footprints_exact.md: FETCH_SIZE and WRITE_SIZE scaled by the copy calibration)
     (2, "exact", "76c8ae46ea49"): {"fetch_bytes": 220030829, "write_bytes": 10000000},
+    # footprints, filtered mode, k_filtered_fp32<4, false> (profiles/filtered_footprints.md)
+    (2, "filtered", "16534d72238d"): {"fetch_bytes": 220461580, "write_bytes": 10001760},
 }
 
+# VALU instructions of the main kernel per launch (rocprofv3 --pmc SQ_INSTS_VALU, SQ_WAVES; median
+# over launches), keyed like PROFILED_TRAFFIC.
+PROFILED_VALU: dict = {
+    (2, "exact", "76c8ae46ea49"): {"valu_insts": 19081996, "waves": 39064,
+                                   "source": "profiles/staged_footprints_exact.md"},
+    (2, "filtered", "16534d72238d"): {"valu_insts": 25513125, "waves": 39064,
+                                      "source": "profiles/filtered_footprints.md"},
+}
+SIMDS = 1024          # 256 compute units x 4 SIMDs
+CLOCK_HZ = 2.4e9      # peak engine clock
 
-def kernel_digest() -> str:
-    """Digest of the code the staged kernels are compiled from (their sources and
-    the per-edge arithmetic, comments and spacing left out); a change there
-    invalidates the recorded traffic."""
+
+DIGEST_SOURCES = {"exact": ("kernels_exact.hip", "ring_walk.h"),
+                  "filtered": ("kernels_filtered.hip", "ring_walk.h")}
+
+
+def kernel_digest(mode: str = "exact") -> str:
+    """Digest of the code a mode's main kernel is compiled from (its sources,
+    comments and spacing left out); a change there invalidates the recorded
+    traffic and instruction counts."""
     import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2306_04316_amd", "csrc")
-    for f in ("kernels_exact.hip", "ring_walk.h"):
+    for f in DIGEST_SOURCES[mode]:
         with open(os.path.join(csrc, f), encoding="utf-8") as fh:
             code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
         code = re.sub(r"//[^\n]*", " ", code)
         h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:12]
+
+
+def valu_issue(mode: str, config: int, kernel_ms: float):
+    """VALU issue utilisation of a mode's main kernel: its recorded VALU
+    instruction count per launch (rocprofv3 SQ_INSTS_VALU) times 4 cycles (a
+    wavefront instruction on a 16-lane SIMD) over all SIMD cycles of the
+    measured duration (1024 SIMDs at 2.4 GHz).  None when the kernel has
+    changed since the count was taken."""
+    rec = PROFILED_VALU.get((config, mode, kernel_digest(mode)))
+    if rec is None:
+        return None
+    cycles = kernel_ms * 1e-3 * SIMDS * CLOCK_HZ
+    return {"insts_per_launch": rec["valu_insts"], "insts_per_wavefront": rec["valu_insts"] / rec["waves"],
+            "issue_frac": rec["valu_insts"] * 4 / cycles, "peak": "1 wavefront instruction per 4 cycles per SIMD",
+            "source": rec["source"]}
 
 
 def parse():
@@ -458,6 +490,16 @@ def main():
                 s = st.stats()
                 entry["recheck_fraction"] = s["rechecked_pairs"] / max(1, N)
                 entry["recheck_ms"] = float(np.mean(ph[:, 2]))
+            if opts["mode"] != a.mode and label.startswith("mode_"):
+                kms = entry["main_kernel_ms"]
+                gbs = alg_bytes / (kms * 1e-3) / 1e9
+                tr2 = PROFILED_TRAFFIC.get((a.config, opts["mode"], kernel_digest(opts["mode"])))
+                entry["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": gbs / HBM_PEAK_GBS,
+                                     "traffic": None if tr2 is None else tr2["fetch_bytes"] + tr2["write_bytes"],
+                                     "kernel": "main classification kernel", "kernel_ms": kms,
+                                     "alg_bytes_per_launch": alg_bytes, "kernel_digest": kernel_digest(opts["mode"]),
+                                     "valu": valu_issue(opts["mode"], a.config, kms)}
             if want is not None:
                 got = copies[(2 + a.compare_steps - 1) % len(copies)]["out"].cpu().numpy()
                 entry["parity"] = "bit-exact" if np.array_equal(got, want) else "MISMATCH"
@@ -479,7 +521,7 @@ def main():
         torch.cuda.empty_cache()
         ext = extensions(P, W, a, cfg, dev)
 
-    digest = kernel_digest()
+    digest = kernel_digest(a.mode)
     tr = PROFILED_TRAFFIC.get((a.config, a.mode, digest))
     traffic = None if tr is None else tr["fetch_bytes"] + tr["write_bytes"]
     rec = {
@@ -510,7 +552,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes per launch",
                      "kernel": "main classification kernel", "kernel_ms": main_ms, "kernel_ms_source": main_src,
-                     "alg_bytes_per_launch": alg_bytes, "kernel_digest": digest},
+                     "alg_bytes_per_launch": alg_bytes, "kernel_digest": digest,
+                     "valu": valu_issue(a.mode, a.config, main_ms)},
         "compare": compare,
         "extensions": ext,
         "cpu_baseline": cpu,

@@ -50,3 +50,17 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in line["error"]
+
+
+def test_valu_issue_tied_to_digest(monkeypatch):
+    # 600 wavefront instructions on each of the 1024 SIMDs take 2400 cycles: 1 us at 2.4 GHz
+    d = bench.kernel_digest("exact")
+    monkeypatch.setattr(bench, "PROFILED_VALU", {(2, "exact", d): {"valu_insts": 1024 * 600, "waves": 1024,
+                                                                     "source": "test"}})
+    v = bench.valu_issue("exact", 2, 1e-3)
+    assert abs(v["issue_frac"] - 1.0) < 1e-12 and v["insts_per_wavefront"] == 600
+    assert bench.valu_issue("exact", 2, 2e-3)["issue_frac"] == 0.5
+    # another mode, config or digest has no record
+    assert bench.valu_issue("filtered", 2, 1e-3) is None
+    assert bench.valu_issue("exact", 4, 1e-3) is None
+    assert bench.kernel_digest("filtered") != d
