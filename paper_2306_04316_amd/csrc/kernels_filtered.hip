@@ -43,6 +43,7 @@
 
 #include "pip_common.h"
 #include "ring_walk.h"
+#include "staged_exact.h"
 
 namespace pip {
 namespace {
@@ -161,7 +162,7 @@ __device__ __forceinline__ void filtered_item(
     const int64_t *__restrict__ offsets, int64_t n_polys,
     const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
     const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
-    float bound_scale, int force_recheck, int32_t *__restrict__ recheck, unsigned *recheck_count,
+    int tile_edges, float bound_scale, int force_recheck, int32_t *__restrict__ recheck, unsigned *recheck_count,
     unsigned char *smem)
 {
     const int tid = threadIdx.x;
@@ -255,9 +256,30 @@ __device__ __forceinline__ void filtered_item(
     const bool staged = block_all(fits && mine_ok, s_all);
 
     if (!staged) {
-        // Rings too large for the workgroup's LDS (or unsorted pairs): these
-        // pairs take the exact binary64 wave-uniform walk instead.
-        group_walk_rows<kSide, U>(p0, x, y, q, n, offsets, n_polys, nullptr, n_polys, vx, vy, nv, inside);
+        // A vertex range larger than the binary32 layout's LDS budget, more
+        // rings than its tables hold, or pairs not sorted by polygon: the
+        // item is classified exactly in binary64 by the staged exact item,
+        // which walks a large range in LDS tiles of tile_edges vertices (and
+        // itself takes the scalar-load group walk when its tables cannot
+        // hold the item or the pairs are unsorted).  Every thread has passed
+        // the vote's barrier, so the LDS is free to be laid out anew.
+        ItemRows<U> P;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            P.x[u] = x[u];
+            P.y[u] = y[u];
+            P.q[u] = q[u];
+        }
+        ItemRange R;
+        R.vb = vb;
+        R.rf = qf;
+        R.qf = qf;
+        R.ql = ql;
+        R.nr = range_ok ? nr : 0;
+        R.nv = nvr;
+        R.ok = range_ok;
+        staged_item_fp64<kSide, U, false, true>(p0, P, n, offsets, n_polys, nullptr, n_polys, vx, vy, nv, inside,
+                                                tile_edges, max_rings, smem, R);
         return;
     }
 
@@ -417,14 +439,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUEUE ? 1 :
     const int64_t *__restrict__ offsets, int64_t n_polys,
     const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
     const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside, int max_edges, int max_rings,
-    float bound_scale, int force_recheck, int32_t *__restrict__ recheck, unsigned *recheck_count,
+    int tile_edges, float bound_scale, int force_recheck, int32_t *__restrict__ recheck, unsigned *recheck_count,
     const int32_t *__restrict__ order, int n_items, unsigned *queue)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     if (!QUEUE) {
         const int item = order ? order[blockIdx.x] : (int)blockIdx.x;
         filtered_item<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside,
-                         max_edges, max_rings, bound_scale, force_recheck, recheck, recheck_count, smem);
+                         max_edges, max_rings, tile_edges, bound_scale, force_recheck, recheck, recheck_count, smem);
         return;
     }
     __shared__ int s_item;
@@ -438,7 +460,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUEUE ? 1 :
             break;
         const int item = order ? order[it] : it;
         filtered_item<U>((int64_t)item * (256 * U), px, py, n, offsets, n_polys, vx, vy, nv, point_poly, inside,
-                         max_edges, max_rings, bound_scale, force_recheck, recheck, recheck_count, smem);
+                         max_edges, max_rings, tile_edges, bound_scale, force_recheck, recheck, recheck_count, smem);
         __syncthreads();
     }
 }
@@ -500,6 +522,14 @@ int launch_filtered(const Problem &p, hipStream_t stream, int pairs_per_lane, in
     const int U = pairs_per_lane == 1 ? 1 : (pairs_per_lane == 4 ? 4 : 2);
     const int max_rings = 256 * U < 128 ? 256 * U : 128;
     const size_t shmem = filtered_smem_bytes(max_edges, max_rings);
+    // the exact layout's tile for items beyond the binary32 layout: the
+    // largest size (in steps of 16 vertices) whose staged layout fits the
+    // same LDS; at 16 edges it needs less than the binary32 layout
+    int tile_edges = max_edges;
+    while (tile_edges > 16 && staged_smem_bytes(tile_edges, max_rings) > shmem)
+        tile_edges -= 16;
+    if (staged_smem_bytes(tile_edges, max_rings) > shmem)
+        return fail(PIP_EINVAL, "LDS budget of %d edges too small for the filtered mode", max_edges);
     if (!queue)
         grid = n_items;
     if (grid <= 0)
@@ -507,7 +537,7 @@ int launch_filtered(const Problem &p, hipStream_t stream, int pairs_per_lane, in
 #define PIP_LAUNCH_F(UU, QQ)                                                                                     \
     PIP_LAUNCH((k_filtered_fp32<UU, QQ>), dim3(grid), dim3(256), shmem, stream, p.px, p.py, p.n_points,             \
                p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside, max_edges, max_rings,       \
-               bound_scale, force_recheck, recheck, recheck_count, order, n_items, queue)
+               tile_edges, bound_scale, force_recheck, recheck, recheck_count, order, n_items, queue)
     if (U == 1) {
         if (queue)
             PIP_LAUNCH_F(1, true);
