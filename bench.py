@@ -55,25 +55,25 @@ WORKLOAD_TEXT = {
 PROFILED_TRAFFIC: dict = {
     # footprints, exact mode, k_staged_batched_fp64<0, 4, false, false, false>
     # (profiles/staged_footprints_exact.md: FETCH_SIZE and WRITE_SIZE scaled by the copy calibration)
-    (2, "exact", "76c8ae46ea49"): {"fetch_bytes": 220030829, "write_bytes": 10000000},
+    (2, "exact", "f12a22754daa"): {"fetch_bytes": 220029037, "write_bytes": 10000000},
     # footprints, filtered mode, k_filtered_fp32<4, false> (profiles/filtered_footprints.md)
-    (2, "filtered", "16534d72238d"): {"fetch_bytes": 220461580, "write_bytes": 10001760},
+    (2, "filtered", "937a1951ac77"): {"fetch_bytes": 220086313, "write_bytes": 10001792},
 }
 
 # VALU instructions of the main kernel per launch (rocprofv3 --pmc SQ_INSTS_VALU, SQ_WAVES; median
 # over launches), keyed like PROFILED_TRAFFIC.
 PROFILED_VALU: dict = {
-    (2, "exact", "76c8ae46ea49"): {"valu_insts": 19081996, "waves": 39064,
+    (2, "exact", "f12a22754daa"): {"valu_insts": 19081996, "waves": 39064,
                                    "source": "profiles/staged_footprints_exact.md"},
-    (2, "filtered", "16534d72238d"): {"valu_insts": 25513125, "waves": 39064,
+    (2, "filtered", "937a1951ac77"): {"valu_insts": 26096941, "waves": 39064,
                                       "source": "profiles/filtered_footprints.md"},
 }
 SIMDS = 1024          # 256 compute units x 4 SIMDs
 CLOCK_HZ = 2.4e9      # peak engine clock
 
 
-DIGEST_SOURCES = {"exact": ("kernels_exact.hip", "ring_walk.h"),
-                  "filtered": ("kernels_filtered.hip", "ring_walk.h")}
+DIGEST_SOURCES = {"exact": ("kernels_exact.hip", "staged_exact.h", "ring_walk.h"),
+                  "filtered": ("kernels_filtered.hip", "staged_exact.h", "ring_walk.h")}
 
 
 def kernel_digest(mode: str = "exact") -> str:

@@ -33,6 +33,7 @@ def test_kernel_digest_ignores_comments(tmp_path, monkeypatch):
     csrc = tmp_path / "paper_2306_04316_amd" / "csrc"
     csrc.mkdir(parents=True)
     src = {"kernels_exact.hip": "int f(int a) { return a + 1; } // one\n/* block */\n",
+           "staged_exact.h": "#pragma once\nint h();\n",
            "ring_walk.h": "#pragma once\nint g();\n"}
     for name, text in src.items():
         (csrc / name).write_text(text)
@@ -42,6 +43,9 @@ def test_kernel_digest_ignores_comments(tmp_path, monkeypatch):
     assert bench.kernel_digest() == d0, "comments and spacing must not change the digest"
     (csrc / "kernels_exact.hip").write_text("int f(int a) { return a + 2; }\n")
     assert bench.kernel_digest() != d0, "a code change must change the digest"
+    d1 = bench.kernel_digest()
+    (csrc / "staged_exact.h").write_text("#pragma once\nint h(int);\n")
+    assert bench.kernel_digest() != d1, "a change in the shared staged item must change the digest"
 
 
 def test_more_than_one_gpu_is_refused():
