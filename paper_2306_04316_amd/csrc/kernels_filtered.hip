@@ -31,12 +31,16 @@
 // 4 eta (N1 + 1), one threshold per pair, then |E| > 1.97 u M s, while the
 // binary64 value the rule computes differs from E by at most
 // 6.02 * 2^-53 M (|n_x| + |n_y|): that value is nonzero with the sign of S
-// (the 12 also covers the rounding of B itself and of M).  The bound needs every nonzero |n|
-// component in [2^-60, 2^60] (no overflow of s; scaled components stay at
-// or above 2^-121, so none underflows in binary32) and |p - c|, |v - c| <=
-// 2^60; rings or points outside that range are not filtered.  A pair with
-// any undecided straddle or side test is appended to a list and re-run in
-// binary64 in the rule's order.
+// (the 12 also covers the rounding of B itself and of M).  The bound needs
+// every nonzero |n| component in [2^-60, 2^60] (no overflow of s; scaled
+// components stay at or above 2^-121, so none underflows in binary32) and
+// |p - c|, |v - c| <= 2^60; rings or points outside that range are not
+// filtered.  A pair with any undecided straddle or side test is appended to
+// a list and re-run in binary64 in the rule's order.
+//
+// An item whose vertex range does not fit this layout (or whose pairs are
+// not sorted by polygon) is classified in binary64 by the exact kernels'
+// staged item (staged_exact.h), which walks a large range in LDS tiles.
 //
 // This translation unit must be compiled with -ffp-contract=off: the bound
 // assumes separately rounded binary32 products and sums.
