@@ -224,7 +224,8 @@ PIP_API int pip_classify(const double *px, const double *py, int64_t n_points,
  * so that pip_plan_execute is one graph launch.  Both modes are accepted;
  * the filtered mode (PIP_MODE_FILTERED_FP32) evaluates in binary32 with a
  * proven error bound and re-runs undecided pairs in binary64, with the same
- * bits as the exact mode.  With tune, creation times candidate
+ * bits as the exact mode (work items whose rings exceed its LDS budget are
+ * classified in binary64 directly, their rings walked in LDS tiles).  With tune, creation times candidate
  * configurations on the given data (this runs the classification several
  * times on `stream` and waits for it).  The plan reads the buffers' contents
  * at each execution, so new data in the same buffers needs no new plan; new
