@@ -66,6 +66,25 @@ def test_ring_sizes_at_boundaries(P, kernel, lds, predicate):
     assert_same_mask(got.cpu().numpy(), want, f"ring sizes {kernel} lds={lds}", w.px, w.py, w.point_poly)
 
 
+@pytest.mark.parametrize("ppl", [1, 4])
+@pytest.mark.parametrize("lds", [64, 256, 1024])
+def test_ring_sizes_at_boundaries_filtered(P, lds, ppl):
+    """The filtered mode across the same ring sizes: items that fit its binary32
+    layout are filtered, larger ones take the binary64 tile walk in the same LDS."""
+    import torch
+    w = star_polys(KS, 300, seed=2)
+    note(f"ring sizes filtered lds={lds} ppl={ppl}")
+    d = to_dev(w)
+    pl = P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], mode="filtered",
+                kernel="staged", lds_slots=lds, pairs_per_lane=ppl, persistent=0, order=0, use_graph=False)
+    pl.execute()
+    torch.cuda.synchronize()
+    got = pl.out.cpu().numpy()
+    pl.close()
+    want = oracle.classify_workload(w)
+    assert_same_mask(got, want, f"ring sizes filtered lds={lds} ppl={ppl}", w.px, w.py, w.point_poly)
+
+
 @pytest.mark.parametrize("pairs_per_poly", [8, 7])
 @pytest.mark.parametrize("ppl", [1, 2, 4])
 def test_rings_per_item_limit(P, pairs_per_poly, ppl):
