@@ -469,9 +469,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QUEUE ? 1 :
     }
 }
 
+// The rule's binary64 crossing test for edge (a, b) against point (x, y):
+// half-open straddle, then the side value with the oriented normal, each
+// operation separately rounded.
+__device__ __forceinline__ unsigned rule_crossing(double x, double y, double ax, double ay, double bx, double by)
+{
+    if ((ay > y) == (by > y))
+        return 0u;
+    double nx = by - ay;
+    double ny = ax - bx;
+    if (nx < 0.0) {
+        nx = -nx;
+        ny = -ny;
+    }
+    const double t1 = x - ax;
+    const double t2 = y - ay;
+    const double s = t1 * nx + t2 * ny;
+    return s <= 0.0 ? 1u : 0u;
+}
+
+constexpr int64_t kRecheckWide = 64;   // rings longer than this are walked by a whole wavefront
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    return __longlong_as_double(readlane64(__double_as_longlong(v), lane));
+}
+
 // Binary64 recheck, in the rule's operation order, of the listed pairs.  A
-// fixed grid strides over the list; its length is read on the device, so the
-// launch does not depend on it (graph-safe).
+// wavefront takes 64 consecutive list entries: a pair whose ring has at most
+// kRecheckWide vertices is walked by its own lane; each longer ring is then
+// walked by the whole wavefront, lane l taking edges l, l + 64, ... (coalesced
+// loads), the crossings' parity gathered with one ballot.  A fixed grid
+// strides over the list; its length is read on the device, so the launch
+// does not depend on it (graph-safe).
 __global__ __launch_bounds__(256) void k_recheck_fp64(
     const double *__restrict__ px, const double *__restrict__ py,
     const int64_t *__restrict__ offsets, int64_t n_polys,
@@ -481,35 +518,52 @@ __global__ __launch_bounds__(256) void k_recheck_fp64(
 {
     int64_t m = (int64_t)*count;
     m = m < cap ? m : cap;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = list[t];
-        int64_t qq = point_poly ? (int64_t)point_poly[i] : 0;
-        qq = ((uint64_t)qq < (uint64_t)n_polys) ? qq : 0;
-        int64_t b = offsets[qq], e = offsets[qq + 1];
-        clamp_ring(b, e, nv);
-        const double x = px[i], y = py[i];
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // the loop bound is the same for every lane of a wavefront
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); base < m; base += stride) {
+        const int64_t t = base + lane;
+        const bool valid = t < m;
+        int64_t i = 0, b = 0, e = 0;
+        double x = 0.0, y = 0.0;
+        if (valid) {
+            i = list[t];
+            int64_t qq = point_poly ? (int64_t)point_poly[i] : 0;
+            qq = ((uint64_t)qq < (uint64_t)n_polys) ? qq : 0;
+            b = offsets[qq];
+            e = offsets[qq + 1];
+            clamp_ring(b, e, nv);
+            x = px[i];
+            y = py[i];
+        }
+        const bool wide = valid && e - b > kRecheckWide;
         unsigned par = 0;
-        if (e > b) {
+        if (valid && !wide && e > b) {
             double ax = vx[e - 1], ay = vy[e - 1];
             for (int64_t j = b; j < e; ++j) {
                 const double bx = vx[j], by = vy[j];
-                if ((ay > y) != (by > y)) {
-                    double nx = by - ay;
-                    double ny = ax - bx;
-                    if (nx < 0.0) {
-                        nx = -nx;
-                        ny = -ny;
-                    }
-                    const double t1 = x - ax;
-                    const double t2 = y - ay;
-                    const double s = t1 * nx + t2 * ny;
-                    par ^= (s <= 0.0) ? 1u : 0u;
-                }
+                par ^= rule_crossing(x, y, ax, ay, bx, by);
                 ax = bx;
                 ay = by;
             }
         }
-        inside[i] = (uint8_t)par;
+        uint64_t todo = __builtin_amdgcn_ballot_w64(wide);
+        while (todo) {
+            const int s = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const double xs = readlane_f64(x, s), ys = readlane_f64(y, s);
+            const int64_t bs = readlane64(b, s), ks = readlane64(e, s) - bs;
+            unsigned lp = 0;
+            for (int64_t j = lane; j < ks; j += 64) {
+                const int64_t ja = j == 0 ? ks - 1 : j - 1;
+                lp ^= rule_crossing(xs, ys, vx[bs + ja], vy[bs + ja], vx[bs + j], vy[bs + j]);
+            }
+            const unsigned odd = (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64(lp != 0)) & 1u;
+            if (lane == s)
+                par = odd;
+        }
+        if (valid)
+            inside[i] = (uint8_t)par;
     }
 }
 
