@@ -67,7 +67,7 @@ def test_ring_sizes_at_boundaries(P, kernel, lds, predicate):
 
 
 @pytest.mark.parametrize("ppl", [1, 4])
-@pytest.mark.parametrize("lds", [64, 256, 1024])
+@pytest.mark.parametrize("lds", [16, 64, 256, 1024, 2048])
 def test_ring_sizes_at_boundaries_filtered(P, lds, ppl):
     """The filtered mode across the same ring sizes: items that fit its binary32
     layout are filtered, larger ones take the binary64 tile walk in the same LDS."""
