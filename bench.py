@@ -191,9 +191,45 @@ def cpu_baseline(w, budget_s: float):
         if el >= 0.5 * budget_s:
             break
     per = el / reps
+    # one thread, on a sample sized for about a tenth of the budget
+    n1 = int(min(s.n_points, max(1000, s.n_points * 0.1 * budget_s / (per * th))))
+    s1 = W.subsample(w, np.arange(n1))
+    t1 = time.perf_counter()
+    oracle.classify_workload(s1, nthreads=1)
+    d1 = max(time.perf_counter() - t1, 1e-6)
     return {"value": s.n_tests / per, "unit": "tests/s", "points_per_s": s.n_points / per, "cores": th,
             "kind": "oracle", "sample": f"{label}, {reps} pass(es), {per:.4f} s per pass",
-            "cpu_model": cpu_model()}
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": s1.n_tests / d1, "unit": "tests/s",
+                              "sample": f"the first {n1} pairs, one pass, {d1:.3f} s"}}
+
+
+def measured_peaks(P, dev, nbytes: int = 1 << 30, reps: int = 10):
+    """HBM rates this device reaches with plain streaming kernels over nbytes
+    (median of reps launches, HIP events on the current stream): a read-only
+    stream (pip_probe_read) and a copy (pip_probe_copy, read plus write)."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = {}
+    for name, fn, moved in (("read_stream", lambda: P.probe_read(src, sink), nbytes),
+                            ("copy", lambda: P.probe_copy(dst, src), 2 * nbytes)):
+        for _ in range(3):
+            fn()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b) * 1e-3)
+        out[name + "_GBs"] = moved / float(np.median(ts)) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    out["probe"] = f"pip_probe_read / pip_probe_copy over {nbytes >> 20} MiB, median of {reps} launches"
+    return out
 
 
 def single_kernel_step(cfg) -> bool:
@@ -528,6 +564,9 @@ def main():
         torch.cuda.empty_cache()
         ext = extensions(P, W, a, cfg, dev)
 
+    progress("bandwidth probes")
+    peaks = measured_peaks(P, dev)
+    peaks["frac_of_read_stream"] = achieved / peaks["read_stream_GBs"]
     digest = kernel_digest(a.mode)
     tr = PROFILED_TRAFFIC.get((a.config, a.mode, digest))
     traffic = None if tr is None else tr["fetch_bytes"] + tr["write_bytes"]
@@ -560,7 +599,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes per launch",
                      "kernel": "main classification kernel", "kernel_ms": main_ms, "kernel_ms_source": main_src,
                      "alg_bytes_per_launch": alg_bytes, "kernel_digest": digest,
-                     "valu": valu_issue(a.mode, a.config, main_ms)},
+                     "valu": valu_issue(a.mode, a.config, main_ms), "measured_peaks": peaks},
         "compare": compare,
         "extensions": ext,
         "cpu_baseline": cpu,

@@ -341,9 +341,19 @@ PIP_API int pip_join_destroy(pip_join *join);
 /*
  * Diagnostic: copy nbytes (a multiple of 16) from src to dst with a plain
  * streaming kernel.  Used to calibrate HBM traffic counters against a
- * kernel of known size.  Asynchronous on `stream`.
+ * kernel of known size.  The pointers may be NULL when nbytes is 0.
+ * Asynchronous on `stream`.
  */
 PIP_API int pip_probe_copy(void *dst, const void *src, int64_t nbytes, void *stream);
+
+/*
+ * Diagnostic: read nbytes (a multiple of 16) of device memory at src once,
+ * with a plain streaming kernel, writing at most one 32-bit word of the
+ * device buffer sink (>= 4 bytes; its contents are meaningless).  Measures
+ * the read-stream bandwidth that read-dominated kernels are compared with.
+ * The pointers may be NULL when nbytes is 0.  Asynchronous on `stream`.
+ */
+PIP_API int pip_probe_read(const void *src, int64_t nbytes, uint32_t *sink, void *stream);
 
 #ifdef __cplusplus
 }

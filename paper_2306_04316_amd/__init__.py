@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import PipError  # noqa: F401
 
 __all__ = ["classify", "classify_rings", "candidate_pairs", "Plan", "PipError", "abi_version", "probe_copy",
-           "to_device"]
+           "probe_read", "to_device"]
 
 
 def _require(t, dtype, name, numel=None):
@@ -233,6 +233,15 @@ def probe_copy(dst, src, stream=None):
     if dst.numel() * dst.element_size() != nbytes:
         raise ValueError("size mismatch")
     _lib.check(_lib.load().pip_probe_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)))
+
+
+def probe_read(src, sink, stream=None):
+    """Plain streaming read of src (byte size a multiple of 16); sink: a device
+    tensor of at least 4 bytes that may receive one meaningless word."""
+    if sink.numel() * sink.element_size() < 4:
+        raise ValueError("sink must hold at least 4 bytes")
+    nbytes = src.numel() * src.element_size()
+    _lib.check(_lib.load().pip_probe_read(_ptr(src), nbytes, _ptr(sink), _stream_handle(stream)))
 
 
 def abi_version() -> int:

@@ -232,13 +232,25 @@ int pip_classify_rings(const double *px, const double *py, int64_t n_points, con
 int pip_probe_copy(void *dst, const void *src, int64_t nbytes, void *stream)
 {
     clear_error();
-    if (!dst || !src || nbytes < 0 || (nbytes % 16) != 0)
+    if (nbytes < 0 || (nbytes % 16) != 0 || (nbytes > 0 && (!dst || !src)))
         return fail(PIP_EINVAL, "pip_probe_copy: NULL pointer or nbytes not a non-negative multiple of 16");
     DeviceInfo *dev = nullptr;
     PIP_TRY(current_device(&dev));
     if (nbytes == 0)
         return PIP_OK;
     return launch_copy(dst, src, nbytes, (hipStream_t)stream);
+}
+
+int pip_probe_read(const void *src, int64_t nbytes, uint32_t *sink, void *stream)
+{
+    clear_error();
+    if (nbytes < 0 || (nbytes % 16) != 0 || (nbytes > 0 && (!src || !sink)))
+        return fail(PIP_EINVAL, "pip_probe_read: NULL pointer or nbytes not a non-negative multiple of 16");
+    DeviceInfo *dev = nullptr;
+    PIP_TRY(current_device(&dev));
+    if (nbytes == 0)
+        return PIP_OK;
+    return launch_read(src, nbytes, sink, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -109,6 +109,10 @@ def test_host_argument_errors(lib):
     # copy probe with a size that is not a multiple of 16
     rc = lib.pip_probe_copy(dummy, dummy, 17, None)
     assert rc == _lib.PIP_EINVAL
+    rc = lib.pip_probe_read(dummy, 17, dummy, None)
+    assert rc == _lib.PIP_EINVAL
+    rc = lib.pip_probe_read(dummy, 16, None, None)
+    assert rc == _lib.PIP_EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):

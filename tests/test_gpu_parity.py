@@ -188,3 +188,19 @@ def test_validation_errors(P):
     with pytest.raises(P.PipError) as e:
         P.classify(**args(point_poly=None))
     assert e.value.code == -1
+
+
+def test_bandwidth_probes(P):
+    """The copy and read-stream probes the measurement uses: the copy is exact,
+    the read leaves its sink word alone or writes one word, sizes are checked."""
+    import torch
+    src = torch.arange(1 << 20, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    P.probe_copy(dst, src)
+    P.probe_read(src, sink)
+    P.probe_read(src[:0], sink)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    with pytest.raises(P.PipError):
+        P.probe_read(src[:3], sink)   # 12 bytes: not a multiple of 16
