@@ -138,6 +138,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle timing budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-clocks", action="store_true", help="skip reading clocks and power cap with rocm-smi")
     ap.add_argument("--no-extensions", action="store_true",
                     help="skip the extension measurements (constraint 2, several rings, candidate pairs, y-index)")
     ap.add_argument("--probe-copy-mb", type=int, default=0,
@@ -202,6 +203,21 @@ def cpu_baseline(w, budget_s: float):
             "cpu_model": cpu_model(),
             "single_thread": {"value": s1.n_tests / d1, "unit": "tests/s",
                               "sample": f"the first {n1} pairs, one pass, {d1:.3f} s"}}
+
+
+def device_clocks():
+    """The GPU's current clocks and power cap as rocm-smi reports them (a child
+    process; None when the tool is missing, fails or prints no JSON)."""
+    import shutil
+    import subprocess
+    exe = shutil.which("rocm-smi") or "/opt/rocm/bin/rocm-smi"
+    try:
+        r = subprocess.run([exe, "--showclocks", "--showmaxpower", "--json"], capture_output=True, text=True,
+                           timeout=20, stdin=subprocess.DEVNULL)
+        j = r.stdout[r.stdout.index("{"):]
+        return json.loads(j)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        return None
 
 
 def measured_peaks(P, dev, nbytes: int = 1 << 30, reps: int = 10):
@@ -421,6 +437,10 @@ def main():
                                    "(the pairs are independent: a multi-GPU split is a partition "
                                    "of polygons with their points, with no exchange)"}), flush=True)
         sys.exit(2)
+    clocks = None
+    if not a.no_clocks and not a.probe_copy_mb:
+        progress("device clocks (rocm-smi)")
+        clocks = device_clocks()
     import torch
     import paper_2306_04316_amd as P
     from paper_2306_04316_amd import workloads as W
@@ -603,6 +623,7 @@ def main():
         "compare": compare,
         "extensions": ext,
         "cpu_baseline": cpu,
+        "device_clocks": clocks,
         "wall_s_timed": wall,
         "gen_s": t_gen,
     }
