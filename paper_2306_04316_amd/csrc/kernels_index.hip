@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_bounds_root(const double2 *__restrict__
     shi[threadIdx.x] = hi;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
+        if ((int)threadIdx.x < o) {
             slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + o]);
             shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + o]);
         }
