@@ -139,6 +139,17 @@ def test_filtered_negative_control(P):
     note(f"negative control mismatches: {nbad}")
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("mode", ["exact", "filtered"])
+@pytest.mark.parametrize("name", ["footprints", "batched", "stress"])
+def test_plan_other_seeds(P, name, mode, seed):
+    """The same generators at other seeds, tuned plans, both modes."""
+    make = {"footprints": lambda: W.footprints(seed=seed, scale=0.01),
+            "batched": lambda: W.batched(seed=seed, scale=0.005),
+            "stress": lambda: W.stress(seed=seed, scale=0.01)}[name]
+    check_plan(P, make(), f"{name} seed {seed}", mode=mode, tune=1)
+
+
 @pytest.mark.parametrize("mode", ["exact", "filtered"])
 def test_graph_replays(P, mode):
     """Several replays of one captured graph, with eager work between them."""
