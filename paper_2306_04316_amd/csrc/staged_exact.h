@@ -135,8 +135,11 @@ __device__ __forceinline__ ItemRange item_range(int64_t p0, int64_t pairs, int64
 //   1. straddle pass: above_j = (y_j > p_y) for every vertex (one compare,
 //      exact), shifted into a 32-bit word, vertex j of the chunk at bit 31-j;
 //      straddle bits = above XOR above shifted by one (half-open rule);
-//   2. side tests only for the lane's straddling edges, lowest set bit first
-//      (the order of the tests does not matter: only their count's parity).
+//   2. side tests only for the lane's straddling edges, taken from the
+//      bit-reversed straddle word (bit b: the edge ending at chunk vertex b,
+//      so its record sits at a fixed stride from the chunk's first), lowest
+//      set bit first (the order of the tests does not matter: only their
+//      count's parity).
 // Returns the lane's parity (0 or 1).  Must be called by the whole wavefront.
 // above_prev: the above bit of the vertex before e0 in the ring (for a whole
 // ring, its last vertex); with own_prev set (a whole ring of at most 32
@@ -178,13 +181,14 @@ __device__ __forceinline__ uint32_t staged_ring_parity(const StagedLds &L, int e
         const int rc = rem < 0 ? 0 : (rem > 32 ? 32 : rem);
         strad &= (uint32_t)(0xffffffff00000000ull >> rc);
         above_prev = rem >= 32 ? (above & 1u) : above_prev;
-        // phase 2: side tests for this lane's straddling edges only; bit b
-        // is the edge ending at chunk vertex 31 - b
-        const int elast = e0 + c0 + 31;
+        // phase 2: side tests for this lane's straddling edges only; after
+        // the reversal bit b is the edge ending at chunk vertex b
+        strad = __builtin_bitreverse32(strad);
+        const double4 *er = L.E + (e0 + c0);
         while (strad != 0) {
             const int b = __builtin_ctz(strad);
             strad &= strad - 1u;
-            const double4 rec = L.E[elast - b];
+            const double4 rec = er[b];
             bool cr;
             if (PRED == kIntersection) {
                 const double lam = (yu - rec.y) / rec.w;
@@ -255,11 +259,13 @@ __device__ __forceinline__ uint32_t staged_poly_parity1(const StagedLds &L, int 
     const int kc = k < 0 ? 0 : (k > 32 ? 32 : k);
     strad &= (uint32_t)(0xffffffff00000000ull >> kc);
     uint32_t cnt = 0;
-    const int elast = e0 + 31;
+    // after the reversal bit b is the edge ending at chunk vertex b
+    strad = __builtin_bitreverse32(strad);
+    const double4 *er = L.E + e0;
     while (strad != 0) {
         const int b = __builtin_ctz(strad);
         strad &= strad - 1u;
-        const double4 rec = L.E[elast - b];
+        const double4 rec = er[b];
         bool cr;
         if (PRED == kIntersection) {
             const double lam = (yu - rec.y) / rec.w;
