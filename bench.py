@@ -55,24 +55,24 @@ WORKLOAD_TEXT = {
 PROFILED_TRAFFIC: dict = {
     # footprints, exact mode, k_staged_batched_fp64<0, 4, false, false, false>
     # (profiles/staged_footprints_exact.md: FETCH_SIZE and WRITE_SIZE scaled by the copy calibration)
-    (2, "exact", "f12a22754daa"): {"fetch_bytes": 220029037, "write_bytes": 10000000},
+    (2, "exact", "3490bb00a683"): {"fetch_bytes": 220034029, "write_bytes": 10000000},
     # footprints, filtered mode, k_filtered_fp32<4, false> (profiles/filtered_footprints.md)
-    (2, "filtered", "c2a8411c4263"): {"fetch_bytes": 220088553, "write_bytes": 10001760},
+    (2, "filtered", "ef05df756c55"): {"fetch_bytes": 220086121, "write_bytes": 10001760},
     # batched, both modes (profiles/staged_batched_exact.md, profiles/filtered_batched.md)
-    (4, "exact", "f12a22754daa"): {"fetch_bytes": 2415086080, "write_bytes": 100025920},
-    (4, "filtered", "c2a8411c4263"): {"fetch_bytes": 2413972181, "write_bytes": 100029504},
+    (4, "exact", "3490bb00a683"): {"fetch_bytes": 2415001030, "write_bytes": 100027584},
+    (4, "filtered", "ef05df756c55"): {"fetch_bytes": 2413919385, "write_bytes": 100029552},
 }
 
 # VALU instructions of the main kernel per launch (rocprofv3 --pmc SQ_INSTS_VALU, SQ_WAVES; median
 # over launches), keyed like PROFILED_TRAFFIC.
 PROFILED_VALU: dict = {
-    (2, "exact", "f12a22754daa"): {"valu_insts": 19081996, "waves": 39064,
+    (2, "exact", "3490bb00a683"): {"valu_insts": 19025260, "waves": 39064,
                                    "source": "profiles/staged_footprints_exact.md"},
-    (2, "filtered", "c2a8411c4263"): {"valu_insts": 26096941, "waves": 39064,
+    (2, "filtered", "ef05df756c55"): {"valu_insts": 26096941, "waves": 39064,
                                       "source": "profiles/filtered_footprints.md"},
-    (4, "exact", "f12a22754daa"): {"valu_insts": 440684136, "waves": 390656,
+    (4, "exact", "3490bb00a683"): {"valu_insts": 431314460, "waves": 390656,
                                    "source": "profiles/staged_batched_exact.md"},
-    (4, "filtered", "c2a8411c4263"): {"valu_insts": 505138776, "waves": 390656,
+    (4, "filtered", "ef05df756c55"): {"valu_insts": 498057611, "waves": 390656,
                                       "source": "profiles/filtered_batched.md"},
 }
 SIMDS = 1024          # 256 compute units x 4 SIMDs
