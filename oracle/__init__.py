@@ -64,6 +64,10 @@ def load(mutant: int = 0) -> ctypes.CDLL:
                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                   ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    f = lib.pip_oracle_classify_indexed
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     f = lib.pip_oracle_bbox_join
     f.restype = ctypes.c_int
     f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
@@ -99,6 +103,27 @@ def classify(px, py, offsets, vx, vy, point_poly=None, nthreads: int | None = No
             _ptr(vx), _ptr(vy), _ptr(point_poly), _ptr(out), int(nthreads))
     if rc != 0:
         raise ValueError(f"pip_oracle_classify rejected its arguments (rc={rc})")
+    return out
+
+
+def classify_indexed(px, py, offsets, vx, vy, nthreads: int | None = None, mutant: int = 0) -> np.ndarray:
+    """One ring against many points, with the edges that cannot straddle a point's
+    ray skipped through an exact y index (pip_oracle_classify_indexed): the same
+    bits as classify(), in time proportional to the straddling edges."""
+    px = np.ascontiguousarray(px, dtype=np.float64)
+    py = np.ascontiguousarray(py, dtype=np.float64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    vx = np.ascontiguousarray(vx, dtype=np.float64)
+    vy = np.ascontiguousarray(vy, dtype=np.float64)
+    if offsets.shape[0] != 2 or py.shape[0] != px.shape[0] or offsets[-1] > vx.shape[0]:
+        raise ValueError("the indexed mode takes one ring and matching point arrays")
+    out = np.empty(px.shape[0], dtype=np.uint8)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    rc = load(mutant).pip_oracle_classify_indexed(_ptr(px), _ptr(py), px.shape[0], _ptr(offsets), 1, _ptr(vx),
+                                                  _ptr(vy), _ptr(out), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"pip_oracle_classify_indexed failed (rc={rc})")
     return out
 
 

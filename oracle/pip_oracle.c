@@ -44,6 +44,50 @@
 #define PIP_ORACLE_MUTANT 0
 #endif
 
+/* Whether edge (a, b) counts for the ray from point (x, y): the straddle
+ * test, then the side of p against the edge's oriented normal. */
+static int edge_counts(double x, double y, double ax, double ay, double bx, double by)
+{
+    /* candidate crossing: endpoints on opposite sides of y = p_y (half-open) */
+#if PIP_ORACLE_MUTANT == 5
+    int a_above = ay >= y, b_above = by >= y;
+#else
+    int a_above = ay > y, b_above = by > y;
+#endif
+    if (a_above == b_above)
+        return 0;
+
+    /* edge normal, oriented to make an acute angle with the ray (1, 0) */
+    double nx = by - ay;
+#if PIP_ORACLE_MUTANT == 6
+    double ny = bx - ax;
+#else
+    double ny = ax - bx;
+#endif
+#if PIP_ORACLE_MUTANT != 3
+    if (nx < 0) {
+        nx = -nx;
+        ny = -ny;
+    }
+#endif
+    /* side of p relative to the edge's line, anchored at a */
+#if PIP_ORACLE_MUTANT == 2
+    double t1 = x - bx, t2 = y - by;
+#else
+    double t1 = x - ax, t2 = y - ay;
+#endif
+#if PIP_ORACLE_MUTANT == 7
+    double s = t1 * ny + t2 * nx;
+#else
+    double s = t1 * nx + t2 * ny;
+#endif
+#if PIP_ORACLE_MUTANT == 1
+    return s < 0;
+#else
+    return s <= 0;
+#endif
+}
+
 /* Parity of the ray crossings of point (x, y) against the ring vx/vy[0..k). */
 static int ring_parity(double x, double y, const double *vx, const double *vy, int64_t k)
 {
@@ -55,48 +99,7 @@ static int ring_parity(double x, double y, const double *vx, const double *vy, i
 #endif
     for (int64_t i = 0; i < nedges; ++i) {
         int64_t j = (i + 1 == k) ? 0 : i + 1;
-        double ax = vx[i], ay = vy[i];
-        double bx = vx[j], by = vy[j];
-
-        /* candidate crossing: endpoints on opposite sides of y = p_y (half-open) */
-#if PIP_ORACLE_MUTANT == 5
-        int a_above = ay >= y, b_above = by >= y;
-#else
-        int a_above = ay > y, b_above = by > y;
-#endif
-        if (a_above == b_above)
-            continue;
-
-        /* edge normal, oriented to make an acute angle with the ray (1, 0) */
-        double nx = by - ay;
-#if PIP_ORACLE_MUTANT == 6
-        double ny = bx - ax;
-#else
-        double ny = ax - bx;
-#endif
-#if PIP_ORACLE_MUTANT != 3
-        if (nx < 0) {
-            nx = -nx;
-            ny = -ny;
-        }
-#endif
-        /* side of p relative to the edge's line, anchored at a */
-#if PIP_ORACLE_MUTANT == 2
-        double t1 = x - bx, t2 = y - by;
-#else
-        double t1 = x - ax, t2 = y - ay;
-#endif
-#if PIP_ORACLE_MUTANT == 7
-        double s = t1 * ny + t2 * nx;
-#else
-        double s = t1 * nx + t2 * ny;
-#endif
-#if PIP_ORACLE_MUTANT == 1
-        if (s < 0)
-#else
-        if (s <= 0)
-#endif
-            ++count;
+        count += edge_counts(x, y, vx[i], vy[i], vx[j], vy[j]);
     }
     return (int)(count & 1);
 }
@@ -408,5 +411,175 @@ int pip_oracle_bbox_join(const double *px, const double *py, int64_t n_points,
     proto.pair_point = pair_point;
     join_run(&proto, n_polys, nthreads);
     free(starts);
+    return 0;
+}
+
+/*
+ * Indexed mode for one ring (the parity check of a huge ring against many
+ * points, where the plain double loop would take hours): the same rule, with
+ * the edges that cannot straddle a point's ray skipped through an exact y
+ * index.  Edge (a, b) straddles the ray at p_y exactly when
+ * min(a_y, b_y) <= p_y < max(a_y, b_y).  Points and edges are placed in
+ * buckets by bucket(y) = floor((y - y_lo) * scale), clamped to [0, nb - 1]:
+ * a non-decreasing function of y (every rounded operation in it is monotone),
+ * so an edge listed in every bucket from bucket(min) to bucket(max) is listed
+ * in the bucket of each point whose ray it straddles.  A point applies the
+ * full rule (edge_counts) to the edges of its bucket; the edges it skips are
+ * ones that contribute nothing, and the count's parity does not depend on the
+ * order, so the result equals pip_oracle_classify's bit for bit.
+ */
+typedef struct {
+    const double *px, *py;
+    const double *vx, *vy;
+    int64_t k;
+    const int64_t *start, *list;
+    double ylo, scale;
+    int64_t nb;
+    uint8_t *out;
+    int64_t i0, i1;
+} index_job;
+
+static int64_t bucket_of(double y, double ylo, double scale, int64_t nb)
+{
+    double t = (y - ylo) * scale;
+    if (!(t > 0))
+        return 0;
+    if (t >= (double)nb)
+        return nb - 1;
+    return (int64_t)t;
+}
+
+static void *index_worker(void *arg)
+{
+    const index_job *j = (const index_job *)arg;
+    for (int64_t i = j->i0; i < j->i1; ++i) {
+        double x = j->px[i], y = j->py[i];
+        int64_t b = bucket_of(y, j->ylo, j->scale, j->nb);
+        int64_t count = 0;
+        for (int64_t t = j->start[b]; t < j->start[b + 1]; ++t) {
+            int64_t e = j->list[t];
+            int64_t f = (e + 1 == j->k) ? 0 : e + 1;
+            count += edge_counts(x, y, j->vx[e], j->vy[e], j->vx[f], j->vy[f]);
+        }
+        j->out[i] = (uint8_t)(count & 1);
+    }
+    return NULL;
+}
+
+/* Edges listed per bucket for nb buckets; total entries, or -1 when over cap. */
+static int64_t index_entries(const double *vy, int64_t k, double ylo, double scale, int64_t nb, int64_t cap)
+{
+    int64_t total = 0;
+    for (int64_t e = 0; e < k; ++e) {
+        int64_t f = (e + 1 == k) ? 0 : e + 1;
+        double lo = vy[e] < vy[f] ? vy[e] : vy[f], hi = vy[e] < vy[f] ? vy[f] : vy[e];
+        if (!(lo < hi))
+            continue;   /* horizontal: never straddles */
+        total += bucket_of(hi, ylo, scale, nb) - bucket_of(lo, ylo, scale, nb) + 1;
+        if (total > cap)
+            return -1;
+    }
+    return total;
+}
+
+int pip_oracle_classify_indexed(const double *px, const double *py, int64_t n_points, const int64_t *offsets,
+                                int64_t n_polys, const double *vx, const double *vy, uint8_t *out, int nthreads)
+{
+    if (n_points < 0 || n_polys != 1 || !offsets || (n_points > 0 && (!px || !py || !out)))
+        return -1;
+    int64_t b0 = offsets[0], k = offsets[1] - offsets[0];
+    if (k < 0 || b0 < 0)
+        return -1;
+    const double *rx = vx + b0, *ry = vy + b0;
+    double ylo = 0.0, yhi = 0.0;
+    for (int64_t e = 0; e < k; ++e) {
+        if (e == 0 || ry[e] < ylo)
+            ylo = ry[e];
+        if (e == 0 || ry[e] > yhi)
+            yhi = ry[e];
+    }
+    int64_t nb = k < (1 << 20) ? (k > 0 ? k : 1) : (1 << 20);
+    double scale = 0.0;
+    int64_t total = -1;
+    for (;;) {
+        scale = yhi > ylo ? (double)nb / (yhi - ylo) : 0.0;
+        if (!(scale < 1e300))
+            scale = 0.0;   /* a degenerate y range: one bucket in effect */
+        total = index_entries(ry, k, ylo, scale, nb, 16 * k + nb);
+        if (total >= 0 || nb == 1)
+            break;
+        nb /= 2;
+    }
+    if (total < 0)
+        total = index_entries(ry, k, ylo, scale, nb, INT64_MAX);
+    int64_t *start = (int64_t *)calloc((size_t)nb + 1, sizeof(int64_t));
+    int64_t *list = (int64_t *)malloc((size_t)(total > 0 ? total : 1) * sizeof(int64_t));
+    if (!start || !list) {
+        free(start);
+        free(list);
+        return -2;
+    }
+    for (int64_t e = 0; e < k; ++e) {
+        int64_t f = (e + 1 == k) ? 0 : e + 1;
+        double lo = ry[e] < ry[f] ? ry[e] : ry[f], hi = ry[e] < ry[f] ? ry[f] : ry[e];
+        if (!(lo < hi))
+            continue;
+        for (int64_t b = bucket_of(lo, ylo, scale, nb); b <= bucket_of(hi, ylo, scale, nb); ++b)
+            start[b + 1]++;
+    }
+    for (int64_t b = 0; b < nb; ++b)
+        start[b + 1] += start[b];
+    int64_t *fill = (int64_t *)malloc((size_t)nb * sizeof(int64_t));
+    if (!fill) {
+        free(start);
+        free(list);
+        return -2;
+    }
+    for (int64_t b = 0; b < nb; ++b)
+        fill[b] = start[b];
+    for (int64_t e = 0; e < k; ++e) {
+        int64_t f = (e + 1 == k) ? 0 : e + 1;
+        double lo = ry[e] < ry[f] ? ry[e] : ry[f], hi = ry[e] < ry[f] ? ry[f] : ry[e];
+        if (!(lo < hi))
+            continue;
+        for (int64_t b = bucket_of(lo, ylo, scale, nb); b <= bucket_of(hi, ylo, scale, nb); ++b)
+            list[fill[b]++] = e;
+    }
+    free(fill);
+
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    index_job jobs[256];
+    pthread_t th[256];
+    int started[256] = {0};
+    int64_t chunk = (n_points + nthreads - 1) / nthreads;
+    for (int t = 0; t < nthreads; ++t) {
+        index_job *j = &jobs[t];
+        j->px = px;
+        j->py = py;
+        j->vx = rx;
+        j->vy = ry;
+        j->k = k;
+        j->start = start;
+        j->list = list;
+        j->ylo = ylo;
+        j->scale = scale;
+        j->nb = nb;
+        j->out = out;
+        j->i0 = (int64_t)t * chunk < n_points ? (int64_t)t * chunk : n_points;
+        j->i1 = j->i0 + chunk < n_points ? j->i0 + chunk : n_points;
+        if (t > 0 && j->i0 < j->i1)
+            started[t] = pthread_create(&th[t], NULL, index_worker, j) == 0;
+        if (t > 0 && j->i0 < j->i1 && !started[t])
+            index_worker(j);
+    }
+    index_worker(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t)
+        if (started[t])
+            pthread_join(th[t], NULL);
+    free(start);
+    free(list);
     return 0;
 }
