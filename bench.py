@@ -121,7 +121,7 @@ def parse():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", default="exact", choices=["exact", "filtered"])
-    ap.add_argument("--kernel", default="auto", choices=["auto", "per_pair", "segmented", "staged", "runs"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "per_pair", "segmented", "staged", "runs", "batched"])
     ap.add_argument("--pairs-per-lane", type=int, default=0)
     ap.add_argument("--lds-slots", type=int, default=0)
     ap.add_argument("--persistent", type=int, default=-1)

@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PIP_ABI_VERSION 2
+#define PIP_ABI_VERSION 3
 
 #if defined(__GNUC__) || defined(__clang__)
 #define PIP_API __attribute__((visibility("default")))
@@ -83,9 +83,9 @@ typedef enum {
 typedef enum {
     /* every side value in binary64, in the rule's operation order */
     PIP_MODE_EXACT_FP64 = 0,
-    /* binary32 on per-polygon re-centred coordinates with a proven forward
-     * error bound; a pair with any undecided edge is re-run in binary64 in
-     * the rule's operation order (plans only) */
+    /* binary32 side values on per-polygon re-centred coordinates with a
+     * proven forward error bound; a pair with any undecided edge is re-run in
+     * binary64 in the rule's operation order */
     PIP_MODE_FILTERED_FP32 = 1
 } pip_mode;
 
@@ -118,7 +118,14 @@ typedef enum {
      * polygon id (at most 64 pairs each) and walks each run's ring
      * wave-uniformly: an exact straddle pass into per-lane bit words, then
      * side values only for each lane's straddling edges */
-    PIP_KERNEL_RUNS = 4
+    PIP_KERNEL_RUNS = 4,
+    /* one lane per pair, both modes; a workgroup walks the vertex range of its
+     * (sorted) pairs in LDS tiles, builds every edge's record there once
+     * (binary64, or binary32 re-centred on the ring's first vertex in the
+     * filtered mode) and each lane walks its own ring: straddle tests exact
+     * (binary64 comparisons) in both modes, side values only for straddling
+     * edges.  Constraint 1, one ring per polygon. */
+    PIP_KERNEL_BATCHED = 5
 } pip_kernel;
 
 typedef struct {
@@ -162,6 +169,10 @@ typedef struct {
                                visit the points in y order, so whole groups of
                                edges are skipped by comparisons (same bits; work
                                no longer proportional to every edge) */
+    int32_t stats;          /* plans, PIP_KERNEL_BATCHED: 1 = count point-edge tests
+                               and undecided binary32 side tests on the device at
+                               every execution (a kernel variant with counters;
+                               pip_stats.tests / ambiguous_tests), 0 = no counts */
 } pip_options;
 
 /* Configuration a plan runs with (after automatic choices and tuning). */
@@ -184,6 +195,12 @@ typedef struct {
 /* Figures of a plan's last execution (see pip_plan_stats). */
 typedef struct {
     uint64_t pairs;             /* pairs the plan classifies */
+    uint64_t tests;             /* point-edge tests (sum of the tested rings'
+                                   vertex counts), counted on the device by plans
+                                   created with stats = 1; 0 otherwise */
+    uint64_t ambiguous_tests;   /* filtered mode, stats = 1: side tests whose
+                                   binary32 value fell inside the error bound (a
+                                   pair with any such test is rechecked) */
     uint64_t rechecked_pairs;   /* pairs re-run in binary64 (filtered mode) */
     float ms_prep;              /* device time: counter resets and item ordering */
     float ms_main;              /* device time: main kernel */
@@ -203,11 +220,16 @@ PIP_API const char *pip_last_error(void);
 
 /*
  * Classify n_points points (see the layout above).  opts may be NULL
- * (defaults).  n_points == 0 is a no-op.  Only PIP_MODE_EXACT_FP64 is
- * accepted here (the filtered mode needs a plan's workspace).  Allocates
- * nothing on the device.  Asynchronous on `stream` unless opts->validate.
- * The plan-only options (persistent, order, use_graph, tune, tune_cache) are
- * ignored here.
+ * (defaults).  n_points == 0 is a no-op.  Asynchronous on `stream` unless
+ * opts->validate.  The plan-only options (persistent, order, use_graph, tune,
+ * tune_cache, timing, stats) are ignored here.
+ * PIP_MODE_EXACT_FP64 allocates nothing on the device.
+ * PIP_MODE_FILTERED_FP32 runs the batched kernel (PIP_KERNEL_AUTO or
+ * PIP_KERNEL_BATCHED; constraint 1, one ring per polygon, n_points below
+ * 2^31, else PIP_EINVAL) followed by the binary64 recheck; its list of
+ * undecided pairs (4 bytes per point) is a stream-ordered allocation from a
+ * device-memory pool of the library's own (one per device, released memory
+ * kept for later calls), freed in stream order after the recheck.
  */
 PIP_API int pip_classify(const double *px, const double *py, int64_t n_points,
                  const int64_t *offsets, int64_t n_polys,
@@ -273,10 +295,13 @@ PIP_API int pip_plan_create_rings(pip_plan **out,
                           const int32_t *point_poly, uint8_t *inside,
                           const pip_options *opts, void *stream);
 
-/* Enqueue one execution on `stream` (asynchronous). */
-PIP_API int pip_plan_execute(pip_plan *plan, void *stream);
+/* Enqueue one execution on `stream`.  stats NULL: asynchronous.  stats
+ * non-NULL: waits for the execution to complete on `stream` and fills *stats
+ * as pip_plan_stats does. */
+PIP_API int pip_plan_execute(pip_plan *plan, pip_stats *stats, void *stream);
 
-/* Waits for the plan's last execution and reports its figures (the phase
+/* Waits for the plan's last execution (synchronises the stream it was
+ * enqueued on, which must still exist) and reports its figures (the phase
  * times only when the plan was created with timing = 1). */
 PIP_API int pip_plan_stats(pip_plan *plan, pip_stats *stats);
 

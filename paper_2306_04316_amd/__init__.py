@@ -48,7 +48,7 @@ def _stream_handle(stream):
 
 def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block=0, lds_slots=0,
             persistent=-1, order=-1, use_graph=True, tune=0, force_recheck=False, bound_scale=1.0,
-            tune_cache=None, timing=False, index=False, predicate="side") -> _lib.pip_options:
+            tune_cache=None, timing=False, index=False, predicate="side", stats=False) -> _lib.pip_options:
     o = _lib.pip_options()
     _lib.load().pip_options_init(ctypes.byref(o))
     o.mode = _lib.MODES[mode] if isinstance(mode, str) else int(mode)
@@ -68,6 +68,7 @@ def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block
     o.timing = 2 if (timing == 2 or timing == "kernel") else (1 if timing else 0)
     o.index = 1 if index else 0
     o.predicate = _lib.PREDICATES[predicate] if isinstance(predicate, str) else int(predicate)
+    o.stats = 1 if stats else 0
     return o
 
 
@@ -125,10 +126,16 @@ class Plan:
         _lib.check(rc)
         self._h = h
 
-    def execute(self, stream=None):
+    def execute(self, stream=None, stats=False):
+        """Enqueue one execution; with stats=True wait for it and return its
+        figures (a dict, as stats()) instead of the output tensor."""
         import torch
+        st = _lib.pip_stats() if stats else None
         with torch.cuda.device(self.device):
-            _lib.check(self._lib.pip_plan_execute(self._h, _stream_handle(stream)))
+            _lib.check(self._lib.pip_plan_execute(self._h, ctypes.byref(st) if stats else None,
+                                                  _stream_handle(stream)))
+        if stats:
+            return {f: getattr(st, f) for f, _ in _lib.pip_stats._fields_}
         return self.out
 
     def stats(self) -> dict:
@@ -160,13 +167,17 @@ class Plan:
 
 
 def classify(px, py, offsets, vx, vy, point_poly=None, *, kernel="auto", validate=False, out=None,
-             stream=None, pairs_per_lane=0, block=0, lds_slots=0, predicate="side"):
-    """inside[i] for point i against polygon point_poly[i] (or polygon 0)."""
+             stream=None, pairs_per_lane=0, block=0, lds_slots=0, predicate="side", mode="exact",
+             force_recheck=False, bound_scale=1.0):
+    """inside[i] for point i against polygon point_poly[i] (or polygon 0).
+    mode="filtered": binary32 side values with the binary64 recheck (pip_classify's
+    filtered mode, workspace from the library's device-memory pool)."""
     import torch
     lib = _lib.load()
     n = px.numel()
     out = _check_inputs(px, py, offsets, vx, vy, point_poly, out)
-    o = options("exact", kernel, validate, pairs_per_lane, block, lds_slots, predicate=predicate)
+    o = options(mode, kernel, validate, pairs_per_lane, block, lds_slots, predicate=predicate,
+                force_recheck=force_recheck, bound_scale=bound_scale)
     with torch.cuda.device(px.device):
         rc = lib.pip_classify(_ptr(px), _ptr(py), n, _ptr(offsets), offsets.numel() - 1, _ptr(vx), _ptr(vy),
                               vx.numel(), _ptr(point_poly), _ptr(out), ctypes.byref(o), _stream_handle(stream))

@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "PIP_OK", -1: "PIP_EINVAL", -2: "PIP_ERANGE", -3: "PIP_EDOM",
                 -5: "PIP_EHIP", -6: "PIP_ENOTSUP"}
 
 MODES = {"exact": 0, "fp64": 0, "filtered": 1, "fp32": 1}
-KERNELS = {"auto": 0, "per_pair": 1, "segmented": 2, "staged": 3, "runs": 4}
+KERNELS = {"auto": 0, "per_pair": 1, "segmented": 2, "staged": 3, "runs": 4, "batched": 5}
 PREDICATES = {"side": 0, "c1": 0, "intersection": 1, "c2": 1}
 
 
@@ -28,7 +28,7 @@ class pip_options(ctypes.Structure):
                 ("lds_slots", ctypes.c_int32), ("persistent", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("tune", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
                 ("bound_scale", ctypes.c_float), ("tune_cache", ctypes.c_char_p), ("timing", ctypes.c_int32),
-                ("predicate", ctypes.c_int32), ("index", ctypes.c_int32)]
+                ("predicate", ctypes.c_int32), ("index", ctypes.c_int32), ("stats", ctypes.c_int32)]
 
 
 class pip_plan_config(ctypes.Structure):
@@ -40,7 +40,8 @@ class pip_plan_config(ctypes.Structure):
 
 
 class pip_stats(ctypes.Structure):
-    _fields_ = [("pairs", ctypes.c_uint64), ("rechecked_pairs", ctypes.c_uint64), ("ms_prep", ctypes.c_float),
+    _fields_ = [("pairs", ctypes.c_uint64), ("tests", ctypes.c_uint64), ("ambiguous_tests", ctypes.c_uint64),
+                ("rechecked_pairs", ctypes.c_uint64), ("ms_prep", ctypes.c_float),
                 ("ms_main", ctypes.c_float), ("ms_recheck", ctypes.c_float)]
 
 
@@ -65,7 +66,7 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_int64), _VP]),
     "pip_join_fill": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pip_join_destroy": (ctypes.c_int, [_VP]),
-    "pip_plan_execute": (ctypes.c_int, [_VP, _VP]),
+    "pip_plan_execute": (ctypes.c_int, [_VP, ctypes.POINTER(pip_stats), _VP]),
     "pip_plan_stats": (ctypes.c_int, [_VP, ctypes.POINTER(pip_stats)]),
     "pip_plan_timing": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                        ctypes.POINTER(ctypes.c_float)]),

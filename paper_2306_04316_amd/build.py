@@ -33,8 +33,50 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+def _compile_objects(objdir: str, verbose: bool) -> list:
+    """One hipcc per source, in parallel; returns the object files."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(objdir, exist_ok=True)
+    cflags = [f for f in FLAGS if f != "-shared"]
+
+    def one(src):
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = ["hipcc", *cflags, f"-I{INCLUDE}", f"-I{CSRC}", "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True, cwd=PKG)
+        return src, obj, r
+
+    jobs = max(1, min(8, os.cpu_count() or 1))
+    objs = []
+    with ThreadPoolExecutor(jobs) as ex:
+        for src, obj, r in ex.map(one, sources()):
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError(f"hipcc failed compiling {src}")
+            objs.append(obj)
+    return objs
+
+
 def build(save_temps: str | None = None, verbose: bool = False) -> str:
     tmp = LIB + f".tmp{os.getpid()}"
+    if not save_temps:
+        # compile the sources in parallel, then link them into the library
+        objdir = os.path.join(PKG, "_build", f"obj{os.getpid()}")
+        try:
+            objs = _compile_objects(objdir, verbose)
+            cmd = ["hipcc", *FLAGS, *objs, "-o", tmp]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            r = subprocess.run(cmd, capture_output=True, text=True, cwd=PKG)
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError(f"hipcc failed linking {LIB}")
+        finally:
+            import shutil
+            shutil.rmtree(objdir, ignore_errors=True)
+        os.replace(tmp, LIB)
+        return LIB
     cmd = ["hipcc", *FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *sources(), "-o", tmp]
     if save_temps:
         os.makedirs(save_temps, exist_ok=True)

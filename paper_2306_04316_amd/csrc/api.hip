@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "pip_common.h"
@@ -17,6 +18,7 @@ thread_local char g_err[512] = "";
 // Flag word written by the validation kernels (one per device; concurrent
 // validating calls on one device share it).
 __device__ unsigned g_validate_word;
+
 
 std::mutex g_dev_mu;
 std::vector<DeviceInfo *> g_devs;
@@ -95,6 +97,17 @@ int clamp_lds_slots(int lds_slots, bool filtered, int pairs_per_lane, const Devi
     return lds_slots;
 }
 
+// Largest LDS tile (vertices, halved from the request) whose batched layout
+// fits a workgroup's LDS.
+int clamp_batched_tile(int tile, bool filtered, int pairs_per_lane, const DeviceInfo *dev)
+{
+    tile = tile < 32 ? 32 : (tile > 2048 ? 2048 : tile);
+    const int rings = staged_max_rings(pairs_per_lane);
+    while (tile > 32 && batched_smem_bytes(tile, rings, filtered) > dev->lds_per_block)
+        tile /= 2;
+    return tile;
+}
+
 int check_host_args(const Problem &p)
 {
     if (p.n_points < 0 || p.n_polys < 1 || p.n_vertices < 0)
@@ -114,6 +127,66 @@ int check_host_args(const Problem &p)
     if (p.n_points > 0 && !p.point_poly && p.n_polys != 1)
         return fail(PIP_EINVAL, "point_poly is NULL but n_polys=%lld (must be 1)", (long long)p.n_polys);
     return PIP_OK;
+}
+
+namespace {
+std::mutex g_pool_mu;
+std::unordered_map<int, hipMemPool_t> g_pools;
+
+hipMemPool_t workspace_pool(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pools.find(dev);
+    if (it != g_pools.end())
+        return it->second;
+    hipMemPoolProps props = {};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    const hipError_t ce = hipMemPoolCreate(&pool, &props);
+    if (ce != hipSuccess) {
+        (void)hipGetLastError();
+        log_msg("workspace pool unavailable on device %d (%s): plain allocations", dev, hipGetErrorString(ce));
+        pool = nullptr;
+    } else {
+        uint64_t keep = UINT64_MAX;   // never trim on synchronisation
+        if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess)
+            (void)hipGetLastError();
+    }
+    g_pools[dev] = pool;
+    return pool;
+}
+}  // namespace
+
+hipError_t pool_alloc(void **p, size_t bytes, int dev, hipStream_t s, bool *pooled)
+{
+    hipMemPool_t pool = workspace_pool(dev);
+    if (pool) {
+        const hipError_t e = hipMallocFromPoolAsync(p, bytes, pool, s);
+        if (e == hipSuccess) {
+            *pooled = true;
+            return e;
+        }
+        (void)hipGetLastError();
+        log_msg("workspace pool allocation of %zu bytes failed (%s): plain allocation", bytes, hipGetErrorString(e));
+    }
+    *pooled = false;
+    return hipMalloc(p, bytes);
+}
+
+void pool_release(void *p, bool pooled, hipStream_t s)
+{
+    if (!p)
+        return;
+    if (pooled) {
+        if (hipFreeAsync(p, s) != hipSuccess)
+            (void)hipGetLastError();
+        return;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess)
+        (void)hipGetLastError();
+    (void)hipFree(p);
 }
 
 int validate_on_device(const Problem &p, DeviceInfo *dev, hipStream_t stream)
@@ -154,6 +227,7 @@ void pip_options_init(pip_options *opts)
     opts->timing = 0;
     opts->index = 0;
     opts->predicate = PIP_PRED_SIDE;
+    opts->stats = 0;
 }
 
 int pip_abi_version(void) { return PIP_ABI_VERSION; }
@@ -164,6 +238,38 @@ const char *pip_last_error(void) { return g_err; }
 
 namespace pip {
 namespace {
+// The filtered mode of pip_classify: the batched kernel in binary32 with its
+// list of undecided pairs (list length word, padded to 256 bytes, then
+// n_points list entries), then the binary64 recheck of the list.  The
+// workspace is a pooled, stream-ordered allocation, or `fixed` when the
+// caller provides it.
+int classify_filtered(const Problem &p, DeviceInfo *dev, const pip_options &o, hipStream_t s, unsigned char *fixed)
+{
+    const int u = o.pairs_per_lane == 1 ? 1 : (o.pairs_per_lane == 4 ? 4 : 2);
+    const int tile = clamp_batched_tile(o.lds_slots > 0 ? o.lds_slots : 512, true, u, dev);
+    void *ws = fixed;
+    bool pooled = false;
+    const size_t bytes = 256 + (size_t)p.n_points * sizeof(int32_t);
+    if (!fixed) {
+        hipError_t e = pool_alloc(&ws, bytes, dev->device, s, &pooled);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(PIP_ENOMEM, "filtered workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+        }
+    }
+    unsigned *count = (unsigned *)ws;
+    int32_t *list = (int32_t *)((unsigned char *)ws + 256);
+    int rc = launch_fill(count, 1, 0u, s);
+    if (rc == PIP_OK)
+        rc = launch_batched(p, s, true, u, tile, o.bound_scale, o.force_recheck, list, count, nullptr, nullptr,
+                            (int)((p.n_points + 256 * u - 1) / (256 * u)));
+    if (rc == PIP_OK)
+        rc = launch_recheck(p, s, list, count, dev->cu_count * 8);
+    if (!fixed)
+        pool_release(ws, pooled, s);
+    return rc;
+}
+
 int classify_problem(Problem p, const pip_options *opts, void *stream)
 {
     pip_options o;
@@ -174,10 +280,23 @@ int classify_problem(Problem p, const pip_options *opts, void *stream)
                         sizeof(pip_options));
         o = *opts;
     }
-    if (o.mode != PIP_MODE_EXACT_FP64)
-        return fail(PIP_EINVAL, "pip_classify supports PIP_MODE_EXACT_FP64 only (mode=%d); use a plan", o.mode);
-    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_RUNS)
+    if (o.mode != PIP_MODE_EXACT_FP64 && o.mode != PIP_MODE_FILTERED_FP32)
+        return fail(PIP_EINVAL, "unknown mode %d", o.mode);
+    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_BATCHED)
         return fail(PIP_EINVAL, "unknown kernel %d", o.kernel);
+    if (o.mode == PIP_MODE_FILTERED_FP32) {
+        if (o.kernel != PIP_KERNEL_AUTO && o.kernel != PIP_KERNEL_BATCHED)
+            return fail(PIP_EINVAL, "pip_classify runs the filtered mode on the batched kernel only");
+        if (p.poly_rings)
+            return fail(PIP_ENOTSUP, "the filtered mode takes one ring per polygon");
+        if (o.predicate != PIP_PRED_SIDE)
+            return fail(PIP_ENOTSUP, "the filtered mode implements the side test (constraint 1) only");
+        if (p.n_points > INT32_MAX)
+            return fail(PIP_EINVAL, "n_points=%lld: the filtered mode takes fewer than 2^31 pairs",
+                        (long long)p.n_points);
+    }
+    if (o.kernel == PIP_KERNEL_BATCHED && (p.poly_rings || o.predicate != PIP_PRED_SIDE))
+        return fail(PIP_ENOTSUP, "the batched kernel takes one ring per polygon and the side test only");
     if (o.predicate != PIP_PRED_SIDE && o.predicate != PIP_PRED_INTERSECTION)
         return fail(PIP_EINVAL, "unknown predicate %d", o.predicate);
     p.pred = o.predicate;
@@ -189,6 +308,14 @@ int classify_problem(Problem p, const pip_options *opts, void *stream)
         PIP_TRY(validate_on_device(p, dev, s));
     if (p.n_points == 0)
         return PIP_OK;
+    if (o.mode == PIP_MODE_FILTERED_FP32)
+        return classify_filtered(p, dev, o, s, nullptr);
+    if (o.kernel == PIP_KERNEL_BATCHED) {
+        const int u = o.pairs_per_lane == 1 ? 1 : (o.pairs_per_lane == 4 ? 4 : 2);
+        return launch_batched(p, s, false, u, clamp_batched_tile(o.lds_slots > 0 ? o.lds_slots : 512, false, u, dev),
+                              1.0f, 0, nullptr, nullptr,
+                              nullptr, nullptr, (int)((p.n_points + 256 * u - 1) / (256 * u)));
+    }
     if (o.kernel == PIP_KERNEL_PER_PAIR)
         return launch_per_pair(p, s);
     if (o.kernel == PIP_KERNEL_SEGMENTED)

@@ -276,77 +276,6 @@ __global__ __launch_bounds__(256) void k_units(const int64_t *__restrict__ unit_
 
 using namespace pip;
 
-// ---------------------------------------------------------------- workspace pool
-// A join's workspace (hundreds of MB for 10^7 points) comes from a memory pool
-// of the library's own, one per device, that keeps released memory for the
-// next join instead of returning it to the driver: creating and destroying a
-// join then costs no device-memory mapping and unmapping.  Falls back to
-// hipMalloc / hipFree where the pool cannot be created.
-namespace {
-
-std::mutex g_pool_mu;
-std::unordered_map<int, hipMemPool_t> g_pools;
-
-hipMemPool_t workspace_pool(int dev)
-{
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    auto it = g_pools.find(dev);
-    if (it != g_pools.end())
-        return it->second;
-    hipMemPoolProps props = {};
-    props.allocType = hipMemAllocationTypePinned;
-    props.location.type = hipMemLocationTypeDevice;
-    props.location.id = dev;
-    hipMemPool_t pool = nullptr;
-    const hipError_t ce = hipMemPoolCreate(&pool, &props);
-    if (ce != hipSuccess) {
-        (void)hipGetLastError();
-        log_msg("join workspace pool unavailable on device %d (%s): plain allocations", dev, hipGetErrorString(ce));
-        pool = nullptr;
-    } else {
-        uint64_t keep = UINT64_MAX;   // never trim on synchronisation
-        if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess)
-            (void)hipGetLastError();
-    }
-    g_pools[dev] = pool;
-    return pool;
-}
-
-// Stream-ordered allocation from the device's pool (or plain hipMalloc).
-hipError_t ws_alloc(void **p, size_t bytes, int dev, hipStream_t s, bool *pooled)
-{
-    hipMemPool_t pool = workspace_pool(dev);
-    if (pool) {
-        const hipError_t e = hipMallocFromPoolAsync(p, bytes, pool, s);
-        if (e == hipSuccess) {
-            *pooled = true;
-            return e;
-        }
-        (void)hipGetLastError();
-        log_msg("join workspace pool allocation of %zu bytes failed (%s): plain allocation", bytes,
-                hipGetErrorString(e));
-    }
-    *pooled = false;
-    return hipMalloc(p, bytes);
-}
-
-// Release once the device is idle (callers synchronise first).  A pooled
-// block goes back to the pool in stream order on the null stream, with no
-// host wait: the pool orders its reuse after the release.
-void ws_free(void *p, bool pooled)
-{
-    if (!p)
-        return;
-    if (pooled) {
-        if (hipFreeAsync(p, nullptr) != hipSuccess)
-            (void)hipGetLastError();
-        return;
-    }
-    (void)hipFree(p);
-}
-
-}  // namespace
-
 struct pip_join {
     Problem p;              // points and polygons (inside unused)
     int device = -1;
@@ -371,8 +300,8 @@ int pip_join_destroy(pip_join *j)
     if (!j)
         return PIP_OK;
     (void)hipDeviceSynchronize();   // no enqueued work may still use the workspace
-    ws_free(j->ws, j->ws_pooled);
-    ws_free(j->ws2, j->ws2_pooled);
+    pool_release(j->ws, j->ws_pooled);
+    pool_release(j->ws2, j->ws2_pooled);
     delete j;
     return PIP_OK;
 }
@@ -437,7 +366,7 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
     const size_t o_rows = take((size_t)P * 4);
     const size_t o_ustart = take((size_t)(P + 1) * 8);
     const size_t o_scan = take((size_t)scan_blocks * 8);
-    hipError_t e = ws_alloc(&j->ws, off, j->device, s, &j->ws_pooled);
+    hipError_t e = pool_alloc(&j->ws, off, j->device, s, &j->ws_pooled);
     if (e != hipSuccess) {
         delete j;
         (void)hipGetLastError();
@@ -499,7 +428,7 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
         const size_t o_ucount = take2((size_t)U * 4);
         const size_t o_uoff = take2((size_t)(U + 1) * 8);
         const size_t o_uscan = take2((size_t)scan_ws_entries(U) * 8);
-        e = ws_alloc(&j->ws2, off2, j->device, s, &j->ws2_pooled);
+        e = pool_alloc(&j->ws2, off2, j->device, s, &j->ws2_pooled);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             rc = fail(PIP_ENOMEM, "join unit workspace of %zu bytes: %s", off2, hipGetErrorString(e));

@@ -58,8 +58,22 @@ struct DeviceInfo {
 };
 // Largest edge budget (lds_slots) whose staging fits the device's LDS per workgroup.
 int clamp_lds_slots(int lds_slots, bool filtered, int pairs_per_lane, const DeviceInfo *dev);
+// Largest LDS tile of the batched kernel (vertices, halved from the request)
+// whose layout fits a workgroup's LDS.
+int clamp_batched_tile(int tile, bool filtered, int pairs_per_lane, const DeviceInfo *dev);
 // Info for the current device (cached per device); PIP_ENOTSUP if not gfx950.
 int current_device(DeviceInfo **out);
+
+// ---------------------------------------------------------------- device-memory pool
+// Stream-ordered workspace from a pool of the library's own, one per device,
+// that keeps released memory for later calls (no device-memory mapping and
+// unmapping per call); plain hipMalloc where the pool cannot be created
+// (*pooled = false).
+hipError_t pool_alloc(void **p, size_t bytes, int dev, hipStream_t s, bool *pooled);
+// Release p: a pooled block in stream order on s (no host wait: the pool
+// orders its reuse after the work enqueued on s so far); a plain allocation
+// after synchronising s.
+void pool_release(void *p, bool pooled, hipStream_t s = nullptr);
 
 // ---------------------------------------------------------------- problem description
 struct Problem {
@@ -108,6 +122,13 @@ int launch_filtered(const Problem &p, hipStream_t stream, int pairs_per_lane, in
                     int force_recheck, int32_t *recheck, unsigned *recheck_count, const int32_t *order,
                     int n_items, unsigned *queue, int grid);
 int launch_recheck(const Problem &p, hipStream_t stream, const int32_t *list, const unsigned *count, int grid);
+
+// ---------------------------------------------------------------- batched kernel (both modes, LDS tiles)
+size_t batched_smem_bytes(int tile, int max_rings, bool filtered);
+// stats: NULL, or [256][2] counters (point-edge tests, undecided side tests) added to
+int launch_batched(const Problem &p, hipStream_t stream, bool filtered, int pairs_per_lane, int tile,
+                   float bound_scale, int force_recheck, int32_t *recheck, unsigned *recheck_count,
+                   unsigned long long *stats, const int32_t *order, int n_items);
 
 // ---------------------------------------------------------------- y-index for one large ring
 struct IndexLayout {

@@ -28,12 +28,14 @@ struct pip_plan {
     uint8_t *bucket = nullptr;
     int32_t *order = nullptr;
     int32_t *recheck = nullptr;
+    unsigned long long *stats = nullptr;   // [256][2] device counters (plans with stats = 1)
     unsigned char *index_ws = nullptr;
     pip::IndexLayout index;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool executed = false;
+    hipStream_t last_stream = nullptr;   // the stream of the last execution
     int timed = 0;   // events of the last execution: 0 none, 1 phases, 2 main kernel only
     unsigned span[33] = {0};   // vertex ranges of the 1024-pair work items at creation: max, log2 histogram
     int64_t n_items4 = 0;
@@ -46,6 +48,7 @@ constexpr int kQueue = 64;
 constexpr int kRecheckCount = 65;
 constexpr int kSpan = 66;        // [66, 99): item span maximum and log2 histogram
 constexpr int kCounters = 100;
+constexpr int kStatWords = 1024;   // [256][2] 64-bit counters of the batched kernel's stats variant
 
 int item_pairs_of(const pip_plan_config &c) { return 256 * c.pairs_per_lane; }
 
@@ -54,14 +57,19 @@ int item_pairs_of(const pip_plan_config &c) { return 256 * c.pairs_per_lane; }
 bool staged_kind(const pip_plan_config &c)
 {
     return c.mode == PIP_MODE_FILTERED_FP32 || c.kernel == PIP_KERNEL_STAGED || c.kernel == PIP_KERNEL_RUNS ||
-           c.kernel == PIP_KERNEL_AUTO;
+           c.kernel == PIP_KERNEL_BATCHED || c.kernel == PIP_KERNEL_AUTO;
 }
 
 int resolve_grid(pip_plan *pl, pip_plan_config &c)
 {
     DeviceInfo *dev = nullptr;
     PIP_TRY(current_device(&dev));
-    c.lds_slots = clamp_lds_slots(c.lds_slots, c.mode == PIP_MODE_FILTERED_FP32, c.pairs_per_lane, dev);
+    if (c.kernel == PIP_KERNEL_BATCHED) {
+        c.lds_slots = clamp_batched_tile(c.lds_slots, c.mode == PIP_MODE_FILTERED_FP32, c.pairs_per_lane, dev);
+        c.persistent = 0;   // one workgroup per item only
+    } else {
+        c.lds_slots = clamp_lds_slots(c.lds_slots, c.mode == PIP_MODE_FILTERED_FP32, c.pairs_per_lane, dev);
+    }
     c.n_items = (int)((pl->p.n_points + item_pairs_of(c) - 1) / item_pairs_of(c));
     if (!staged_kind(c) || !c.persistent) {
         c.grid = c.n_items;
@@ -109,7 +117,8 @@ bool phase_empty(const pip_plan *pl, const pip_plan_config &c, int ph)
         if (!staged_kind(c))
             return true;
         const bool lpt = c.order == 1 && pl->p.point_poly;
-        const bool counters = c.mode == PIP_MODE_FILTERED_FP32 || (c.persistent && c.kernel == PIP_KERNEL_RUNS);
+        const bool counters = c.mode == PIP_MODE_FILTERED_FP32 || (c.persistent && c.kernel == PIP_KERNEL_RUNS) ||
+                              (pl->stats && c.kernel == PIP_KERNEL_BATCHED);
         return !(lpt || counters);
     }
     if (ph == kRecheck)
@@ -128,6 +137,8 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
     const bool lpt = staged_kind(c) && c.order == 1 && p.point_poly;
     if (ph == kPrep) {
         PIP_TRY(launch_fill(pl->counters + kQueue, kSpan - kQueue, 0u, s));
+        if (pl->stats && c.kernel == PIP_KERNEL_BATCHED)
+            PIP_TRY(launch_fill((unsigned *)pl->stats, kStatWords, 0u, s));
         if (lpt)
             PIP_TRY(launch_item_order(p, s, item_pairs_of(c), c.n_items, pl->bucket, pl->counters, pl->order));
         return PIP_OK;
@@ -135,6 +146,10 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
     if (ph == kMain) {
         unsigned *queue = c.persistent ? pl->counters + kQueue : nullptr;
         const int32_t *order = lpt ? pl->order : nullptr;
+        if (c.kernel == PIP_KERNEL_BATCHED)
+            return launch_batched(p, s, c.mode == PIP_MODE_FILTERED_FP32, c.pairs_per_lane, c.lds_slots,
+                                  pl->o.bound_scale, pl->o.force_recheck, pl->recheck, pl->counters + kRecheckCount,
+                                  pl->stats, order, c.n_items);
         if (c.mode == PIP_MODE_FILTERED_FP32)
             return launch_filtered(p, s, c.pairs_per_lane, c.lds_slots, pl->o.bound_scale, pl->o.force_recheck,
                                    pl->recheck, pl->counters + kRecheckCount, order, c.n_items, queue, c.grid);
@@ -247,7 +262,26 @@ const char *cache_path(const pip_plan *pl)
     return (e && e[0]) ? e : nullptr;
 }
 
-// Cache lines: "<key> <kernel> <pairs_per_lane> <lds_slots> <persistent> <order> <use_graph> <ms>"
+// Kernels a plan's tuner and cache may choose: the work-item kernels that
+// support the plan's mode, predicate and ring index, within the kernel the
+// caller asked for (AUTO: any of them).
+bool kernel_allowed(const pip_plan *pl, int kern)
+{
+    if (pl->o.kernel != PIP_KERNEL_AUTO && kern != pl->o.kernel)
+        return false;
+    if (kern == PIP_KERNEL_BATCHED)
+        return !pl->p.poly_rings && pl->o.predicate == PIP_PRED_SIDE;
+    if (kern == PIP_KERNEL_STAGED)
+        return true;
+    if (kern == PIP_KERNEL_RUNS)
+        return pl->o.mode == PIP_MODE_EXACT_FP64 && !pl->p.poly_rings;
+    return false;
+}
+
+// Cache lines: "<key> <kernel> <pairs_per_lane> <lds_slots> <persistent> <order> <use_graph> <ms>".
+// A cached choice fills only what the caller left open: the kernel when it
+// asked for AUTO, pairs per lane and LDS slots when 0, persistence and order
+// when -1 (an explicit request is never overridden).
 bool cache_lookup(const pip_plan *pl, pip_plan_config &c)
 {
     const char *path = cache_path(pl);
@@ -262,16 +296,18 @@ bool cache_lookup(const pip_plan *pl, pip_plan_config &c)
     float ms;
     bool found = false;
     while (fscanf(f, "%199s %d %d %d %d %d %d %f", k, &kern, &u, &l, &pe, &od, &gr, &ms) == 8) {
-        const bool sane = (kern == PIP_KERNEL_STAGED || kern == PIP_KERNEL_RUNS) && (u == 1 || u == 2 || u == 4) &&
-                          l >= 16 && l <= 2048 && (pe == 0 || pe == 1) && (od == 0 || od == 1) &&
-                          (gr == 0 || gr == 1) &&
-                          !((pl->o.mode == PIP_MODE_FILTERED_FP32 || pl->p.poly_rings) && kern != PIP_KERNEL_STAGED);
+        const bool sane = kernel_allowed(pl, kern) && (u == 1 || u == 2 || u == 4) && l >= 16 && l <= 2048 &&
+                          (pe == 0 || pe == 1) && (od == 0 || od == 1) && (gr == 0 || gr == 1);
         if (key == k && sane) {
             c.kernel = kern;
-            c.pairs_per_lane = u;
-            c.lds_slots = l;
-            c.persistent = pe;
-            c.order = od;
+            if (pl->o.pairs_per_lane <= 0)
+                c.pairs_per_lane = u;
+            if (pl->o.lds_slots <= 0)
+                c.lds_slots = l;
+            if (pl->o.persistent < 0)
+                c.persistent = pe;
+            if (pl->o.order < 0)
+                c.order = od;
             c.use_graph = gr && pl->o.use_graph && !pl->o.timing;
             c.tune_ms = ms;
             found = true;   // the last matching line wins
@@ -360,18 +396,15 @@ int autotune(pip_plan *pl, hipStream_t s)
     const int lds_opts[] = {128, 256, 512, 1024};
     const int ppl_opts[] = {1, 2, 4};
     std::vector<int> kernels;
-    if (pl->o.mode == PIP_MODE_FILTERED_FP32 || pl->o.kernel == PIP_KERNEL_STAGED || pl->p.poly_rings)
-        kernels = {PIP_KERNEL_STAGED};
-    else if (pl->o.kernel == PIP_KERNEL_RUNS)
-        kernels = {PIP_KERNEL_RUNS};
-    else
-        kernels = {PIP_KERNEL_STAGED, PIP_KERNEL_RUNS};
+    for (int kern : {PIP_KERNEL_BATCHED, PIP_KERNEL_STAGED, PIP_KERNEL_RUNS})
+        if (kernel_allowed(pl, kern))
+            kernels.push_back(kern);
     for (int kern : kernels)
         for (int u : ppl_opts)
             for (int l : lds_opts) {
                 if (kern == PIP_KERNEL_RUNS && l != lds_opts[0])
                     continue;   // the runs kernel stages nothing
-                for (int pe = 0; pe <= 1; ++pe)
+                for (int pe = 0; pe <= (kern == PIP_KERNEL_BATCHED ? 0 : 1); ++pe)
                     for (int od = 0; od <= (pl->p.point_poly ? 1 : 0); ++od) {
                         pip_plan_config c = pl->cfg;
                         c.kernel = kern;
@@ -444,10 +477,15 @@ int check_options(const pip_options *opts, pip_options &o)
     }
     if (o.mode != PIP_MODE_EXACT_FP64 && o.mode != PIP_MODE_FILTERED_FP32)
         return fail(PIP_EINVAL, "unknown mode %d", o.mode);
-    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_RUNS)
+    if (o.kernel < PIP_KERNEL_AUTO || o.kernel > PIP_KERNEL_BATCHED)
         return fail(PIP_EINVAL, "unknown kernel %d", o.kernel);
-    if (o.mode == PIP_MODE_FILTERED_FP32 && (o.kernel == PIP_KERNEL_PER_PAIR || o.kernel == PIP_KERNEL_SEGMENTED))
-        return fail(PIP_EINVAL, "the filtered mode runs on the staged kernel only");
+    if (o.mode == PIP_MODE_FILTERED_FP32 &&
+        (o.kernel == PIP_KERNEL_PER_PAIR || o.kernel == PIP_KERNEL_SEGMENTED || o.kernel == PIP_KERNEL_RUNS))
+        return fail(PIP_EINVAL, "the filtered mode runs on the staged or batched kernel only");
+    if (o.kernel == PIP_KERNEL_BATCHED && o.predicate != PIP_PRED_SIDE)
+        return fail(PIP_ENOTSUP, "the batched kernel implements the side test (constraint 1) only");
+    if (o.stats < 0 || o.stats > 1)
+        return fail(PIP_EINVAL, "stats must be 0 or 1");
     if (!(o.bound_scale >= 0.0f))
         return fail(PIP_EINVAL, "bound_scale must be >= 0");
     if (o.index && o.mode != PIP_MODE_EXACT_FP64)
@@ -492,6 +530,11 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
     }
     p.pred = o.predicate;
     PIP_TRY(check_host_args(p));
+    // pair ids are int32 in the recheck list and the item order, and items are counted in int
+    if (n_points > INT32_MAX)
+        return fail(PIP_EINVAL, "n_points=%lld: plans take fewer than 2^31 pairs", (long long)n_points);
+    if (o.stats && o.kernel != PIP_KERNEL_BATCHED && o.kernel != PIP_KERNEL_AUTO)
+        return fail(PIP_EINVAL, "stats counting needs the batched kernel");
     DeviceInfo *dev = nullptr;
     PIP_TRY(current_device(&dev));
     hipStream_t s = (hipStream_t)stream;
@@ -510,8 +553,9 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
     c.kernel = o.kernel;
     if (o.kernel == PIP_KERNEL_AUTO) {
         // rings shared by every pair of a large single polygon stream best through
-        // scalar loads; batched small rings best through LDS
-        c.kernel = PIP_KERNEL_STAGED;
+        // scalar loads; batched small rings best through LDS (the filtered mode:
+        // the batched kernel, where it applies)
+        c.kernel = (o.mode == PIP_MODE_FILTERED_FP32 && !p.poly_rings) ? PIP_KERNEL_BATCHED : PIP_KERNEL_STAGED;
         if (o.mode == PIP_MODE_EXACT_FP64 && !point_poly && !p.poly_rings && n_points > 0) {
             int64_t o2[2] = {0, 0};
             if (hipMemcpy(o2, offsets, sizeof o2, hipMemcpyDeviceToHost) == hipSuccess && o2[1] - o2[0] > 512)
@@ -519,8 +563,8 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
             (void)hipGetLastError();
         }
     }
-    c.pairs_per_lane = o.pairs_per_lane > 0 ? o.pairs_per_lane : 4;
-    c.lds_slots = o.lds_slots > 0 ? std::min(o.lds_slots, 2048) : 256;
+    c.pairs_per_lane = o.pairs_per_lane > 0 ? o.pairs_per_lane : (c.kernel == PIP_KERNEL_BATCHED ? 2 : 4);
+    c.lds_slots = o.lds_slots > 0 ? std::min(o.lds_slots, 2048) : (c.kernel == PIP_KERNEL_BATCHED ? 512 : 256);
     // one workgroup per item unless asked: the hardware dispatcher already
     // starts a new workgroup wherever one finishes
     c.persistent = o.persistent > 0 ? 1 : 0;
@@ -542,6 +586,7 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
     const size_t o_bkt = take((size_t)max_items);
     const size_t o_ord = take((size_t)max_items * sizeof(int32_t));
     const size_t o_rck = take(o.mode == PIP_MODE_FILTERED_FP32 ? (size_t)std::max<int64_t>(n_points, 1) * 4 : 0);
+    const size_t o_st = take(o.stats ? kStatWords * sizeof(unsigned) : 0);
     if (o.index) {
         if (point_poly) {
             delete pl;
@@ -566,6 +611,7 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
     pl->bucket = w + o_bkt;
     pl->order = (int32_t *)(w + o_ord);
     pl->recheck = o.mode == PIP_MODE_FILTERED_FP32 ? (int32_t *)(w + o_rck) : nullptr;
+    pl->stats = o.stats ? (unsigned long long *)(w + o_st) : nullptr;
     pl->index_ws = o.index ? w + o_idx : nullptr;
     for (int k = 0; k < 4 && rc == PIP_OK; ++k) {
         e = hipEventCreate(&pl->ev[k]);
@@ -574,6 +620,8 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
     }
     if (rc == PIP_OK)
         rc = launch_fill(pl->counters, kCounters, 0u, s);
+    if (rc == PIP_OK && pl->stats)
+        rc = launch_fill((unsigned *)pl->stats, kStatWords, 0u, s);
     // the largest vertex range of a work item (for the largest items): the
     // staged kernel walks ranges beyond its LDS budget in tiles, in a separate
     // form used only when some item needs it (the data may change between
@@ -647,7 +695,7 @@ int pip_plan_create_rings(pip_plan **out, const double *px, const double *py, in
     return plan_create(out, p, opts, stream);
 }
 
-int pip_plan_execute(pip_plan *pl, void *stream)
+int pip_plan_execute(pip_plan *pl, pip_stats *stats, void *stream)
 {
     clear_error();
     if (!pl)
@@ -665,6 +713,9 @@ int pip_plan_execute(pip_plan *pl, void *stream)
         pl->timed = pl->o.timing;
     }
     pl->executed = true;
+    pl->last_stream = s;
+    if (stats)
+        return pip_plan_stats(pl, stats);
     return PIP_OK;
 }
 
@@ -677,12 +728,23 @@ int pip_plan_stats(pip_plan *pl, pip_stats *st)
     st->pairs = (uint64_t)pl->p.n_points;
     if (!pl->executed)
         return PIP_OK;
+    // the execution's stream, not the null stream: a non-blocking stream is
+    // not ordered with the null stream
+    PIP_HIP_TRY(hipStreamSynchronize(pl->last_stream));
     if (pl->timed)
         PIP_TRY(read_timing(pl, &st->ms_prep, &st->ms_main, &st->ms_recheck));
     if (pl->recheck) {
         unsigned cnt = 0;
         PIP_HIP_TRY(hipMemcpy(&cnt, pl->counters + kRecheckCount, sizeof cnt, hipMemcpyDeviceToHost));
         st->rechecked_pairs = cnt;
+    }
+    if (pl->stats && pl->cfg.kernel == PIP_KERNEL_BATCHED) {
+        std::vector<unsigned long long> v(kStatWords / 2);
+        PIP_HIP_TRY(hipMemcpy(v.data(), pl->stats, v.size() * sizeof(v[0]), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < v.size(); i += 2) {
+            st->tests += v[i];
+            st->ambiguous_tests += v[i + 1];
+        }
     }
     return PIP_OK;
 }

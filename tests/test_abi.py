@@ -121,3 +121,71 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libpip.so"))
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_filtered_and_batched_argument_errors(lib):
+    """Host-side checks of the filtered pip_classify, the batched kernel and the
+    plans' int32 pair limit (no device call is made)."""
+    from paper_2306_04316_amd import _lib
+    o = _lib.pip_options()
+    lib.pip_options_init(ctypes.byref(o))
+    dummy = ctypes.c_void_p(16)
+    plan = ctypes.c_void_p()
+    # the filtered mode of pip_classify: batched kernel, constraint 1, one ring per polygon
+    o.mode = 1
+    o.kernel = 3
+    rc = lib.pip_classify(dummy, dummy, 10, dummy, 1, dummy, dummy, 4, None, dummy, ctypes.byref(o), None)
+    assert rc == _lib.PIP_EINVAL and b"batched" in lib.pip_last_error()
+    o.kernel = 0
+    o.predicate = 1
+    rc = lib.pip_classify(dummy, dummy, 10, dummy, 1, dummy, dummy, 4, None, dummy, ctypes.byref(o), None)
+    assert rc == _lib.PIP_ENOTSUP
+    o.predicate = 0
+    rc = lib.pip_classify_rings(dummy, dummy, 10, dummy, 1, dummy, 1, dummy, dummy, 4, None, dummy,
+                                ctypes.byref(o), None)
+    assert rc == _lib.PIP_ENOTSUP
+    big = (1 << 31)
+    rc = lib.pip_classify(dummy, dummy, big, dummy, 1, dummy, dummy, 4, None, dummy, ctypes.byref(o), None)
+    assert rc == _lib.PIP_EINVAL and b"2^31" in lib.pip_last_error()
+    # plans: fewer than 2^31 pairs in either mode (int32 pair ids in the recheck list and the item order)
+    for mode in (0, 1):
+        o.mode = mode
+        rc = lib.pip_plan_create(ctypes.byref(plan), dummy, dummy, big, dummy, 1, dummy, dummy, 4, None, dummy,
+                                 ctypes.byref(o), None)
+        assert rc == _lib.PIP_EINVAL and b"2^31" in lib.pip_last_error()
+        assert not plan.value
+    # the batched kernel: constraint 1 only
+    o.mode = 0
+    o.kernel = 5
+    o.predicate = 1
+    rc = lib.pip_classify(dummy, dummy, 10, dummy, 1, dummy, dummy, 4, None, dummy, ctypes.byref(o), None)
+    assert rc == _lib.PIP_ENOTSUP
+    rc = lib.pip_plan_create(ctypes.byref(plan), dummy, dummy, 10, dummy, 1, dummy, dummy, 4, None, dummy,
+                             ctypes.byref(o), None)
+    assert rc == _lib.PIP_ENOTSUP
+    o.predicate = 0
+    # stats counting: 0 or 1, and only with the batched kernel
+    o.stats = 2
+    rc = lib.pip_plan_create(ctypes.byref(plan), dummy, dummy, 10, dummy, 1, dummy, dummy, 4, None, dummy,
+                             ctypes.byref(o), None)
+    assert rc == _lib.PIP_EINVAL and b"stats" in lib.pip_last_error()
+    o.stats = 1
+    o.kernel = 3
+    rc = lib.pip_plan_create(ctypes.byref(plan), dummy, dummy, 10, dummy, 1, dummy, dummy, 4, None, dummy,
+                             ctypes.byref(o), None)
+    assert rc == _lib.PIP_EINVAL and b"batched" in lib.pip_last_error()
+    # pip_plan_execute / pip_plan_stats with a NULL plan
+    st = _lib.pip_stats()
+    assert lib.pip_plan_execute(None, ctypes.byref(st), None) == _lib.PIP_EINVAL
+    assert lib.pip_plan_stats(None, ctypes.byref(st)) == _lib.PIP_EINVAL
+
+
+def test_stats_struct_layout():
+    """pip_stats as the header lays it out: four 64-bit counters, then three floats."""
+    from paper_2306_04316_amd import _lib
+    names = [f for f, _ in _lib.pip_stats._fields_]
+    assert names == ["pairs", "tests", "ambiguous_tests", "rechecked_pairs", "ms_prep", "ms_main", "ms_recheck"]
+    src = open(HEADER).read()
+    body = re.search(r"typedef struct \{([^{}]*?)\} pip_stats;", src, re.S).group(1)
+    hdr = re.findall(r"^\s*(?:uint64_t|float)\s+(\w+);", body, re.M)
+    assert hdr == names

@@ -93,10 +93,13 @@ def test_filtered_force_recheck(P):
     assert st["rechecked_pairs"] >= 0.5 * w.n_points
 
 
-def test_filtered_levels_equal_in_binary32(P):
+@pytest.mark.parametrize("kernel", ["staged", "batched"])
+def test_filtered_levels_equal_in_binary32(P, kernel):
     """Points level with a vertex to within a binary64 ulp or two, far from the
-    vertex in x: after re-centring their binary32 y equals the vertex's, so the
-    straddle order is undecided and every such pair must be rechecked."""
+    vertex in x: after re-centring their binary32 y equals the vertex's.  The
+    staged kernel's binary32 straddle order is then undecided and every such
+    pair must be rechecked; the batched kernel compares y in binary64 (exact)
+    and decides them.  Both must match the oracle."""
     base = 1.0e6
     rel = [(0.0, 0.0), (4.0, 0.3), (4.5, 1.7), (2.0, 1.1), (0.5, 2.9), (-0.5, 1.4)]
     vx = np.array([base + a for a, _ in rel])
@@ -113,8 +116,9 @@ def test_filtered_levels_equal_in_binary32(P):
     cy = 0.5 * vy.min() + 0.5 * vy.max()
     level = np.isin(np.float32(py - cy), np.float32(vy - cy))
     assert level.sum() >= len(vy) * 12
-    st, _ = check_plan(P, w, "levels", mode="filtered")
-    assert st["rechecked_pairs"] >= int(level.sum())
+    st, _ = check_plan(P, w, "levels", mode="filtered", kernel=kernel)
+    if kernel == "staged":
+        assert st["rechecked_pairs"] >= int(level.sum())
     rx = np.array([-0.0, 1e-300, 1e-300, -0.0])
     ry = np.array([-0.0, -0.0, 1e-300, 1e-300])
     tx = np.array([0.0, -0.0, 5e-301, 1e-300, 2e-300, 0.0, -1e-300])
@@ -123,7 +127,7 @@ def test_filtered_levels_equal_in_binary32(P):
     by = np.array([-1e300, -1e300, 1e300, 1e300])
     for ringx, ringy, name in ((rx, ry, "tiny square"), (bx, by, "huge square")):
         w = W.Workload(name, tx, ty, np.array([0, 4], dtype=np.int64), ringx, ringy, None, {})
-        check_plan(P, w, name, mode="filtered")
+        check_plan(P, w, name, mode="filtered", kernel=kernel)
 
 
 def test_filtered_negative_control(P):
