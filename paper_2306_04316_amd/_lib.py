@@ -8,6 +8,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpip.so")
 
 PIP_OK, PIP_EINVAL, PIP_ERANGE, PIP_EDOM, PIP_ENOMEM, PIP_EHIP, PIP_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+PIP_NOALLOC_MAX_POINTS = 4194304   # include/pip.h
 STATUS_NAMES = {0: "PIP_OK", -1: "PIP_EINVAL", -2: "PIP_ERANGE", -3: "PIP_EDOM", -4: "PIP_ENOMEM",
                 -5: "PIP_EHIP", -6: "PIP_ENOTSUP"}
 
@@ -54,6 +55,8 @@ _SIGS = {
     "pip_last_error": (ctypes.c_char_p, []),
     "pip_classify": (ctypes.c_int, [_VP, _VP, _I64, _VP, _I64, _VP, _VP, _I64, _VP, _VP,
                                     ctypes.POINTER(pip_options), _VP]),
+    "pip_classify_noalloc": (ctypes.c_int, [_VP, _VP, _I64, _VP, _I64, _VP, _VP, _I64, _VP, _VP,
+                                            ctypes.POINTER(pip_options), _VP]),
     "pip_probe_copy": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "pip_probe_read": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
     "pip_plan_create": (ctypes.c_int, [ctypes.POINTER(_VP), _VP, _VP, _I64, _VP, _I64, _VP, _VP, _I64, _VP, _VP,

@@ -19,6 +19,12 @@ thread_local char g_err[512] = "";
 // validating calls on one device share it).
 __device__ unsigned g_validate_word;
 
+// The workspace of pip_classify_noalloc: a count word (padded to 256 bytes)
+// and the list of undecided pairs, PIP_NOALLOC_MAX_POINTS entries.  Host code
+// uses only the address hipGetSymbolAddress gives for the current device
+// (DeviceInfo::scratch), never the array's name.
+constexpr size_t kScratchHead = 256;
+__device__ __align__(256) unsigned char scratch[kScratchHead + (size_t)PIP_NOALLOC_MAX_POINTS * sizeof(int32_t)];
 
 std::mutex g_dev_mu;
 std::vector<DeviceInfo *> g_devs;
@@ -79,6 +85,13 @@ int current_device(DeviceInfo **out)
             return fail(PIP_EHIP, "hipGetSymbolAddress(validate word) failed: %s", hipGetErrorString(e));
         }
         d->validate_flags = (unsigned *)sym;
+        void *scr = nullptr;
+        e = hipGetSymbolAddress(&scr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            delete d;
+            return fail(PIP_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        }
+        d->scratch = (unsigned char *)scr;
         g_devs[dev] = d;
     }
     if (!g_devs[dev]->gfx950)
@@ -241,15 +254,15 @@ namespace {
 // The filtered mode of pip_classify: the batched kernel in binary32 with its
 // list of undecided pairs (list length word, padded to 256 bytes, then
 // n_points list entries), then the binary64 recheck of the list.  The
-// workspace is a pooled, stream-ordered allocation, or `fixed` when the
-// caller provides it.
+// workspace is a pooled, stream-ordered allocation, or `fixed` (the static
+// scratch array of pip_classify_noalloc, which allocates nothing).
 int classify_filtered(const Problem &p, DeviceInfo *dev, const pip_options &o, hipStream_t s, unsigned char *fixed)
 {
     const int u = o.pairs_per_lane == 1 ? 1 : (o.pairs_per_lane == 4 ? 4 : 2);
     const int tile = clamp_batched_tile(o.lds_slots > 0 ? o.lds_slots : 512, true, u, dev);
     void *ws = fixed;
     bool pooled = false;
-    const size_t bytes = 256 + (size_t)p.n_points * sizeof(int32_t);
+    const size_t bytes = kScratchHead + (size_t)p.n_points * sizeof(int32_t);
     if (!fixed) {
         hipError_t e = pool_alloc(&ws, bytes, dev->device, s, &pooled);
         if (e != hipSuccess) {
@@ -258,7 +271,7 @@ int classify_filtered(const Problem &p, DeviceInfo *dev, const pip_options &o, h
         }
     }
     unsigned *count = (unsigned *)ws;
-    int32_t *list = (int32_t *)((unsigned char *)ws + 256);
+    int32_t *list = (int32_t *)((unsigned char *)ws + kScratchHead);
     int rc = launch_fill(count, 1, 0u, s);
     if (rc == PIP_OK)
         rc = launch_batched(p, s, true, u, tile, o.bound_scale, o.force_recheck, list, count, nullptr, nullptr,
@@ -270,7 +283,7 @@ int classify_filtered(const Problem &p, DeviceInfo *dev, const pip_options &o, h
     return rc;
 }
 
-int classify_problem(Problem p, const pip_options *opts, void *stream)
+int classify_problem(Problem p, const pip_options *opts, void *stream, bool noalloc = false)
 {
     pip_options o;
     pip_options_init(&o);
@@ -294,6 +307,9 @@ int classify_problem(Problem p, const pip_options *opts, void *stream)
         if (p.n_points > INT32_MAX)
             return fail(PIP_EINVAL, "n_points=%lld: the filtered mode takes fewer than 2^31 pairs",
                         (long long)p.n_points);
+        if (noalloc && p.n_points > PIP_NOALLOC_MAX_POINTS)
+            return fail(PIP_EINVAL, "n_points=%lld exceeds the static scratch of pip_classify_noalloc (%d points)",
+                        (long long)p.n_points, PIP_NOALLOC_MAX_POINTS);
     }
     if (o.kernel == PIP_KERNEL_BATCHED && (p.poly_rings || o.predicate != PIP_PRED_SIDE))
         return fail(PIP_ENOTSUP, "the batched kernel takes one ring per polygon and the side test only");
@@ -309,7 +325,7 @@ int classify_problem(Problem p, const pip_options *opts, void *stream)
     if (p.n_points == 0)
         return PIP_OK;
     if (o.mode == PIP_MODE_FILTERED_FP32)
-        return classify_filtered(p, dev, o, s, nullptr);
+        return classify_filtered(p, dev, o, s, noalloc ? dev->scratch : nullptr);
     if (o.kernel == PIP_KERNEL_BATCHED) {
         const int u = o.pairs_per_lane == 1 ? 1 : (o.pairs_per_lane == 4 ? 4 : 2);
         return launch_batched(p, s, false, u, clamp_batched_tile(o.lds_slots > 0 ? o.lds_slots : 512, false, u, dev),
@@ -340,6 +356,16 @@ int pip_classify(const double *px, const double *py, int64_t n_points, const int
     Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
     p.n_rings = n_polys;
     return classify_problem(p, opts, stream);
+}
+
+int pip_classify_noalloc(const double *px, const double *py, int64_t n_points, const int64_t *offsets,
+                         int64_t n_polys, const double *vx, const double *vy, int64_t n_vertices,
+                         const int32_t *point_poly, uint8_t *inside, const pip_options *opts, void *stream)
+{
+    clear_error();
+    Problem p{px, py, n_points, offsets, n_polys, vx, vy, n_vertices, point_poly, inside};
+    p.n_rings = n_polys;
+    return classify_problem(p, opts, stream, true);
 }
 
 int pip_classify_rings(const double *px, const double *py, int64_t n_points, const int64_t *poly_rings,

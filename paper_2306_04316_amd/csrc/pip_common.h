@@ -54,6 +54,7 @@ struct DeviceInfo {
     int cu_count = 0;
     bool gfx950 = false;
     unsigned *validate_flags = nullptr;   // address of the __device__ flag word
+    unsigned char *scratch = nullptr;     // address of this device's copy of the static scratch array
     size_t lds_per_block = 0;             // largest dynamic LDS a workgroup may request
 };
 // Largest edge budget (lds_slots) whose staging fits the device's LDS per workgroup.
