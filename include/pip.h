@@ -382,6 +382,16 @@ PIP_API int pip_join_create(pip_join **out, const double *px, const double *py, 
 PIP_API int pip_join_fill(pip_join *join, int64_t *pair_point, int32_t *pair_poly,
                   double *pair_px, double *pair_py, void *stream);
 
+/*
+ * Device time (ms) of a join's kernels, without its host synchronisations
+ * and allocations: *ms_count covers pip_join_create's two phases of kernels
+ * (grid and sort of the points, polygon boxes, unit and pair counts), *ms_fill
+ * pip_join_fill's kernel.  Waits for the fill to complete.  PIP_EINVAL when
+ * pip_join_fill has not run on a join with pairs (both 0 for a join without
+ * pairs).
+ */
+PIP_API int pip_join_timing(pip_join *join, float *ms_count, float *ms_fill);
+
 /* Waits for the device, then releases the join's workspace.  NULL is a no-op.
  * The workspace comes from a device-memory pool of the library's own (one per
  * device), which keeps released memory for later joins instead of returning

@@ -203,10 +203,11 @@ def classify_rings(px, py, poly_rings, ring_offsets, vx, vy, point_poly=None, *,
     return out
 
 
-def candidate_pairs(px, py, offsets, vx, vy, poly_rings=None, *, stream=None):
+def candidate_pairs(px, py, offsets, vx, vy, poly_rings=None, *, stream=None, timing=None):
     """Candidate pairs by closed bounding box (pip_join_*): a dict of device tensors
     point (int64), poly (int32), px, py (float64), grouped by polygon in ascending
-    order -- ready to classify as Plan(px, py, offsets, vx, vy, poly, ...)."""
+    order -- ready to classify as Plan(px, py, offsets, vx, vy, poly, ...).
+    timing: a dict that receives the join kernels' device time (ms_count, ms_fill)."""
     import torch
     lib = _lib.load()
     _require(px, torch.float64, "px")
@@ -233,6 +234,10 @@ def candidate_pairs(px, py, offsets, vx, vy, poly_rings=None, *, stream=None):
                        py=torch.empty(n, dtype=torch.float64, device=px.device))
             _lib.check(lib.pip_join_fill(h, _ptr(out["point"]), _ptr(out["poly"]), _ptr(out["px"]), _ptr(out["py"]),
                                          _stream_handle(stream)))
+            if timing is not None:
+                c, f = ctypes.c_float(), ctypes.c_float()
+                _lib.check(lib.pip_join_timing(h, ctypes.byref(c), ctypes.byref(f)))
+                timing.update(ms_count=c.value, ms_fill=f.value)
         finally:
             lib.pip_join_destroy(h)
     return out

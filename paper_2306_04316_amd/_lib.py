@@ -69,6 +69,7 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_int64), _VP]),
     "pip_join_fill": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pip_join_destroy": (ctypes.c_int, [_VP]),
+    "pip_join_timing": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "pip_plan_execute": (ctypes.c_int, [_VP, ctypes.POINTER(pip_stats), _VP]),
     "pip_plan_stats": (ctypes.c_int, [_VP, ctypes.POINTER(pip_stats)]),
     "pip_plan_timing": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),

@@ -290,6 +290,10 @@ struct pip_join {
     int64_t *cell_start = nullptr, *unit_start = nullptr, *unit_off = nullptr;
     int32_t *spt = nullptr, *unit_poly = nullptr;
     double2 *sxy = nullptr;
+    // device timestamps: [0, 1] the first phase's kernels (grid, sort, boxes, unit
+    // count), [2, 3] the second's (unit owners, pair count), [4, 5] the fill
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool filled = false;
 };
 
 extern "C" {
@@ -302,6 +306,9 @@ int pip_join_destroy(pip_join *j)
     (void)hipDeviceSynchronize();   // no enqueued work may still use the workspace
     pool_release(j->ws, j->ws_pooled);
     pool_release(j->ws2, j->ws2_pooled);
+    for (auto &e : j->ev)
+        if (e)
+            (void)hipEventDestroy(e);
     delete j;
     return PIP_OK;
 }
@@ -335,6 +342,13 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
     p.poly_rings = poly_rings;
     p.n_rings = poly_rings ? n_rings : n_polys;
     j->device = dev->device;
+    for (auto &ev : j->ev) {
+        if (hipEventCreate(&ev) != hipSuccess) {
+            (void)hipGetLastError();
+            pip_join_destroy(j);
+            return fail(PIP_EHIP, "join: hipEventCreate failed");
+        }
+    }
     if (n_points == 0 || n_polys == 0) {
         *out = j;
         return PIP_OK;
@@ -390,6 +404,8 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
         if (rc == PIP_OK)
             rc = r;
     };
+    if (hipEventRecord(j->ev[0], s) != hipSuccess)
+        rc = fail(PIP_EHIP, "join: hipEventRecord failed");
     if (rc == PIP_OK) {
         hipLaunchKernelGGL(k_extent_partial, dim3(nparts), dim3(256), 0, s, px, py, N, part);
         hipLaunchKernelGGL(k_extent_final, dim3(1), dim3(256), 0, s, part, nparts, C, j->grid);
@@ -408,6 +424,8 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
             rc = fail(PIP_EHIP, "join polygon kernels failed to launch");
     }
     step(launch_scan_u32(rows, P, j->unit_start, scan_ws, s));
+    if (rc == PIP_OK && hipEventRecord(j->ev[1], s) != hipSuccess)
+        rc = fail(PIP_EHIP, "join: hipEventRecord failed");
     int64_t U = 0;
     if (rc == PIP_OK) {
         e = hipMemcpyAsync(&U, j->unit_start + P, sizeof U, hipMemcpyDeviceToHost, s);
@@ -438,6 +456,8 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
             uint32_t *ucount = (uint32_t *)(w2 + o_ucount);
             j->unit_off = (int64_t *)(w2 + o_uoff);
             const unsigned gq = std::min<unsigned>(grid_for(P, 256), 8192u);
+            if (hipEventRecord(j->ev[2], s) != hipSuccess)
+                rc = fail(PIP_EHIP, "join: hipEventRecord failed");
             hipLaunchKernelGGL(k_unit_owner, dim3(gq), dim3(256), 0, s, j->unit_start, P, j->unit_poly);
             const unsigned gu = std::min<unsigned>(grid_for(U, 4), 65536u);
             hipLaunchKernelGGL((k_units<false>), dim3(gu), dim3(256), 0, s, j->unit_start, j->unit_poly, U, j->pc,
@@ -446,6 +466,8 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
             if (hipGetLastError() != hipSuccess)
                 rc = fail(PIP_EHIP, "join count kernels failed to launch");
             step(launch_scan_u32(ucount, U, j->unit_off, (int64_t *)(w2 + o_uscan), s));
+            if (rc == PIP_OK && hipEventRecord(j->ev[3], s) != hipSuccess)
+                rc = fail(PIP_EHIP, "join: hipEventRecord failed");
             int64_t M = 0;
             if (rc == PIP_OK) {
                 e = hipMemcpyAsync(&M, j->unit_off + U, sizeof M, hipMemcpyDeviceToHost, s);
@@ -480,10 +502,31 @@ int pip_join_fill(pip_join *j, int64_t *pair_point, int32_t *pair_poly, double *
         return PIP_OK;
     const int64_t U = j->n_units;
     const unsigned gu = std::min<unsigned>(grid_for(U, 4), 65536u);
+    PIP_HIP_TRY(hipEventRecord(j->ev[4], (hipStream_t)stream));
     hipLaunchKernelGGL((k_units<true>), dim3(gu), dim3(256), 0, (hipStream_t)stream, j->unit_start, j->unit_poly, U,
                        j->pc, j->grid, j->cell_start, j->spt, j->sxy, nullptr, j->unit_off, pair_point, pair_poly,
                        pair_px, pair_py);
     PIP_HIP_TRY(hipGetLastError());
+    PIP_HIP_TRY(hipEventRecord(j->ev[5], (hipStream_t)stream));
+    j->filled = true;
+    return PIP_OK;
+}
+
+int pip_join_timing(pip_join *j, float *ms_count, float *ms_fill)
+{
+    clear_error();
+    if (!j || !ms_count || !ms_fill)
+        return fail(PIP_EINVAL, "NULL argument");
+    *ms_count = *ms_fill = 0.f;
+    if (j->n_pairs == 0 || !j->filled)
+        return j->filled || j->n_pairs == 0 ? PIP_OK : fail(PIP_EINVAL, "pip_join_fill has not run");
+    float a = 0.f, b = 0.f, c = 0.f;
+    PIP_HIP_TRY(hipEventSynchronize(j->ev[5]));
+    PIP_HIP_TRY(hipEventElapsedTime(&a, j->ev[0], j->ev[1]));
+    PIP_HIP_TRY(hipEventElapsedTime(&b, j->ev[2], j->ev[3]));
+    PIP_HIP_TRY(hipEventElapsedTime(&c, j->ev[4], j->ev[5]));
+    *ms_count = a + b;
+    *ms_fill = c;
     return PIP_OK;
 }
 

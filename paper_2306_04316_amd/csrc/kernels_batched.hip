@@ -33,9 +33,10 @@
 // u |N|, C by u M |N|_1 (1 + 2^-28) (its binary64 part by 3 w M |N|_1), the
 // inner and outer roundings by u (|P_y NY| + |C|) and u (|P_x NX| + |inner|);
 // altogether |S - E 2^-e| <= 7.01 u M |N|_1 plus at most eta (2 N1 + 3) from
-// binary32 subnormals flushed to zero (eta = 2^-126).  If |S| > B =
-// 8 u M N1 + 4 eta (N1 + 1) -- one threshold per pair, its own three binary32
-// roundings covered by the margin -- then |E| 2^-e > 0.98 u M |N|_1, while the
+// binary32 subnormals flushed to zero (eta = 2^-126).  If |S| > B >=
+// 8 u M N1 + 4 eta (N1 + 1) -- one threshold per pair, B = fma(M, k_B, e_B)
+// with both coefficients rounded up by 2^-20 on the host so that its one
+// rounding cannot take it below that -- then |E| 2^-e > 0.98 u M |N|_1, while the
 // rule's binary64 value differs from E by at most 6.02 w M |n|_1: that value
 // is nonzero and has the sign of S, so the edge counts exactly when S < 0
 // (the sign bit of S).  M is taken per pair as max(M_ring rounded up, |P_x|,
@@ -62,8 +63,7 @@ namespace pip {
 
 namespace {
 
-constexpr float kN1Pow2 = 2.0f + 9.5367431640625e-7f;   // 2 + 2^-20 >= |NX| + |NY|
-constexpr float kBoundFma = 8.0f * 5.9604644775390625e-8f; // 8 * 2^-24
+constexpr float kLimF = 1.152921504606846976e18f;        // 2^60
 constexpr unsigned kRingBad = 0xffffffffu;              // M_ring marker: an edge outside the filter's range
 
 struct BatchedArgs {
@@ -78,7 +78,8 @@ struct BatchedArgs {
     int tile;        // S: vertices per LDS tile
     int max_rings;   // ring table entries
     int fb_tile;     // tile of the staged binary64 item (fallback), fits the same LDS
-    float bound_scale;
+    float bound_k;     // B = fma(M, bound_k, bound_eta): bound_k >= 8 u N1, bound_eta >= 4 eta (N1 + 1)
+    float bound_eta;   // (both times the testing scale; rounded up on the host)
     int force_recheck;
     int32_t *recheck;
     unsigned *recheck_count;
@@ -138,6 +139,14 @@ __device__ __forceinline__ BatchedLds batched_lds(unsigned char *smem, int S, in
     L.YD = (double *)(smem + o[4]);
     L.REC = (void *)(smem + o[5]);
     return L;
+}
+
+// A load from LDS through a pointer into the dynamic LDS block, typed for the
+// LDS address space so that it cannot become a generic load.
+template <typename T>
+__device__ __forceinline__ T lds_load(const T *p)
+{
+    return *(const __attribute__((address_space(3))) T *)p;
 }
 
 // The filtered record (NX, NY, -C, 0) of edge (a, b) re-centred on c, and
@@ -327,8 +336,6 @@ __device__ __forceinline__ void batched_item(int64_t p0, const BatchedArgs &A, u
         par[u] = 0;
     uint32_t und = 0;   // bit u: row u has an undecided test (filtered)
     uint32_t n_tests = 0, n_und = 0;
-    const float ks = kBoundFma * A.bound_scale;
-    const float eta = kEta4 * A.bound_scale;
 
     for (int t0 = 0; t0 < nvr; t0 += S) {
         const int t1 = nvr - t0 < S ? nvr : t0 + S;
@@ -352,11 +359,13 @@ __device__ __forceinline__ void batched_item(int64_t p0, const BatchedArgs &A, u
             const int e0 = L.T[r], e1 = L.T[r + 1];
             const int ep = e == e0 ? e1 - 1 : e - 1;
             const double bx = L.XD[e - t0], by = L.YD[e - t0];
-            double ax, ay;
-            if (ep >= t0 && ep < t1) {
-                ax = L.XD[ep - t0];
-                ay = L.YD[ep - t0];
-            } else {
+            // the predecessor from LDS, or (outside the tile) from global
+            // memory: two loads of fixed address spaces, not one load through
+            // a selected generic pointer
+            const bool pin = ep >= t0 && ep < t1;
+            const int epl = pin ? ep - t0 : 0;
+            double ax = lds_load(L.XD + epl), ay = lds_load(L.YD + epl);
+            if (!pin) {
                 ax = A.vx[vb + ep];
                 ay = A.vy[vb + ep];
             }
@@ -392,20 +401,24 @@ __device__ __forceinline__ void batched_item(int64_t p0, const BatchedArgs &A, u
             uint32_t prev = 0;
             if (k > 0 && !own) {
                 const int pr = a == e0 ? e1 - 1 : a - 1;
-                const double yp = (pr >= t0 && pr < t1) ? L.YD[pr - t0] : A.vy[vb + pr];
+                const bool pin = pr >= t0 && pr < t1;
+                double yp = lds_load(L.YD + (pin ? pr - t0 : 0));
+                if (!pin)
+                    yp = A.vy[vb + pr];
                 prev = yp > P.y[u] ? 1u : 0u;
             }
             float PX = 0.0f, PY = 0.0f, bnd = 0.0f;
             bool u_und = false;
             if (F && k > 0) {
                 const double2 c = L.RC[r];
-                const double xr = P.x[u] - c.x, yr = P.y[u] - c.y;
-                PX = (float)xr;
-                PY = (float)yr;
+                PX = (float)(P.x[u] - c.x);
+                PY = (float)(P.y[u] - c.y);
                 const unsigned mr = L.RM[r];
+                // M = max(M_ring, |P_x|, |P_y|); |P| < 2^60 in binary32 implies
+                // |p - c| < 2^60 (rounding is monotone), and M_ring <= 2^60
                 const float mp = fmaxf(__uint_as_float(mr), fmaxf(fabsf(PX), fabsf(PY)));
-                bnd = (ks * mp + eta) * kN1Pow2 + eta;
-                u_und = mr == kRingBad || !(fabs(xr) <= kLim) || !(fabs(yr) <= kLim);
+                bnd = __builtin_fmaf(mp, A.bound_k, A.bound_eta);
+                u_und = mr == kRingBad || !(mp < kLimF);
             }
             walk_part<F, STATS>(L, a - t0, k, prev, own, P.x[u], P.y[u], PX, PY, bnd, S, par[u], u_und, n_und);
             und |= (u_und ? 1u : 0u) << u;
@@ -494,8 +507,13 @@ int launch_batched(const Problem &p, hipStream_t stream, bool filtered, int pair
         return fail(PIP_EINVAL, "the filtered mode needs a recheck list");
     if (n_items <= 0)
         return PIP_OK;
+    // the threshold's two coefficients, rounded up so that the one rounding of
+    // fma(M, k, eta) keeps B at or above 8 u M N1 + 4 eta (N1 + 1)
+    const double n1 = 2.0 + 0x1p-20;
+    const double kb = 8.0 * 0x1p-24 * n1 * (double)bound_scale * (1.0 + 0x1p-20);
+    const double eb = 4.0 * 0x1p-126 * (n1 + 1.0) * (double)bound_scale * (1.0 + 0x1p-20);
     BatchedArgs A{p.px, p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside,
-                  tile, max_rings, fb, bound_scale, force_recheck, recheck, recheck_count, stats, order};
+                  tile, max_rings, fb, (float)kb, (float)eb, force_recheck, recheck, recheck_count, stats, order};
     if (filtered) {
         if (stats)
             launch_batched_u<true, true>(A, U, n_items, shmem, stream);

@@ -3,7 +3,7 @@
 The filter's decision is evaluated here exactly as specified for the batched
 kernel -- S = fma(P_x, N_x, fma(P_y, N_y, -C)) with the edge's line offset C
 and unit normal in binary32, each fused multiply-add rounded once (emulated
-exactly), the threshold in separately rounded binary32 operations, with and
+exactly), the threshold B = fma(M, k_B, e_B) likewise, with and
 without flushing subnormal binary32 values to zero -- on adversarial
 (point, edge) configurations: points 1 to 10^4 binary64 ulps off an edge at
 offsets up to 1e7 and extents down to 1e-9, re-centred coordinates on both
@@ -26,9 +26,10 @@ from adversarial import FAMILIES
 
 F32 = np.float32
 ETA = 2.0 ** -126
-KS = F32(8.0 * 2.0 ** -24)
-ETA4 = F32(4.0 * ETA)
-N1 = F32(2.0 + 2.0 ** -20)
+N1 = 2.0 + 2.0 ** -20
+# the threshold B = fma(M, KB, EB), both coefficients rounded up on the host
+KB = F32(8.0 * 2.0 ** -24 * N1 * (1.0 + 2.0 ** -20))
+EB = F32(4.0 * ETA * (N1 + 1.0) * (1.0 + 2.0 ** -20))
 LIM = 2.0 ** 60
 TINY = 2.0 ** -60
 
@@ -103,7 +104,7 @@ def filter_decide(px, py, ax, ay, bx, by, cx, cy, ftz):
         ok = normal_ok(nx) & normal_ok(ny) & (np.maximum(np.abs(dx), np.abs(dy)) <= LIM) & \
             (np.abs(xr) <= LIM) & (np.abs(yr) <= LIM)
     M = np.maximum(m_anchor, np.maximum(np.abs(PX), np.abs(PY)))
-    bnd = op(np.add, ftz, op(np.multiply, ftz, op(np.add, ftz, op(np.multiply, ftz, KS, M), ETA4), N1), ETA4)
+    bnd = fma32(M, KB, EB, ftz)
     inner = fma32(PY, NY, negC, ftz)
     S = fma32(PX, NX, inner, ftz)
     decided = ok & (np.abs(S) > bnd)
