@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PIP_ABI_VERSION 3
+#define PIP_ABI_VERSION 4
 
 #if defined(__GNUC__) || defined(__clang__)
 #define PIP_API __attribute__((visibility("default")))
@@ -173,6 +173,15 @@ typedef struct {
                                and undecided binary32 side tests on the device at
                                every execution (a kernel variant with counters;
                                pip_stats.tests / ambiguous_tests), 0 = no counts */
+    int32_t wave_k;         /* plans, filtered mode, PIP_KERNEL_BATCHED: pairs whose ring
+                               has at least wave_k vertices are classified by one
+                               workgroup per (ring, work item) whose wavefronts take
+                               64 edges per lane group and the point wave-uniform,
+                               crossings combined by ballot, popcount and XOR parity
+                               (paper, Method section, constraint 1; same bits).
+                               0 = left to the tuner (off, 256 or 1024) or the
+                               tuning cache, off without them; -1 = off; values
+                               below 64 mean 64 */
 } pip_options;
 
 /* Configuration a plan runs with (after automatic choices and tuning). */
@@ -190,6 +199,7 @@ typedef struct {
     int32_t tuned;          /* 0 = defaults/options, 1 = autotuned now, 2 = from the cache */
     float tune_ms;          /* tuned step time (ms), when tuned */
     int32_t index;          /* 1 if the plan runs the y-indexed path */
+    int32_t wave_k;         /* ring size from which the wave kernel takes the pairs (0: off) */
 } pip_plan_config;
 
 /* Figures of a plan's last execution (see pip_plan_stats). */

@@ -48,7 +48,8 @@ def _stream_handle(stream):
 
 def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block=0, lds_slots=0,
             persistent=-1, order=-1, use_graph=True, tune=0, force_recheck=False, bound_scale=1.0,
-            tune_cache=None, timing=False, index=False, predicate="side", stats=False) -> _lib.pip_options:
+            tune_cache=None, timing=False, index=False, predicate="side", stats=False,
+            wave_k=0) -> _lib.pip_options:
     o = _lib.pip_options()
     _lib.load().pip_options_init(ctypes.byref(o))
     o.mode = _lib.MODES[mode] if isinstance(mode, str) else int(mode)
@@ -69,6 +70,9 @@ def options(mode="exact", kernel="auto", validate=False, pairs_per_lane=0, block
     o.index = 1 if index else 0
     o.predicate = _lib.PREDICATES[predicate] if isinstance(predicate, str) else int(predicate)
     o.stats = 1 if stats else 0
+    # filtered batched plans: ring size from which the wavefront-per-ring kernel takes
+    # the pairs (0 = the tuner's or the cache's choice, off without them; -1 = off)
+    o.wave_k = int(wave_k)
     return o
 
 

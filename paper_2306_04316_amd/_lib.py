@@ -29,7 +29,8 @@ class pip_options(ctypes.Structure):
                 ("lds_slots", ctypes.c_int32), ("persistent", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("tune", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
                 ("bound_scale", ctypes.c_float), ("tune_cache", ctypes.c_char_p), ("timing", ctypes.c_int32),
-                ("predicate", ctypes.c_int32), ("index", ctypes.c_int32), ("stats", ctypes.c_int32)]
+                ("predicate", ctypes.c_int32), ("index", ctypes.c_int32), ("stats", ctypes.c_int32),
+                ("wave_k", ctypes.c_int32)]
 
 
 class pip_plan_config(ctypes.Structure):
@@ -37,7 +38,7 @@ class pip_plan_config(ctypes.Structure):
                 ("pairs_per_lane", ctypes.c_int32), ("lds_slots", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("n_items", ctypes.c_int32), ("tuned", ctypes.c_int32), ("tune_ms", ctypes.c_float),
-                ("index", ctypes.c_int32)]
+                ("index", ctypes.c_int32), ("wave_k", ctypes.c_int32)]
 
 
 class pip_stats(ctypes.Structure):

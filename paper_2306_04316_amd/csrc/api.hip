@@ -241,6 +241,7 @@ void pip_options_init(pip_options *opts)
     opts->index = 0;
     opts->predicate = PIP_PRED_SIDE;
     opts->stats = 0;
+    opts->wave_k = 0;
 }
 
 int pip_abi_version(void) { return PIP_ABI_VERSION; }
@@ -275,7 +276,7 @@ int classify_filtered(const Problem &p, DeviceInfo *dev, const pip_options &o, h
     int rc = launch_fill(count, 1, 0u, s);
     if (rc == PIP_OK)
         rc = launch_batched(p, s, true, u, tile, o.bound_scale, o.force_recheck, list, count, nullptr, nullptr,
-                            (int)((p.n_points + 256 * u - 1) / (256 * u)));
+                            nullptr, (int)((p.n_points + 256 * u - 1) / (256 * u)));
     if (rc == PIP_OK)
         rc = launch_recheck(p, s, list, count, dev->cu_count * 8);
     if (!fixed)
@@ -330,7 +331,7 @@ int classify_problem(Problem p, const pip_options *opts, void *stream, bool noal
         const int u = o.pairs_per_lane == 1 ? 1 : (o.pairs_per_lane == 4 ? 4 : 2);
         return launch_batched(p, s, false, u, clamp_batched_tile(o.lds_slots > 0 ? o.lds_slots : 512, false, u, dev),
                               1.0f, 0, nullptr, nullptr,
-                              nullptr, nullptr, (int)((p.n_points + 256 * u - 1) / (256 * u)));
+                              nullptr, nullptr, nullptr, (int)((p.n_points + 256 * u - 1) / (256 * u)));
     }
     if (o.kernel == PIP_KERNEL_PER_PAIR)
         return launch_per_pair(p, s);

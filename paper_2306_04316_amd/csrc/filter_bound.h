@@ -17,10 +17,37 @@ constexpr float kN1 = 1.0f + 2.384185791015625e-7f;            // 1 + 2^-22 >= |
 constexpr double kLim = 1.152921504606846976e18;              // 2^60
 constexpr double kTiny = 8.673617379884035e-19;               // 2^-60
 
+constexpr float kLimF = 1.152921504606846976e18f;   // 2^60
+constexpr unsigned kRingBad = 0xffffffffu;         // M marker: an edge outside the filter's range
+
 __device__ __forceinline__ bool normal_ok(double v)
 {
     const double a = fabs(v);
     return a == 0.0 || (a >= kTiny && a <= kLim);
+}
+
+// The filtered record (NX, NY, -C, 0) of edge (a, b) re-centred on c, and
+// max(|a_x - c_x|, |a_y - c_y|) rounded up (or kRingBad when the edge is
+// outside the filter's range).
+__device__ __forceinline__ float4 filtered_record(double ax, double ay, double bx, double by, double cx, double cy,
+                                                  unsigned *m_bits)
+{
+    double nx = by - ay;
+    double ny = ax - bx;
+    if (nx < 0.0) {
+        nx = -nx;
+        ny = -ny;
+    }
+    const double sn = nx + fabs(ny);
+    // exact scaling by 2^-e, 1 <= sn 2^-e < 2 (sn = 0: a horizontal edge, never straddling)
+    const int e = sn > 0.0 ? ilogb(sn) : 0;
+    const double nxs = ldexp(nx, -e), nys = ldexp(ny, -e);
+    const double dx = ax - cx, dy = ay - cy;
+    const double c = dx * nxs + dy * nys;   // separately rounded (no contraction in this unit)
+    const double m = fmax(fabs(dx), fabs(dy));
+    const bool ok = normal_ok(nx) && normal_ok(ny) && m <= kLim;
+    *m_bits = ok ? __float_as_uint(__double2float_ru(m)) : kRingBad;
+    return make_float4((float)nxs, (float)nys, (float)(-c), 0.0f);
 }
 
 // The item's undecided pairs join the recheck list with one global atomic per

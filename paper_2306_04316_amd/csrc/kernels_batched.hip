@@ -63,9 +63,6 @@ namespace pip {
 
 namespace {
 
-constexpr float kLimF = 1.152921504606846976e18f;        // 2^60
-constexpr unsigned kRingBad = 0xffffffffu;              // M_ring marker: an edge outside the filter's range
-
 struct BatchedArgs {
     const double *px, *py;
     int64_t n;
@@ -85,6 +82,11 @@ struct BatchedArgs {
     unsigned *recheck_count;
     unsigned long long *stats;   // [256][2]: point-edge tests, undecided side tests (stats kernels)
     const int32_t *order;
+    const ItemDesc *desc;        // per workgroup (or NULL: the range is found from the pairs)
+    int wave_k;                  // filtered: rings of at least wave_k vertices go to the wave kernel (0: none)
+    WaveTask *tasks;
+    unsigned *task_count;
+    unsigned max_tasks;
 };
 
 struct BatchedLds {
@@ -94,6 +96,8 @@ struct BatchedLds {
     double *XD;     // the tile's x values
     double *YD;     // the tile's y values, 64 padding slots after the tile
     void *REC;      // per edge (indexed by its end vertex): float4 filtered, double4 exact
+    int *RF;        // per ring: the item's stamp when a pair of the item has it; minus the stamp once
+                    // it is left to the wave kernel
 };
 
 }  // namespace
@@ -102,19 +106,20 @@ struct BatchedLds {
 __host__ __device__ inline size_t batched_layout(int S, int max_rings, bool F, size_t *o)
 {
     size_t x = 0;
-    size_t at[6];
-    const size_t sizes[6] = {(size_t)(max_rings + 1) * 4,
+    size_t at[7];
+    const size_t sizes[7] = {(size_t)(max_rings + 1) * 4,
                              F ? (size_t)max_rings * 16 : 0,
                              F ? (size_t)max_rings * 4 : 0,
                              (size_t)S * 8,
                              ((size_t)S + 64) * 8,
-                             (size_t)S * (F ? 16 : 32)};
-    for (int i = 0; i < 6; ++i) {
+                             (size_t)S * (F ? 16 : 32),
+                             F ? (size_t)max_rings * 4 : 0};
+    for (int i = 0; i < 7; ++i) {
         at[i] = x;
         x = (x + sizes[i] + 15) & ~(size_t)15;
     }
     if (o)
-        for (int i = 0; i < 6; ++i)
+        for (int i = 0; i < 7; ++i)
             o[i] = at[i];
     return x;
 }
@@ -129,7 +134,7 @@ namespace {
 template <bool F>
 __device__ __forceinline__ BatchedLds batched_lds(unsigned char *smem, int S, int max_rings)
 {
-    size_t o[6];
+    size_t o[7];
     batched_layout(S, max_rings, F, o);
     BatchedLds L;
     L.T = (int *)(smem + o[0]);
@@ -138,6 +143,7 @@ __device__ __forceinline__ BatchedLds batched_lds(unsigned char *smem, int S, in
     L.XD = (double *)(smem + o[3]);
     L.YD = (double *)(smem + o[4]);
     L.REC = (void *)(smem + o[5]);
+    L.RF = (int *)(smem + o[6]);
     return L;
 }
 
@@ -147,30 +153,6 @@ template <typename T>
 __device__ __forceinline__ T lds_load(const T *p)
 {
     return *(const __attribute__((address_space(3))) T *)p;
-}
-
-// The filtered record (NX, NY, -C, 0) of edge (a, b) re-centred on c, and
-// max(|a_x - c_x|, |a_y - c_y|) rounded up (or kRingBad when the edge is
-// outside the filter's range).
-__device__ __forceinline__ float4 filtered_record(double ax, double ay, double bx, double by, double cx, double cy,
-                                                  unsigned *m_bits)
-{
-    double nx = by - ay;
-    double ny = ax - bx;
-    if (nx < 0.0) {
-        nx = -nx;
-        ny = -ny;
-    }
-    const double sn = nx + fabs(ny);
-    // exact scaling by 2^-e, 1 <= sn 2^-e < 2 (sn = 0: a horizontal edge, never straddling)
-    const int e = sn > 0.0 ? ilogb(sn) : 0;
-    const double nxs = ldexp(nx, -e), nys = ldexp(ny, -e);
-    const double dx = ax - cx, dy = ay - cy;
-    const double c = dx * nxs + dy * nys;   // separately rounded (no contraction in this unit)
-    const double m = fmax(fabs(dx), fabs(dy));
-    const bool ok = normal_ok(nx) && normal_ok(ny) && m <= kLim;
-    *m_bits = ok ? __float_as_uint(__double2float_ru(m)) : kRingBad;
-    return make_float4((float)nxs, (float)nys, (float)(-c), 0.0f);
 }
 
 // Parity contribution of one lane's ring part: edges ending at staged
@@ -186,7 +168,11 @@ __device__ __forceinline__ void walk_part(const BatchedLds &L, int base, int k, 
                                           uint32_t &n_und)
 {
     const double yq = yu + 0.0;   // no negative zero (see shift_in_above)
-    float amin = __builtin_inff();   // smallest |S| over the part's side tests (filtered)
+    // smallest |S| over the part's side tests (filtered), as binary32 bits:
+    // non-negative floats order as their bit patterns, so an integer minimum
+    // needs no NaN quieting of the running value (a NaN S, never produced for
+    // an eligible pair, would read as larger than any finite value)
+    uint32_t amin = 0x7f800000u;
     const int y_alloc = S + 64;
     for (int c0 = 0; c0 < S; c0 += 32) {
         if (__builtin_amdgcn_ballot_w64(k > c0) == 0)
@@ -224,7 +210,7 @@ __device__ __forceinline__ void walk_part(const BatchedLds &L, int base, int k, 
                 const float sv = __builtin_fmaf(PX, rec.x, __builtin_fmaf(PY, rec.y, rec.z));
                 // finite for every eligible pair (non-finite inputs make the
                 // ring or the point ineligible)
-                amin = fminf(amin, fabsf(sv));
+                amin = min(amin, __float_as_uint(sv) & 0x7fffffffu);
                 if (STATS)
                     n_und += fabsf(sv) > bnd ? 0u : 1u;
                 par ^= __float_as_uint(sv);
@@ -243,23 +229,25 @@ __device__ __forceinline__ void walk_part(const BatchedLds &L, int base, int k, 
         }
     }
     if (F)
-        und = und || !(amin > bnd);
+        und = und || !(__uint_as_float(amin) > bnd);
 }
 
 template <bool F, int U, bool STATS>
-__device__ __forceinline__ void batched_item(int64_t p0, const BatchedArgs &A, unsigned char *smem)
+__device__ __forceinline__ void batched_item(int64_t p0, const ItemRows<U> &P, const ItemRange &R,
+                                             const BatchedArgs &A, unsigned char *smem)
 {
     const int tid = threadIdx.x;
     const int S = A.tile;
-    const ItemRows<U> P = load_rows<U>(p0, A.px, A.py, A.n, A.point_poly);
-    const ItemRange R = uniform_range(item_range<false>(p0, 256 * U, A.n, A.offsets, A.n_polys, nullptr,
-                                                        A.n_polys, A.nv, A.point_poly));
     const int qf = R.qf, ql = R.ql, nr = R.nr, nvr = R.nv;
     const int64_t vb = R.vb;
     const bool tables = R.ok && nr <= A.max_rings;
     const BatchedLds L = batched_lds<F>(smem, S, A.max_rings);
     __shared__ int s_all[4];
     __shared__ unsigned s_rcnt, s_rbase;
+    // tiles the item's own walks need (bit per tile of S vertices), when large
+    // rings go to the wave kernel; items of more tiles than bits walk them all
+    constexpr int kNeedWords = 64;
+    __shared__ unsigned s_need[kNeedWords];
     __shared__ unsigned s_stat[2];
 
     // First round of the ring table and of the first tile: one entry of each
@@ -298,6 +286,8 @@ __device__ __forceinline__ void batched_item(int64_t p0, const BatchedArgs &A, u
         if (F)
             for (int r = tid; r < nr; r += 256)
                 L.RM[r] = 0u;
+        if (F && A.wave_k > 0 && tid < kNeedWords)
+            s_need[tid] = 0u;
     }
     if (tid == 0) {
         s_rcnt = 0;
@@ -308,6 +298,16 @@ __device__ __forceinline__ void batched_item(int64_t p0, const BatchedArgs &A, u
 #pragma unroll
     for (int u = 0; u < U; ++u)
         mine_ok = mine_ok && (P.q[u] < 0 || (P.q[u] >= qf && P.q[u] <= ql));
+    // the rings this item's pairs use, marked with a stamp unique to the
+    // workgroup (no clearing needed)
+    const int stamp = (int)blockIdx.x + 1;
+    const bool wave = F && A.wave_k > 0 && tables;
+    if (wave) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (P.q[u] >= qf && P.q[u] <= ql)
+                L.RF[P.q[u] - qf] = stamp;
+    }
     const bool staged = block_all(tables && mine_ok, s_all);
 
     if (!staged) {
@@ -330,6 +330,32 @@ __device__ __forceinline__ void batched_item(int64_t p0, const BatchedArgs &A, u
         return;
     }
 
+    // Large rings with pairs here go to the wave kernel, one task each; a
+    // ring whose task does not fit the list is walked here as any other.
+    if (wave && tid < nr) {
+        int v = 0;
+        const bool has = L.RF[tid] == stamp;
+        if (L.T[tid + 1] - L.T[tid] >= A.wave_k && has) {
+            const unsigned at = atomicAdd(A.task_count, 1u);
+            if (at < A.max_tasks) {
+                WaveTask t;
+                t.p_lo = p0;
+                t.ring = qf + tid;
+                t.count = (int)(A.n - p0 < 256 * U ? A.n - p0 : 256 * U);
+                A.tasks[at] = t;
+                v = -stamp;
+            }
+        }
+        L.RF[tid] = v;   // read by the rows after the next barrier
+        // a ring with pairs walked here needs the tiles it spans
+        if (L.RF[tid] != -stamp && has && L.T[tid + 1] > L.T[tid]) {
+            const int f = L.T[tid] / S, l = (L.T[tid + 1] - 1) / S;
+            for (int t = f; t <= l && t < 32 * kNeedWords; ++t)
+                atomicOr(&s_need[t >> 5], 1u << (t & 31));
+        }
+    }
+    const bool skip_tiles = wave && (nvr + S - 1) / S <= 32 * kNeedWords;
+
     uint32_t par[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -340,6 +366,10 @@ __device__ __forceinline__ void batched_item(int64_t p0, const BatchedArgs &A, u
     for (int t0 = 0; t0 < nvr; t0 += S) {
         const int t1 = nvr - t0 < S ? nvr : t0 + S;
         const int tn = t1 - t0;
+        // a later tile that only rings of the wave kernel (or rings without
+        // pairs here) cover is neither staged nor walked (uniform: LDS word)
+        if (t0 > 0 && skip_tiles && !((s_need[(t0 / S) >> 5] >> ((t0 / S) & 31)) & 1u))
+            continue;
         if (t0 > 0) {
             for (int e = tid; e < tn; e += 256) {
                 L.XD[e] = A.vx[vb + t0 + e];
@@ -396,7 +426,8 @@ __device__ __forceinline__ void batched_item(int64_t p0, const BatchedArgs &A, u
             const int e0 = L.T[r], e1 = L.T[r + 1];
             const int a = e0 > t0 ? e0 : t0;
             const int b = e1 < t1 ? e1 : t1;
-            const int k = (P.q[u] >= 0 && b > a) ? b - a : 0;
+            const bool dfr = wave && P.q[u] >= 0 && L.RF[r] == -stamp;   // left to the wave kernel
+            const int k = (P.q[u] >= 0 && b > a && !dfr) ? b - a : 0;
             const bool own = a == e0 && b == e1 && k <= 32;
             uint32_t prev = 0;
             if (k > 0 && !own) {
@@ -433,7 +464,8 @@ __device__ __forceinline__ void batched_item(int64_t p0, const BatchedArgs &A, u
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t i = p0 + u * 256 + tid;
-        const bool valid = i < A.n;
+        const bool dfr = wave && P.q[u] >= 0 && L.RF[P.q[u] - qf] == -stamp;
+        const bool valid = i < A.n && !dfr;
         const bool un = F && (((und >> u) & 1u) || A.force_recheck);
         und_rows[u] = __builtin_amdgcn_ballot_w64(valid && un);
         if (valid && !un)
@@ -463,8 +495,29 @@ template <bool F, int U, bool STATS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(U == 4 ? 5 : 8))) void k_batched(BatchedArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int item = A.order ? A.order[blockIdx.x] : (int)blockIdx.x;
-    batched_item<F, U, STATS>((int64_t)item * (256 * U), A, smem);
+    if (A.desc) {
+        // one scalar load gives the item and its range; the pairs, the ring
+        // table and the first tile then load together
+        const ItemDesc d = A.desc[blockIdx.x];
+        const int64_t p0 = (int64_t)d.item * (256 * U);
+        const ItemRows<U> P = load_rows<U>(p0, A.px, A.py, A.n, A.point_poly);
+        ItemRange R;
+        R.vb = d.vb;
+        R.rf = d.qf;
+        R.qf = d.qf;
+        R.ql = d.ql;
+        R.ok = d.nv >= 0;
+        R.nr = d.nv >= 0 ? d.ql - d.qf + 1 : 0;
+        R.nv = d.nv >= 0 ? d.nv : 0;
+        batched_item<F, U, STATS>(p0, P, R, A, smem);
+    } else {
+        const int item = A.order ? A.order[blockIdx.x] : (int)blockIdx.x;
+        const int64_t p0 = (int64_t)item * (256 * U);
+        const ItemRows<U> P = load_rows<U>(p0, A.px, A.py, A.n, A.point_poly);
+        const ItemRange R = uniform_range(item_range<false>(p0, 256 * U, A.n, A.offsets, A.n_polys, nullptr,
+                                                            A.n_polys, A.nv, A.point_poly));
+        batched_item<F, U, STATS>(p0, P, R, A, smem);
+    }
 }
 
 template <bool F, int U, bool STATS>
@@ -488,7 +541,8 @@ void launch_batched_u(const BatchedArgs &A, int U, int grid, size_t shmem, hipSt
 
 int launch_batched(const Problem &p, hipStream_t stream, bool filtered, int pairs_per_lane, int tile,
                    float bound_scale, int force_recheck, int32_t *recheck, unsigned *recheck_count,
-                   unsigned long long *stats, const int32_t *order, int n_items)
+                   unsigned long long *stats, const int32_t *order, const ItemDesc *desc, int n_items,
+                   const WaveOut &wave)
 {
     if (p.poly_rings)
         return fail(PIP_ENOTSUP, "the batched kernel takes one ring per polygon");
@@ -513,12 +567,35 @@ int launch_batched(const Problem &p, hipStream_t stream, bool filtered, int pair
     const double kb = 8.0 * 0x1p-24 * n1 * (double)bound_scale * (1.0 + 0x1p-20);
     const double eb = 4.0 * 0x1p-126 * (n1 + 1.0) * (double)bound_scale * (1.0 + 0x1p-20);
     BatchedArgs A{p.px, p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside,
-                  tile, max_rings, fb, (float)kb, (float)eb, force_recheck, recheck, recheck_count, stats, order};
+                  tile, max_rings, fb, (float)kb, (float)eb, force_recheck, recheck, recheck_count, stats, order, desc,
+                  0, nullptr, nullptr, 0};
     if (filtered) {
+        const bool w = wave.wave_k > 0 && wave.tasks && wave.task_count && wave.cursor && wave.grid > 0;
+        if (w) {
+            A.wave_k = wave.wave_k < 64 ? 64 : wave.wave_k;
+            A.tasks = wave.tasks;
+            A.task_count = wave.task_count;
+            A.max_tasks = wave.max_tasks;
+        }
+        // with the wave kernel after it, the main-kernel timestamps span both
+        KernelTimer &kt = kernel_timer();
+        const KernelTimer saved = kt;
+        if (w)
+            kt.stop = nullptr;
         if (stats)
             launch_batched_u<true, true>(A, U, n_items, shmem, stream);
         else
             launch_batched_u<true, false>(A, U, n_items, shmem, stream);
+        kt = saved;
+        PIP_HIP_TRY(hipGetLastError());
+        if (w) {
+            kt.start = nullptr;
+            const int rc = launch_wave_rings(p, stream, wave.tasks, wave.task_count, wave.max_tasks, wave.cursor,
+                                             (float)kb, (float)eb, force_recheck, recheck, recheck_count, stats,
+                                             wave.grid);
+            kt = saved;
+            return rc;
+        }
     } else {
         if (stats)
             launch_batched_u<false, true>(A, U, n_items, shmem, stream);

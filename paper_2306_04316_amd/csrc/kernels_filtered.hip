@@ -448,13 +448,29 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
     return __longlong_as_double(readlane64(__double_as_longlong(v), lane));
 }
 
-// Binary64 recheck, in the rule's operation order, of the listed pairs.  A
-// wavefront takes 64 consecutive list entries: a pair whose ring has at most
-// kRecheckWide vertices is walked by its own lane; each longer ring is then
-// walked by the whole wavefront, lane l taking edges l, l + 64, ... (coalesced
-// loads), the crossings' parity gathered with one ballot.  A fixed grid
-// strides over the list; its length is read on the device, so the launch
-// does not depend on it (graph-safe).
+// Binary64 recheck, in the rule's operation order, of the listed pairs, in
+// two passes over the list with a fixed grid (its length is read on the
+// device, so the launch does not depend on it: graph-safe):
+//   1. every pair whose ring has at most kRecheckWide vertices is walked by
+//      one lane, four vertices' loads issued together;
+//   2. every longer ring is walked by one wavefront per pair, wavefronts
+//      spread over the list (not one wavefront taking a run of long pairs in
+//      turn), lane l taking edges l, l + 64, ... (coalesced loads, four edges
+//      per round), the crossings' parity gathered with one ballot.
+__device__ __forceinline__ void recheck_ring(const double *__restrict__ px, const double *__restrict__ py,
+                                             const int64_t *__restrict__ offsets, int64_t n_polys,
+                                             int64_t nv, const int32_t *__restrict__ point_poly, int64_t i,
+                                             double &x, double &y, int64_t &b, int64_t &e)
+{
+    int64_t qq = point_poly ? (int64_t)point_poly[i] : 0;
+    qq = ((uint64_t)qq < (uint64_t)n_polys) ? qq : 0;
+    b = offsets[qq];
+    e = offsets[qq + 1];
+    clamp_ring(b, e, nv);
+    x = px[i];
+    y = py[i];
+}
+
 __global__ __launch_bounds__(256) void k_recheck_fp64(
     const double *__restrict__ px, const double *__restrict__ py,
     const int64_t *__restrict__ offsets, int64_t n_polys,
@@ -466,50 +482,74 @@ __global__ __launch_bounds__(256) void k_recheck_fp64(
     m = m < cap ? m : cap;
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // the loop bound is the same for every lane of a wavefront
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); base < m; base += stride) {
-        const int64_t t = base + lane;
-        const bool valid = t < m;
-        int64_t i = 0, b = 0, e = 0;
-        double x = 0.0, y = 0.0;
-        if (valid) {
-            i = list[t];
-            int64_t qq = point_poly ? (int64_t)point_poly[i] : 0;
-            qq = ((uint64_t)qq < (uint64_t)n_polys) ? qq : 0;
-            b = offsets[qq];
-            e = offsets[qq + 1];
-            clamp_ring(b, e, nv);
-            x = px[i];
-            y = py[i];
-        }
-        const bool wide = valid && e - b > kRecheckWide;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += stride) {
+        const int64_t i = list[t];
+        double x, y;
+        int64_t b, e;
+        recheck_ring(px, py, offsets, n_polys, nv, point_poly, i, x, y, b, e);
+        if (e - b > kRecheckWide)
+            continue;
         unsigned par = 0;
-        if (valid && !wide && e > b) {
+        if (e > b) {
             double ax = vx[e - 1], ay = vy[e - 1];
-            for (int64_t j = b; j < e; ++j) {
+            int64_t j = b;
+            for (; j + 4 <= e; j += 4) {
+                double bx[4], by[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    bx[u] = vx[j + u];
+                    by[u] = vy[j + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    par ^= rule_crossing(x, y, ax, ay, bx[u], by[u]);
+                    ax = bx[u];
+                    ay = by[u];
+                }
+            }
+            for (; j < e; ++j) {
                 const double bx = vx[j], by = vy[j];
                 par ^= rule_crossing(x, y, ax, ay, bx, by);
                 ax = bx;
                 ay = by;
             }
         }
-        uint64_t todo = __builtin_amdgcn_ballot_w64(wide);
-        while (todo) {
-            const int s = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const double xs = readlane_f64(x, s), ys = readlane_f64(y, s);
-            const int64_t bs = readlane64(b, s), ks = readlane64(e, s) - bs;
-            unsigned lp = 0;
-            for (int64_t j = lane; j < ks; j += 64) {
-                const int64_t ja = j == 0 ? ks - 1 : j - 1;
-                lp ^= rule_crossing(xs, ys, vx[bs + ja], vy[bs + ja], vx[bs + j], vy[bs + j]);
+        inside[i] = (uint8_t)par;
+    }
+    // wide rings: one wavefront per pair (the loop bound is wave-uniform)
+    const int64_t nwaves = stride >> 6;
+    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < m; t += nwaves) {
+        const int64_t i = list[t];
+        double x, y;
+        int64_t b, e;
+        recheck_ring(px, py, offsets, n_polys, nv, point_poly, i, x, y, b, e);
+        const int64_t k = e - b;
+        if (k <= kRecheckWide)
+            continue;
+        unsigned lp = 0;
+        int64_t j = lane;
+        for (; j + 192 < k; j += 256) {
+            double ax[4], ay[4], bx[4], by[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t jj = j + 64 * u;
+                const int64_t ja = jj == 0 ? k - 1 : jj - 1;
+                ax[u] = vx[b + ja];
+                ay[u] = vy[b + ja];
+                bx[u] = vx[b + jj];
+                by[u] = vy[b + jj];
             }
-            const unsigned odd = (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64(lp != 0)) & 1u;
-            if (lane == s)
-                par = odd;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                lp ^= rule_crossing(x, y, ax[u], ay[u], bx[u], by[u]);
         }
-        if (valid)
-            inside[i] = (uint8_t)par;
+        for (; j < k; j += 64) {
+            const int64_t ja = j == 0 ? k - 1 : j - 1;
+            lp ^= rule_crossing(x, y, vx[b + ja], vy[b + ja], vx[b + j], vy[b + j]);
+        }
+        const unsigned odd = (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64(lp != 0)) & 1u;
+        if (lane == 0)
+            inside[i] = (uint8_t)odd;
     }
 }
 

@@ -10,6 +10,7 @@
 // inside a bucket does not matter for the results.
 
 #include "pip_common.h"
+#include "staged_exact.h"
 
 namespace pip {
 namespace {
@@ -117,10 +118,50 @@ __global__ __launch_bounds__(256) void k_item_hist(const int32_t *__restrict__ p
         atomicAdd(&counters[threadIdx.x], h[threadIdx.x]);
 }
 
+// Descriptor of every work item (the range the batched kernel would find
+// from the item's first and last pair), and with bucket set its cost bucket
+// and the bucket histogram (counters[0..31], zeroed first).
+template <bool LPT>
+__global__ __launch_bounds__(256) void k_item_desc(const int32_t *__restrict__ pp, int64_t n,
+                                                   const int64_t *__restrict__ offsets, int64_t n_polys, int64_t nv,
+                                                   int item_pairs, int n_items, ItemDesc *__restrict__ desc,
+                                                   uint8_t *__restrict__ bucket, unsigned *counters)
+{
+    __shared__ unsigned h[kBuckets];
+    if (LPT) {
+        if (threadIdx.x < kBuckets)
+            h[threadIdx.x] = 0;
+        __syncthreads();
+    }
+    for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < n_items; it += gridDim.x * blockDim.x) {
+        const int64_t p0 = (int64_t)it * item_pairs;
+        const ItemRange R = item_range<false>(p0, item_pairs, n, offsets, n_polys, nullptr, n_polys, nv, pp);
+        ItemDesc d;
+        d.vb = R.vb;
+        d.item = it;
+        d.qf = R.qf;
+        d.ql = R.ql;
+        d.nv = R.ok ? R.nv : -1;
+        desc[it] = d;
+        if (LPT) {
+            const int b = item_bucket(it, pp, n, offsets, n_polys, nullptr, n_polys, item_pairs);
+            bucket[it] = (uint8_t)b;
+            atomicAdd(&h[b], 1u);
+        }
+    }
+    if (LPT) {
+        __syncthreads();
+        if (threadIdx.x < kBuckets && h[threadIdx.x])
+            atomicAdd(&counters[threadIdx.x], h[threadIdx.x]);
+    }
+}
+
 // Each workgroup handles a contiguous chunk of items: counts them per bucket
-// in LDS, reserves a range per bucket with one global atomic, then places them.
+// in LDS, reserves a range per bucket with one global atomic, then places them
+// (and, with desc set, their descriptors in the same order).
 __global__ __launch_bounds__(256) void k_item_scatter(const uint8_t *__restrict__ bucket, int n_items,
-                                                      int chunk, unsigned *counters, int32_t *__restrict__ order)
+                                                      int chunk, unsigned *counters, int32_t *__restrict__ order,
+                                                      const ItemDesc *__restrict__ desc, ItemDesc *__restrict__ sdesc)
 {
     __shared__ unsigned h[kBuckets], base[kBuckets], pos[kBuckets];
     const int t = threadIdx.x;
@@ -144,7 +185,10 @@ __global__ __launch_bounds__(256) void k_item_scatter(const uint8_t *__restrict_
     __syncthreads();
     for (int it = i0 + t; it < i1; it += blockDim.x) {
         const int b = bucket[it];
-        order[base[b] + atomicAdd(&pos[b], 1u)] = it;
+        const unsigned at = base[b] + atomicAdd(&pos[b], 1u);
+        order[at] = it;
+        if (desc)
+            sdesc[at] = desc[it];
     }
 }
 
@@ -185,7 +229,32 @@ int launch_item_order(const Problem &p, hipStream_t stream, int item_pairs, int 
                        p.poly_rings, p.n_rings, item_pairs, n_items, bucket, counters);
     const int chunk = 2048;
     hipLaunchKernelGGL(k_item_scatter, dim3(grid_for(n_items, chunk)), dim3(256), 0, stream, bucket, n_items, chunk,
-                       counters, order);
+                       counters, order, nullptr, nullptr);
+    PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
+
+int launch_item_desc(const Problem &p, hipStream_t stream, int item_pairs, int n_items, ItemDesc *desc,
+                     uint8_t *bucket, unsigned *counters, int32_t *order, ItemDesc *sdesc)
+{
+    if (n_items <= 0)
+        return PIP_OK;
+    if (p.poly_rings)
+        return fail(PIP_ENOTSUP, "item descriptors take one ring per polygon");
+    unsigned g = grid_for(n_items, 256);
+    g = g > 1024 ? 1024 : g;
+    const bool lpt = order && p.point_poly;
+    if (lpt) {
+        PIP_TRY(launch_fill(counters, 2 * kBuckets, 0u, stream));
+        hipLaunchKernelGGL(k_item_desc<true>, dim3(g), dim3(256), 0, stream, p.point_poly, p.n_points, p.offsets,
+                           p.n_polys, p.n_vertices, item_pairs, n_items, desc, bucket, counters);
+        const int chunk = 2048;
+        hipLaunchKernelGGL(k_item_scatter, dim3(grid_for(n_items, chunk)), dim3(256), 0, stream, bucket, n_items,
+                           chunk, counters, order, desc, sdesc);
+    } else {
+        hipLaunchKernelGGL(k_item_desc<false>, dim3(g), dim3(256), 0, stream, p.point_poly, p.n_points, p.offsets,
+                           p.n_polys, p.n_vertices, item_pairs, n_items, desc, nullptr, nullptr);
+    }
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
 }

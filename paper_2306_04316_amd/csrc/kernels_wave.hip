@@ -1,0 +1,285 @@
+// Wavefront-per-large-ring form of the filtered batched step (paper, Method
+// section, constraint 1, and Algorithm 1, with the half-open straddle
+// reading): lanes are edges and the point is wave-uniform.
+//
+// The batched kernel leaves the pairs of rings with at least wave_k vertices
+// to this kernel and lists each such ring once per work item, with the
+// item's pair range (WaveTask).  A workgroup takes one task at a time from a
+// queue.  Its pairs of the ring (point_poly equal to the ring) are compacted
+// into an LDS table of binary64 p_y and binary32 P = fl32(fl64(p - c)), c the
+// ring's first vertex.  The ring's 64-edge chunks are cut into groups of up
+// to eight held in registers, and the four wavefronts share the (group, point
+// slice) units.  Lane l of chunk j holds edge e = 64 j + l, from vertex e-1
+// (the last vertex for e = 0) to vertex e: both endpoints' y in binary64 and
+// the batched kernel's filtered record (NX, NY, -C).  For each point:
+//   above masks A = ballot(y_a > p_y), B = ballot(y_b > p_y), exact, so the
+//   straddling edges are A ^ B (half-open rule);
+//   S = fma(P_x, NX, fma(P_y, NY, -C)) on every lane;
+//   crossings (A ^ B) & ballot(S < 0) fold into a 64-bit XOR, whose popcount
+//   parity is the group's contribution;
+//   a straddling edge with |S| <= B_p, B_p = fma(M, k_B, e_B) and M =
+//   max(the group's M, |P_x|, |P_y|), makes the pair undecided.
+// A group's parity and undecided flag go into the point's LDS word by one
+// lane; when every unit is done the workgroup writes each decided pair's
+// byte and lists the undecided ones for the binary64 recheck.  The error
+// bound and its proof are the batched kernel's: a group's M bounds |a - c|
+// over the anchors its tests use, and the same eligibility limits apply.
+// Edges that cannot straddle (horizontal, or lanes past the ring's end) carry
+// y_a = y_b and a record whose S is 2^100, so they never count.
+//
+// This translation unit must be compiled with -ffp-contract=off.
+
+#include "filter_bound.h"
+#include "pip_common.h"
+#include "ring_walk.h"
+
+namespace pip {
+namespace {
+
+constexpr int kGroup = 8;                 // 64-edge chunks per register group
+constexpr float kFar = 1.2676506002282294e30f;   // 2^100: the offset of a record that never counts
+
+struct WaveArgs {
+    const double *px, *py;
+    int64_t n;
+    const int64_t *offsets;
+    int64_t n_polys;
+    const double *vx, *vy;
+    int64_t nv;
+    const int32_t *point_poly;
+    uint8_t *inside;
+    const WaveTask *tasks;
+    const unsigned *task_count;
+    unsigned max_tasks;
+    unsigned *cursor;
+    float bound_k, bound_eta;
+    int force_recheck;
+    int32_t *recheck;
+    unsigned *recheck_count;
+    unsigned long long *stats;   // [256][2]: point-edge tests, undecided side tests
+};
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, (uint32_t)__shfl_xor((int)v, o));
+    return v;
+}
+
+// One unit: the group's NJ chunks (in registers) against the points m =
+// slice, slice + nslices, ... of the table.  Adds each point's parity and
+// undecided flag into s_acc.
+template <int NJ, bool STATS>
+__device__ __forceinline__ void wave_unit(const double (&ya)[kGroup], const double (&yb)[kGroup],
+                                          const float (&nx)[kGroup], const float (&ny)[kGroup],
+                                          const float (&cc)[kGroup], float mg, bool bad, int M, int slice,
+                                          int nslices, const double *s_py, const float4 *s_pt, unsigned *s_acc,
+                                          float bound_k, float bound_eta, uint32_t &n_und)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t mgb = __float_as_uint(mg);
+    for (int m = slice; m < M; m += nslices) {
+        const double p = s_py[m];
+        const float4 pt = s_pt[m];
+        // M = max(group M, |P_x|, |P_y|): non-negative floats order as their bits
+        const float mm = __uint_as_float(max(mgb, __float_as_uint(pt.z)));
+        const float bnd = __builtin_fmaf(mm, bound_k, bound_eta);
+        uint64_t X = 0, U = 0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const uint64_t strad = __builtin_amdgcn_ballot_w64(ya[j] > p) ^ __builtin_amdgcn_ballot_w64(yb[j] > p);
+            const float sv = __builtin_fmaf(pt.x, nx[j], __builtin_fmaf(pt.y, ny[j], cc[j]));
+            X ^= strad & __builtin_amdgcn_ballot_w64(__float_as_int(sv) < 0);
+            const uint64_t un = strad & __builtin_amdgcn_ballot_w64(!(fabsf(sv) > bnd));
+            U |= un;
+            if (STATS)
+                n_und += (uint32_t)__builtin_popcountll(un);
+        }
+        // bit 0 of the point's word sums (XORs) the groups' parities; an
+        // undecided group adds 2^16 (carries from bit 0 stay below it)
+        const unsigned r = ((unsigned)__builtin_popcountll(X) & 1u) | ((U != 0 || bad) ? 0x10000u : 0u);
+        if (r != 0 && lane == 0)
+            atomicAdd(&s_acc[m], r);
+    }
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(256) void k_wave_rings(WaveArgs A)
+{
+    __shared__ double s_py[256];
+    __shared__ float4 s_pt[256];       // P_x, P_y, max(|P_x|, |P_y|), the pair's offset in the block (bits)
+    __shared__ unsigned s_acc[256];    // bit 0: crossing parity; from bit 16: undecided groups
+    __shared__ unsigned s_task, s_m, s_rcnt, s_rbase;
+    __shared__ unsigned s_stat[2];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+    const unsigned cnt = *A.task_count;
+    const unsigned ntask = cnt < A.max_tasks ? cnt : A.max_tasks;
+    uint32_t n_tests = 0, n_und = 0;
+    if (STATS && tid < 2)
+        s_stat[tid] = 0;
+
+    for (;;) {
+        if (tid == 0)
+            s_task = atomicAdd(A.cursor, 1u);
+        __syncthreads();
+        const unsigned t = s_task;
+        if (t >= ntask)
+            break;
+        const WaveTask T = A.tasks[t];
+        int64_t b = A.offsets[T.ring], e = A.offsets[T.ring + 1];
+        clamp_ring(b, e, A.nv);
+        const int k = (int)(e - b);
+        const double cx = k > 0 ? A.vx[b] : 0.0, cy = k > 0 ? A.vy[b] : 0.0;
+        const int nch = (k + 63) >> 6;
+        const int G = (nch + kGroup - 1) / kGroup;
+        const int nslices = G >= 4 ? 1 : 4 / G;
+        const int64_t pend = T.p_lo + T.count < A.n ? T.p_lo + T.count : A.n;
+
+        for (int64_t q0 = T.p_lo; q0 < pend; q0 += 256) {
+            if (tid == 0) {
+                s_m = 0;
+                s_rcnt = 0;
+            }
+            __syncthreads();
+            // the block's pairs of this ring, compacted into the point table
+            const int64_t i = q0 + tid;
+            const bool mine = i < pend && (A.point_poly ? A.point_poly[i] : 0) == T.ring;
+            double py = 0.0;
+            float PX = 0.0f, PY = 0.0f, mp = 0.0f;
+            if (mine) {
+                const double px = A.px[i];
+                py = A.py[i];
+                PX = (float)(px - cx);
+                PY = (float)(py - cy);
+                mp = fmaxf(fabsf(PX), fabsf(PY));
+            }
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(mine);
+            unsigned wbase = 0;
+            if (lane == 0 && bal)
+                wbase = atomicAdd(&s_m, (unsigned)__builtin_popcountll(bal));
+            wbase = __builtin_amdgcn_readfirstlane(wbase);
+            if (mine) {
+                const int m = (int)wbase + (int)__builtin_popcountll(bal & ((1ull << lane) - 1ull));
+                s_py[m] = py;
+                s_pt[m] = make_float4(PX, PY, mp, __int_as_float(tid));
+                // |P| < 2^60 (binary32) keeps |p - c| < 2^60
+                s_acc[m] = (k > 0 && mp < kLimF) ? 0u : 0x10000u;
+            }
+            __syncthreads();
+            const int M = (int)s_m;
+
+            for (int unit = w; unit < G * nslices; unit += 4) {
+                const int g = unit % G;
+                const int slice = unit / G;
+                const int c0 = g * kGroup;
+                const int nj = nch - c0 < kGroup ? nch - c0 : kGroup;
+                double ya[kGroup], yb[kGroup];
+                float nx[kGroup], ny[kGroup], cc[kGroup];
+                uint32_t mb = 0;
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j) {
+                    const int ej = (c0 + j) * 64 + lane;
+                    ya[j] = 0.0;
+                    yb[j] = 0.0;
+                    nx[j] = 0.0f;
+                    ny[j] = 0.0f;
+                    cc[j] = kFar;
+                    if (j < nj && ej < k) {
+                        const int ep = ej == 0 ? k - 1 : ej - 1;
+                        const double ax = A.vx[b + ep], ay = A.vy[b + ep];
+                        const double bx = A.vx[b + ej], by = A.vy[b + ej];
+                        if (ay != by) {
+                            unsigned mj;
+                            const float4 rec = filtered_record(ax, ay, bx, by, cx, cy, &mj);
+                            ya[j] = ay;
+                            yb[j] = by;
+                            nx[j] = rec.x;
+                            ny[j] = rec.y;
+                            cc[j] = rec.z;
+                            mb = max(mb, mj);
+                        }
+                    }
+                    // one edge's loads and record at a time: the group's
+                    // registers hold only the finished records
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                mb = wave_max_u32(mb);
+                const bool bad = mb == kRingBad;
+                const float mg = bad ? 0.0f : __uint_as_float(mb);
+                switch (nj) {
+                case 1: wave_unit<1, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
+                case 2: wave_unit<2, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
+                case 3: wave_unit<3, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
+                case 4: wave_unit<4, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
+                case 5: wave_unit<5, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
+                case 6: wave_unit<6, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
+                case 7: wave_unit<7, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
+                default: wave_unit<8, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
+                }
+            }
+            __syncthreads();
+
+            // outputs: decided pairs' bytes; undecided ones join the recheck list
+            bool und = false;
+            int64_t ip = 0;
+            if (tid < M) {
+                const unsigned acc = s_acc[tid];
+                ip = q0 + __float_as_int(s_pt[tid].w);
+                und = (acc >> 16) != 0 || A.force_recheck;
+                if (!und)
+                    A.inside[ip] = (uint8_t)(acc & 1u);
+                if (STATS)
+                    n_tests += (uint32_t)k;
+            }
+            const uint64_t ub = __builtin_amdgcn_ballot_w64(und);
+            unsigned rb = 0;
+            if (lane == 0 && ub)
+                rb = atomicAdd(&s_rcnt, (unsigned)__builtin_popcountll(ub));
+            rb = __builtin_amdgcn_readfirstlane(rb);
+            __syncthreads();
+            if (tid == 0 && s_rcnt)
+                s_rbase = atomicAdd(A.recheck_count, s_rcnt);
+            __syncthreads();
+            if (und)
+                A.recheck[s_rbase + rb + (unsigned)__builtin_popcountll(ub & ((1ull << lane) - 1ull))] = (int32_t)ip;
+            // the next block (or task) rewrites the table only after the barrier at its start
+        }
+        __syncthreads();   // every thread has read s_task before thread 0 takes the next one
+    }
+    if (STATS) {
+        if (n_tests)
+            atomicAdd(&s_stat[0], n_tests);
+        if (n_und)
+            atomicAdd(&s_stat[1], n_und);
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long *st = A.stats + (blockIdx.x & 255) * 2;
+            atomicAdd(st, (unsigned long long)s_stat[0]);
+            atomicAdd(st + 1, (unsigned long long)s_stat[1]);
+        }
+    }
+}
+
+}  // namespace
+
+int launch_wave_rings(const Problem &p, hipStream_t stream, const WaveTask *tasks, const unsigned *task_count,
+                      unsigned max_tasks, unsigned *cursor, float bound_k, float bound_eta, int force_recheck,
+                      int32_t *recheck, unsigned *recheck_count, unsigned long long *stats, int grid)
+{
+    if (grid <= 0)
+        return PIP_OK;
+    WaveArgs A{p.px, p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside,
+               tasks, task_count, max_tasks, cursor, bound_k, bound_eta, force_recheck, recheck, recheck_count,
+               stats};
+    if (stats)
+        PIP_LAUNCH(k_wave_rings<true>, dim3(grid), dim3(256), 0, stream, A);
+    else
+        PIP_LAUNCH(k_wave_rings<false>, dim3(grid), dim3(256), 0, stream, A);
+    PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
+
+}  // namespace pip

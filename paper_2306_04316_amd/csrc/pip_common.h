@@ -42,7 +42,7 @@ KernelTimer &kernel_timer();
 #define PIP_LAUNCH(kernel, grid, block, shmem, stream, ...)                                          \
     do {                                                                                             \
         const ::pip::KernelTimer &kt_ = ::pip::kernel_timer();                                       \
-        if (kt_.start)                                                                               \
+        if (kt_.start || kt_.stop)                                                                   \
             hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, kt_.start, kt_.stop, 0u, __VA_ARGS__); \
         else                                                                                         \
             hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                     \
@@ -125,11 +125,46 @@ int launch_filtered(const Problem &p, hipStream_t stream, int pairs_per_lane, in
 int launch_recheck(const Problem &p, hipStream_t stream, const int32_t *list, const unsigned *count, int grid);
 
 // ---------------------------------------------------------------- batched kernel (both modes, LDS tiles)
+// A work item's place in the inputs, written once per execution by the
+// preparation: item id, the polygons qf..ql of its first and last pair and
+// their vertex range [vb, vb + nv); nv = -1 when the ids are out of range or
+// not ordered (one ring per polygon).
+struct ItemDesc {
+    int64_t vb;
+    int32_t item;
+    int32_t qf, ql;
+    int32_t nv;
+};
+// A ring whose pairs in one work item the wavefront-per-large-ring kernel
+// classifies: pairs p_lo .. p_lo+count-1 with point_poly equal to `ring`.
+struct WaveTask {
+    int64_t p_lo;
+    int32_t ring;
+    int32_t count;
+};
+// Where the batched kernel leaves the pairs of rings of at least wave_k
+// vertices (filtered mode; wave_k = 0: none): tasks, their count (zeroed
+// before the launch), at most max_tasks of them, and the queue cursor of the
+// wave kernel (zeroed).
+struct WaveOut {
+    int wave_k = 0;
+    WaveTask *tasks = nullptr;
+    unsigned *task_count = nullptr;
+    unsigned max_tasks = 0;
+    unsigned *cursor = nullptr;
+    int grid = 0;   // workgroups of the wave kernel
+};
 size_t batched_smem_bytes(int tile, int max_rings, bool filtered);
-// stats: NULL, or [256][2] counters (point-edge tests, undecided side tests) added to
+// stats: NULL, or [256][2] counters (point-edge tests, undecided side tests) added to.
+// desc: NULL (each workgroup finds its item's range itself, item order[b] or
+// b), or one descriptor per workgroup (in launch order).
 int launch_batched(const Problem &p, hipStream_t stream, bool filtered, int pairs_per_lane, int tile,
                    float bound_scale, int force_recheck, int32_t *recheck, unsigned *recheck_count,
-                   unsigned long long *stats, const int32_t *order, int n_items);
+                   unsigned long long *stats, const int32_t *order, const ItemDesc *desc, int n_items,
+                   const WaveOut &wave = WaveOut());
+int launch_wave_rings(const Problem &p, hipStream_t stream, const WaveTask *tasks, const unsigned *task_count,
+                      unsigned max_tasks, unsigned *cursor, float bound_k, float bound_eta, int force_recheck,
+                      int32_t *recheck, unsigned *recheck_count, unsigned long long *stats, int grid);
 
 // ---------------------------------------------------------------- y-index for one large ring
 struct IndexLayout {
@@ -147,6 +182,10 @@ int launch_runs_indexed(const Problem &p, hipStream_t s, const IndexLayout &L, u
 int launch_fill(unsigned *p, int n, unsigned v, hipStream_t stream);
 int launch_item_order(const Problem &p, hipStream_t stream, int item_pairs, int n_items, uint8_t *bucket,
                       unsigned *counters, int32_t *order);
+// Descriptors of the work items (one ring per polygon); with `order` set also
+// the heaviest-first order, and sdesc the descriptors in that order.
+int launch_item_desc(const Problem &p, hipStream_t stream, int item_pairs, int n_items, ItemDesc *desc,
+                     uint8_t *bucket, unsigned *counters, int32_t *order, ItemDesc *sdesc);
 int launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t stream);
 int launch_read(const void *src, int64_t nbytes, unsigned *sink, hipStream_t stream);
 // Exclusive scan of n uint32 counts into out[0..n] (int64; out[n] = total);

@@ -27,8 +27,12 @@ struct pip_plan {
     unsigned *counters = nullptr;   // [0,64) ordering, [64] queue, [65] recheck count
     uint8_t *bucket = nullptr;
     int32_t *order = nullptr;
+    pip::ItemDesc *desc = nullptr;    // batched kernel: item descriptors, and in heaviest-first order
+    pip::ItemDesc *sdesc = nullptr;
     int32_t *recheck = nullptr;
     unsigned long long *stats = nullptr;   // [256][2] device counters (plans with stats = 1)
+    pip::WaveTask *tasks = nullptr;        // wave kernel tasks (filtered batched plans)
+    unsigned max_tasks = 0;
     unsigned char *index_ws = nullptr;
     pip::IndexLayout index;
     hipGraph_t graph = nullptr;
@@ -47,7 +51,9 @@ namespace {
 constexpr int kQueue = 64;
 constexpr int kRecheckCount = 65;
 constexpr int kSpan = 66;        // [66, 99): item span maximum and log2 histogram
-constexpr int kCounters = 100;
+constexpr int kTaskCount = 100;  // wave kernel: tasks listed, queue cursor
+constexpr int kTaskCursor = 101;
+constexpr int kCounters = 102;
 constexpr int kStatWords = 1024;   // [256][2] 64-bit counters of the batched kernel's stats variant
 
 int item_pairs_of(const pip_plan_config &c) { return 256 * c.pairs_per_lane; }
@@ -119,7 +125,7 @@ bool phase_empty(const pip_plan *pl, const pip_plan_config &c, int ph)
         const bool lpt = c.order == 1 && pl->p.point_poly;
         const bool counters = c.mode == PIP_MODE_FILTERED_FP32 || (c.persistent && c.kernel == PIP_KERNEL_RUNS) ||
                               (pl->stats && c.kernel == PIP_KERNEL_BATCHED);
-        return !(lpt || counters);
+        return !(lpt || counters || c.kernel == PIP_KERNEL_BATCHED);
     }
     if (ph == kRecheck)
         return c.mode != PIP_MODE_FILTERED_FP32;
@@ -137,8 +143,13 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
     const bool lpt = staged_kind(c) && c.order == 1 && p.point_poly;
     if (ph == kPrep) {
         PIP_TRY(launch_fill(pl->counters + kQueue, kSpan - kQueue, 0u, s));
+        if (c.wave_k > 0)
+            PIP_TRY(launch_fill(pl->counters + kTaskCount, 2, 0u, s));
         if (pl->stats && c.kernel == PIP_KERNEL_BATCHED)
             PIP_TRY(launch_fill((unsigned *)pl->stats, kStatWords, 0u, s));
+        if (c.kernel == PIP_KERNEL_BATCHED)
+            return launch_item_desc(p, s, item_pairs_of(c), c.n_items, pl->desc, pl->bucket, pl->counters,
+                                    lpt ? pl->order : nullptr, pl->sdesc);
         if (lpt)
             PIP_TRY(launch_item_order(p, s, item_pairs_of(c), c.n_items, pl->bucket, pl->counters, pl->order));
         return PIP_OK;
@@ -146,10 +157,20 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
     if (ph == kMain) {
         unsigned *queue = c.persistent ? pl->counters + kQueue : nullptr;
         const int32_t *order = lpt ? pl->order : nullptr;
-        if (c.kernel == PIP_KERNEL_BATCHED)
+        if (c.kernel == PIP_KERNEL_BATCHED) {
+            WaveOut wave;
+            if (c.wave_k > 0 && c.mode == PIP_MODE_FILTERED_FP32) {
+                wave.wave_k = c.wave_k;
+                wave.tasks = pl->tasks;
+                wave.task_count = pl->counters + kTaskCount;
+                wave.max_tasks = pl->max_tasks;
+                wave.cursor = pl->counters + kTaskCursor;
+                wave.grid = pl->cu_count * 6;
+            }
             return launch_batched(p, s, c.mode == PIP_MODE_FILTERED_FP32, c.pairs_per_lane, c.lds_slots,
                                   pl->o.bound_scale, pl->o.force_recheck, pl->recheck, pl->counters + kRecheckCount,
-                                  pl->stats, order, c.n_items);
+                                  pl->stats, nullptr, lpt ? pl->sdesc : pl->desc, c.n_items, wave);
+        }
         if (c.mode == PIP_MODE_FILTERED_FP32)
             return launch_filtered(p, s, c.pairs_per_lane, c.lds_slots, pl->o.bound_scale, pl->o.force_recheck,
                                    pl->recheck, pl->counters + kRecheckCount, order, c.n_items, queue, c.grid);
@@ -278,10 +299,12 @@ bool kernel_allowed(const pip_plan *pl, int kern)
     return false;
 }
 
-// Cache lines: "<key> <kernel> <pairs_per_lane> <lds_slots> <persistent> <order> <use_graph> <ms>".
+// Cache lines: "<key> <kernel> <pairs_per_lane> <lds_slots> <persistent> <order> <use_graph> <ms>
+// [<wave_k>]" (lines without the last field keep the wave kernel off).
 // A cached choice fills only what the caller left open: the kernel when it
 // asked for AUTO, pairs per lane and LDS slots when 0, persistence and order
-// when -1 (an explicit request is never overridden).
+// when -1, the wave kernel's ring size when 0 (an explicit request is never
+// overridden).
 bool cache_lookup(const pip_plan *pl, pip_plan_config &c)
 {
     const char *path = cache_path(pl);
@@ -291,14 +314,21 @@ bool cache_lookup(const pip_plan *pl, pip_plan_config &c)
     if (!f)
         return false;
     const std::string key = tune_key(pl);
-    char k[200];
-    int kern, u, l, pe, od, gr;
+    char line[512], k[200];
+    int kern, u, l, pe, od, gr, wk;
     float ms;
     bool found = false;
-    while (fscanf(f, "%199s %d %d %d %d %d %d %f", k, &kern, &u, &l, &pe, &od, &gr, &ms) == 8) {
+    while (fgets(line, sizeof line, f)) {
+        wk = 0;
+        const int nf = sscanf(line, "%199s %d %d %d %d %d %d %f %d", k, &kern, &u, &l, &pe, &od, &gr, &ms, &wk);
+        if (nf < 8)
+            continue;
         const bool sane = kernel_allowed(pl, kern) && (u == 1 || u == 2 || u == 4) && l >= 16 && l <= 2048 &&
-                          (pe == 0 || pe == 1) && (od == 0 || od == 1) && (gr == 0 || gr == 1);
+                          (pe == 0 || pe == 1) && (od == 0 || od == 1) && (gr == 0 || gr == 1) &&
+                          (wk == 0 || (wk >= 64 && wk <= (1 << 30)));
         if (key == k && sane) {
+            if (pl->o.wave_k == 0 && pl->o.mode == PIP_MODE_FILTERED_FP32 && !pl->p.poly_rings)
+                c.wave_k = wk;
             c.kernel = kern;
             if (pl->o.pairs_per_lane <= 0)
                 c.pairs_per_lane = u;
@@ -325,8 +355,8 @@ void cache_store(const pip_plan *pl, const pip_plan_config &c)
     FILE *f = fopen(path, "a");
     if (!f)
         return;
-    fprintf(f, "%s %d %d %d %d %d %d %.6f\n", tune_key(pl).c_str(), c.kernel, c.pairs_per_lane, c.lds_slots,
-            c.persistent, c.order, c.use_graph, c.tune_ms);
+    fprintf(f, "%s %d %d %d %d %d %d %.6f %d\n", tune_key(pl).c_str(), c.kernel, c.pairs_per_lane, c.lds_slots,
+            c.persistent, c.order, c.use_graph, c.tune_ms, c.wave_k);
     fclose(f);
 }
 
@@ -395,6 +425,12 @@ int autotune(pip_plan *pl, hipStream_t s)
     std::vector<pip_plan_config> cands;
     const int lds_opts[] = {128, 256, 512, 1024};
     const int ppl_opts[] = {1, 2, 4};
+    // the batched kernel's split between lane-per-pair walks and the wave
+    // kernel (filtered mode, ring size left open): off, or rings from 256 or
+    // from 1024 vertices
+    std::vector<int> wave_opts = {0};
+    if (pl->o.wave_k == 0 && pl->o.mode == PIP_MODE_FILTERED_FP32 && !pl->p.poly_rings)
+        wave_opts = {0, 256, 1024};
     std::vector<int> kernels;
     for (int kern : {PIP_KERNEL_BATCHED, PIP_KERNEL_STAGED, PIP_KERNEL_RUNS})
         if (kernel_allowed(pl, kern))
@@ -405,15 +441,20 @@ int autotune(pip_plan *pl, hipStream_t s)
                 if (kern == PIP_KERNEL_RUNS && l != lds_opts[0])
                     continue;   // the runs kernel stages nothing
                 for (int pe = 0; pe <= (kern == PIP_KERNEL_BATCHED ? 0 : 1); ++pe)
-                    for (int od = 0; od <= (pl->p.point_poly ? 1 : 0); ++od) {
-                        pip_plan_config c = pl->cfg;
-                        c.kernel = kern;
-                        c.pairs_per_lane = u;
-                        c.lds_slots = l;
-                        c.persistent = pe;
-                        c.order = od;
-                        cands.push_back(c);
-                    }
+                    for (int od = 0; od <= (pl->p.point_poly ? 1 : 0); ++od)
+                        for (int wk : wave_opts) {
+                            if (wk && kern != PIP_KERNEL_BATCHED)
+                                continue;
+                            pip_plan_config c = pl->cfg;
+                            c.kernel = kern;
+                            c.pairs_per_lane = u;
+                            c.lds_slots = l;
+                            c.persistent = pe;
+                            c.order = od;
+                            if (kern == PIP_KERNEL_BATCHED && pl->o.wave_k == 0)
+                                c.wave_k = wk;
+                            cands.push_back(c);
+                        }
             }
     // total budget: about 2 s of device time, or every candidate once for long steps
     float spent = 0.f;
@@ -535,6 +576,8 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
         return fail(PIP_EINVAL, "n_points=%lld: plans take fewer than 2^31 pairs", (long long)n_points);
     if (o.stats && o.kernel != PIP_KERNEL_BATCHED && o.kernel != PIP_KERNEL_AUTO)
         return fail(PIP_EINVAL, "stats counting needs the batched kernel");
+    if (o.wave_k < -1)
+        return fail(PIP_EINVAL, "wave_k=%d (0 default, -1 off, else a ring size)", o.wave_k);
     DeviceInfo *dev = nullptr;
     PIP_TRY(current_device(&dev));
     hipStream_t s = (hipStream_t)stream;
@@ -572,9 +615,13 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
     c.use_graph = (o.use_graph && !o.timing) ? 1 : 0;
     if (c.pairs_per_lane != 1 && c.pairs_per_lane != 2 && c.pairs_per_lane != 4)
         c.pairs_per_lane = 4;
+    // the wave kernel takes the large rings of filtered batched plans
+    // (0: left to the tuner or the cache, off until they choose)
+    c.wave_k = (o.mode == PIP_MODE_FILTERED_FP32 && o.wave_k > 0 && !p.poly_rings) ? std::max(64, o.wave_k) : 0;
 
     int rc = PIP_OK;
-    // workspace: counters | bucket[n_items max] | order[n_items max] | recheck[n_points]
+    // workspace: counters | bucket[n_items max] | order[n_items max] | item descriptors, unsorted and
+    // sorted [n_items max] | recheck[n_points]
     const int64_t max_items = (n_points + 255) / 256 + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -585,8 +632,16 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
     const size_t o_cnt = take(kCounters * sizeof(unsigned));
     const size_t o_bkt = take((size_t)max_items);
     const size_t o_ord = take((size_t)max_items * sizeof(int32_t));
+    const size_t o_dsc = take((size_t)max_items * sizeof(ItemDesc));
+    const size_t o_sds = take((size_t)max_items * sizeof(ItemDesc));
     const size_t o_rck = take(o.mode == PIP_MODE_FILTERED_FP32 ? (size_t)std::max<int64_t>(n_points, 1) * 4 : 0);
     const size_t o_st = take(o.stats ? kStatWords * sizeof(unsigned) : 0);
+    // wave kernel tasks: one per (work item, large ring with pairs in it); with
+    // pairs sorted by polygon at most items + polygons of them (a list that
+    // would overflow leaves the extra rings to the batched kernel itself)
+    const bool wave_ws = o.mode == PIP_MODE_FILTERED_FP32 && o.wave_k >= 0 && !p.poly_rings;
+    const uint64_t mt = wave_ws ? std::min<uint64_t>((uint64_t)max_items + (uint64_t)p.n_polys, 0x7fffffffull) : 0;
+    const size_t o_tsk = take((size_t)mt * sizeof(WaveTask));
     if (o.index) {
         if (point_poly) {
             delete pl;
@@ -610,8 +665,12 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
     pl->counters = (unsigned *)(w + o_cnt);
     pl->bucket = w + o_bkt;
     pl->order = (int32_t *)(w + o_ord);
+    pl->desc = (ItemDesc *)(w + o_dsc);
+    pl->sdesc = (ItemDesc *)(w + o_sds);
     pl->recheck = o.mode == PIP_MODE_FILTERED_FP32 ? (int32_t *)(w + o_rck) : nullptr;
     pl->stats = o.stats ? (unsigned long long *)(w + o_st) : nullptr;
+    pl->tasks = mt ? (WaveTask *)(w + o_tsk) : nullptr;
+    pl->max_tasks = (unsigned)mt;
     pl->index_ws = o.index ? w + o_idx : nullptr;
     for (int k = 0; k < 4 && rc == PIP_OK; ++k) {
         e = hipEventCreate(&pl->ev[k]);

@@ -239,11 +239,21 @@ def test_autotune_and_cache(P, tmp_path):
     st, cfg = check_plan(P, w, "batched", mode="exact", tune=1, tune_cache=cache)
     assert cfg["tuned"] == 1 and cfg["tune_ms"] > 0
     text = open(cache).read().split()
-    assert len(text) == 8
+    assert len(text) == 9 and text[-1] == "0"     # exact mode: no wave kernel
     st, cfg2 = check_plan(P, w, "batched", mode="exact", tune=1, tune_cache=cache)
     assert cfg2["tuned"] == 2
-    for k in ("kernel", "pairs_per_lane", "lds_slots", "persistent", "order", "use_graph"):
+    for k in ("kernel", "pairs_per_lane", "lds_slots", "persistent", "order", "use_graph", "wave_k"):
         assert cfg2[k] == cfg[k]
+    # filtered: the tuner also picks the wave kernel's ring size (off, 256 or 1024), kept by the cache
+    st, cfg = check_plan(P, w, "batched", mode="filtered", tune=1, tune_cache=cache)
+    assert cfg["tuned"] == 1 and cfg["wave_k"] in (0, 256, 1024)
+    st, cfg2 = check_plan(P, w, "batched", mode="filtered", tune=1, tune_cache=cache)
+    assert cfg2["tuned"] == 2 and cfg2["wave_k"] == cfg["wave_k"] and cfg2["kernel"] == cfg["kernel"]
+    # an old cache line without the field keeps the wave kernel off
+    with open(cache, "w") as f:
+        f.write(" ".join(text[:-1]) + "\n")
+    st, cfg3 = check_plan(P, w, "batched", mode="exact", tune=1, tune_cache=cache)
+    assert cfg3["tuned"] == 2 and cfg3["wave_k"] == 0
 
 
 @pytest.mark.parametrize("mode", ["exact", "filtered"])
