@@ -77,10 +77,14 @@ PAPER_CONTEXT = {
 # under profiles/), keyed by (workload, mode, kernel name, digest of the kernel's sources): an entry
 # stops applying when the sources change, and the figures it feeds are then reported as null.
 # fetch/write: FETCH_SIZE and WRITE_SIZE scaled by their reading of a copy kernel of known size.
-PROFILED: dict = {}
+PROFILED: dict = {
+    (4, "filtered", "k_filtered_fp32", "519e538e64e5"): {
+        "fetch_bytes": 2413930019, "write_bytes": 100029869, "valu_insts": 498057611, "waves": 390656,
+        "source": "profiles/filtered_batched.md"},
+}
 
 KERNEL_SOURCES = {
-    "k_batched": ("kernels_batched.hip", "staged_exact.h", "ring_walk.h", "filter_bound.h"),
+    "k_batched": ("kernels_batched.hip", "kernels_wave.hip", "staged_exact.h", "ring_walk.h", "filter_bound.h"),
     "k_filtered_fp32": ("kernels_filtered.hip", "staged_exact.h", "ring_walk.h", "filter_bound.h"),
     "k_staged_batched_fp64": ("kernels_exact.hip", "staged_exact.h", "ring_walk.h"),
     "k_runs_batched_fp64": ("kernels_exact.hip", "ring_walk.h"),
@@ -130,6 +134,9 @@ def parse(argv=None):
     ap.add_argument("--lds-slots", type=int, default=0)
     ap.add_argument("--persistent", type=int, default=-1)
     ap.add_argument("--order", type=int, default=-1)
+    ap.add_argument("--wave-k", type=int, default=0,
+                    help="filtered batched plans: ring size from which the wavefront-per-ring kernel takes the "
+                         "pairs (0 = the tuner's or the cache's choice, -1 = off)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip autotuning at plan creation")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
@@ -457,7 +464,8 @@ def cpu_baseline(w, budget_s, th, sample_n=None):
 def plan_options(a, mode, kernel, **kw):
     o = dict(mode=mode, kernel=kernel, pairs_per_lane=a.pairs_per_lane, lds_slots=a.lds_slots,
              persistent=a.persistent, order=a.order, use_graph=not a.no_graph,
-             tune=0 if (a.no_tune or kernel in ("per_pair", "segmented")) else 1, tune_cache=a.tune_cache)
+             tune=0 if (a.no_tune or kernel in ("per_pair", "segmented")) else 1, tune_cache=a.tune_cache,
+             wave_k=a.wave_k)
     o.update(kw)
     return o
 
@@ -471,7 +479,8 @@ def measure(P, w, copies, opts, steps, warmup, config, mode, th, parity=True, wa
     last = r.last_out(warmup + steps - 1).cpu().numpy()
     r.close()
     tuned = dict(opts, tune=0, kernel=cfg["kernel"], pairs_per_lane=cfg["pairs_per_lane"],
-                 lds_slots=cfg["lds_slots"], persistent=cfg["persistent"], order=cfg["order"])
+                 lds_slots=cfg["lds_slots"], persistent=cfg["persistent"], order=cfg["order"],
+                 wave_k=cfg["wave_k"] if cfg["wave_k"] > 0 else -1)
     rk = Runner(P, copies, dict(tuned, use_graph=False, timing=1))
     ph = rk.phase_times(ktimes or max(10, min(steps, 50)))
     rk.close()
@@ -491,19 +500,32 @@ def measure(P, w, copies, opts, steps, warmup, config, mode, th, parity=True, wa
 
 
 def recheck_figures(P, w, copies, tuned):
-    """Counts of one execution with the device counters on (batched kernel):
-    point-edge tests, undecided side tests, rechecked pairs."""
-    if tuned.get("kernel") != 5 or tuned.get("mode") != "filtered":
+    """Recheck counts of one execution of the tuned filtered plan (pairs sent to the binary64
+    recheck), and the batched kernel's device counters on the same workload (point-edge tests
+    counted, side tests inside its bound) from one execution of a stats plan."""
+    if tuned.get("mode") != "filtered":
         return None
     d = copies[0]
     pl = P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], out=d["out"],
-                **dict(tuned, stats=True, use_graph=False))
+                **dict(tuned, use_graph=False))
+    pl.execute()
+    own = pl.stats()
+    pl.close()
+    opts = dict(tuned, use_graph=False, stats=True)
+    if tuned.get("kernel") != 5:
+        opts.update(kernel=5, pairs_per_lane=2, lds_slots=512)
+    pl = P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], out=d["out"], **opts)
     st = pl.execute(stats=True)
     pl.close()
-    return {"tests_counted": st["tests"], "tests_expected": w.n_tests,
-            "ambiguous_tests": st["ambiguous_tests"], "ambiguous_test_fraction": st["ambiguous_tests"] / max(1, w.n_tests),
-            "rechecked_pairs": st["rechecked_pairs"], "recheck_pair_fraction": st["rechecked_pairs"] / max(1, w.n_points),
-            "source": "one execution with the batched kernel's device counters (pip_stats)"}
+    return {"rechecked_pairs": own["rechecked_pairs"], "recheck_pair_fraction": own["rechecked_pairs"] / max(1, w.n_points),
+            "source": "one execution of the tuned plan (pip_plan_stats)",
+            "batched_kernel_counters": {
+                "tests_counted": st["tests"], "tests_expected": w.n_tests, "ambiguous_tests": st["ambiguous_tests"],
+                "ambiguous_test_fraction": st["ambiguous_tests"] / max(1, w.n_tests),
+                "rechecked_pairs": st["rechecked_pairs"],
+                "recheck_pair_fraction": st["rechecked_pairs"] / max(1, w.n_points),
+                "wave_k": opts.get("wave_k", 0),
+                "source": "one execution of a batched-kernel plan with device counters (pip_stats)"}}
 
 
 def config_entry(P, W, a, config, dev, th, clock):

@@ -8,15 +8,17 @@
 // queue.  Its pairs of the ring (point_poly equal to the ring) are compacted
 // into an LDS table of binary64 p_y and binary32 P = fl32(fl64(p - c)), c the
 // ring's first vertex.  The ring's 64-edge chunks are cut into groups of up
-// to eight held in registers, and the four wavefronts share the (group, point
-// slice) units.  Lane l of chunk j holds edge e = 64 j + l, from vertex e-1
+// to kGroup held in registers, and the four wavefronts share the (group,
+// point slice) units.  Lane l of chunk j holds edge e = 64 j + l, from vertex e-1
 // (the last vertex for e = 0) to vertex e: both endpoints' y in binary64 and
 // the batched kernel's filtered record (NX, NY, -C).  For each point:
-//   above masks A = ballot(y_a > p_y), B = ballot(y_b > p_y), exact, so the
-//   straddling edges are A ^ B (half-open rule);
+//   above bits (y_a > p_y), (y_b > p_y): the sign bits of the binary64
+//   differences p_y - y (exact), so the edge straddles when they differ
+//   (half-open rule);
 //   S = fma(P_x, NX, fma(P_y, NY, -C)) on every lane;
-//   crossings (A ^ B) & ballot(S < 0) fold into a 64-bit XOR, whose popcount
-//   parity is the group's contribution;
+//   a lane's crossing bit (straddles and S < 0) folds into its XOR word, and
+//   the popcount parity of the ballot of those words is the group's
+//   contribution;
 //   a straddling edge with |S| <= B_p, B_p = fma(M, k_B, e_B) and M =
 //   max(the group's M, |P_x|, |P_y|), makes the pair undecided.
 // A group's parity and undecided flag go into the point's LDS word by one
@@ -36,7 +38,7 @@
 namespace pip {
 namespace {
 
-constexpr int kGroup = 8;                 // 64-edge chunks per register group
+constexpr int kGroup = 5;   // 64-edge chunks per register group (80 VGPRs: six wavefronts per SIMD)
 constexpr float kFar = 1.2676506002282294e30f;   // 2^100: the offset of a record that never counts
 
 struct WaveArgs {
@@ -68,37 +70,49 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 }
 
 // One unit: the group's NJ chunks (in registers) against the points m =
-// slice, slice + nslices, ... of the table.  Adds each point's parity and
-// undecided flag into s_acc.
+// slice, slice + nslices, ... of the table.  Per chunk and point, on every
+// lane (edge): the sign bits of p_y - y_a and p_y - y_b (binary64, p_y + 0.0
+// so that p_y - y is -0 only for y > p_y... never: x - x is +0), their XOR (bit
+// 31: the edge straddles), S, then two three-input bit operations: the lane's
+// crossing word x ^= straddle & S (bit 31: S < 0) and its undecided word
+// u |= straddle & (|S| - B') with B' the float after B (bit 31: |S| <= B).
+// The point's parity is the popcount parity of ballot(x bit 31) and it is
+// undecided when any lane's u has bit 31; both go into the point's LDS word.
 template <int NJ, bool STATS>
 __device__ __forceinline__ void wave_unit(const double (&ya)[kGroup], const double (&yb)[kGroup],
                                           const float (&nx)[kGroup], const float (&ny)[kGroup],
-                                          const float (&cc)[kGroup], float mg, bool bad, int M, int slice,
-                                          int nslices, const double *s_py, const float4 *s_pt, unsigned *s_acc,
-                                          float bound_k, float bound_eta, uint32_t &n_und)
+                                          const float (&cc)[kGroup], uint32_t bgb, bool bad, int M, int slice,
+                                          int nslices, const double2 *s_pp, const float *s_bp, unsigned *s_acc,
+                                          uint32_t &n_und)
 {
     const int lane = threadIdx.x & 63;
-    const uint32_t mgb = __float_as_uint(mg);
     for (int m = slice; m < M; m += nslices) {
-        const double p = s_py[m];
-        const float4 pt = s_pt[m];
-        // M = max(group M, |P_x|, |P_y|): non-negative floats order as their bits
-        const float mm = __uint_as_float(max(mgb, __float_as_uint(pt.z)));
-        const float bnd = __builtin_fmaf(mm, bound_k, bound_eta);
-        uint64_t X = 0, U = 0;
+        const double2 pp = s_pp[m];   // p_y + 0.0; (P_x, P_y) as two binary32 in the second word
+        const double p = pp.x;
+        const float px = __uint_as_float((uint32_t)__double_as_longlong(pp.y));
+        const float py = __uint_as_float((uint32_t)(__double_as_longlong(pp.y) >> 32));
+        // B = fma(max(group M, |P|), k_B, e_B) = max(the group's B, the point's B)
+        // (the rounding is monotone); non-negative floats order as their bits.
+        // B' = the float after B: |S| < B' iff |S| <= B.
+        const float bnd1 = __uint_as_float(max(bgb, __float_as_uint(s_bp[m])) + 1u);
+        uint32_t x = 0, u = 0;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const uint64_t strad = __builtin_amdgcn_ballot_w64(ya[j] > p) ^ __builtin_amdgcn_ballot_w64(yb[j] > p);
-            const float sv = __builtin_fmaf(pt.x, nx[j], __builtin_fmaf(pt.y, ny[j], cc[j]));
-            X ^= strad & __builtin_amdgcn_ballot_w64(__float_as_int(sv) < 0);
-            const uint64_t un = strad & __builtin_amdgcn_ballot_w64(!(fabsf(sv) > bnd));
-            U |= un;
-            if (STATS)
-                n_und += (uint32_t)__builtin_popcountll(un);
+            const uint32_t ha = (uint32_t)(__double_as_longlong(p - ya[j]) >> 32);
+            const uint32_t hb = (uint32_t)(__double_as_longlong(p - yb[j]) >> 32);
+            const uint32_t t = ha ^ hb;
+            const float sv = __builtin_fmaf(px, nx[j], __builtin_fmaf(py, ny[j], cc[j]));
+            x ^= t & __float_as_uint(sv);
+            u |= t & __float_as_uint(fabsf(sv) - bnd1);
         }
+        const uint64_t xs = __builtin_amdgcn_ballot_w64((int)x < 0);
+        const uint64_t us = __builtin_amdgcn_ballot_w64((int)u < 0);
+        if (STATS)
+            n_und += (uint32_t)__builtin_popcountll(us);
         // bit 0 of the point's word sums (XORs) the groups' parities; an
         // undecided group adds 2^16 (carries from bit 0 stay below it)
-        const unsigned r = ((unsigned)__builtin_popcountll(X) & 1u) | ((U != 0 || bad) ? 0x10000u : 0u);
+        const unsigned r = __builtin_amdgcn_readfirstlane(((unsigned)__builtin_popcountll(xs) & 1u) |
+                                                         ((us != 0 || bad) ? 0x10000u : 0u));
         if (r != 0 && lane == 0)
             atomicAdd(&s_acc[m], r);
     }
@@ -107,8 +121,9 @@ __device__ __forceinline__ void wave_unit(const double (&ya)[kGroup], const doub
 template <bool STATS>
 __global__ __launch_bounds__(256) void k_wave_rings(WaveArgs A)
 {
-    __shared__ double s_py[256];
-    __shared__ float4 s_pt[256];       // P_x, P_y, max(|P_x|, |P_y|), the pair's offset in the block (bits)
+    __shared__ double2 s_pp[256];      // p_y + 0.0, and P_x, P_y (binary32) packed in one word
+    __shared__ float s_bp[256];        // fma(max(|P_x|, |P_y|), k_B, e_B): the point's part of the bound
+    __shared__ int s_off[256];         // the pair's offset in the block
     __shared__ unsigned s_acc[256];    // bit 0: crossing parity; from bit 16: undecided groups
     __shared__ unsigned s_task, s_m, s_rcnt, s_rbase;
     __shared__ unsigned s_stat[2];
@@ -149,11 +164,14 @@ __global__ __launch_bounds__(256) void k_wave_rings(WaveArgs A)
             const bool mine = i < pend && (A.point_poly ? A.point_poly[i] : 0) == T.ring;
             double py = 0.0;
             float PX = 0.0f, PY = 0.0f, mp = 0.0f;
+            bool elig = false;
             if (mine) {
                 const double px = A.px[i];
                 py = A.py[i];
                 PX = (float)(px - cx);
                 PY = (float)(py - cy);
+                // |P| < 2^60 (binary32, so |p - c| < 2^60); NaN is ineligible
+                elig = fabsf(PX) < kLimF && fabsf(PY) < kLimF;
                 mp = fmaxf(fabsf(PX), fabsf(PY));
             }
             const uint64_t bal = __builtin_amdgcn_ballot_w64(mine);
@@ -163,10 +181,11 @@ __global__ __launch_bounds__(256) void k_wave_rings(WaveArgs A)
             wbase = __builtin_amdgcn_readfirstlane(wbase);
             if (mine) {
                 const int m = (int)wbase + (int)__builtin_popcountll(bal & ((1ull << lane) - 1ull));
-                s_py[m] = py;
-                s_pt[m] = make_float4(PX, PY, mp, __int_as_float(tid));
-                // |P| < 2^60 (binary32) keeps |p - c| < 2^60
-                s_acc[m] = (k > 0 && mp < kLimF) ? 0u : 0x10000u;
+                const uint64_t pxy = (uint64_t)__float_as_uint(PX) | ((uint64_t)__float_as_uint(PY) << 32);
+                s_pp[m] = make_double2(py + 0.0, __longlong_as_double((long long)pxy));   // no negative zero
+                s_bp[m] = __builtin_fmaf(mp, A.bound_k, A.bound_eta);
+                s_off[m] = tid;
+                s_acc[m] = (k > 0 && elig) ? 0u : 0x10000u;
             }
             __syncthreads();
             const int M = (int)s_m;
@@ -206,18 +225,18 @@ __global__ __launch_bounds__(256) void k_wave_rings(WaveArgs A)
                     // registers hold only the finished records
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                mb = wave_max_u32(mb);
+                mb = __builtin_amdgcn_readfirstlane(wave_max_u32(mb));
                 const bool bad = mb == kRingBad;
-                const float mg = bad ? 0.0f : __uint_as_float(mb);
+                // the group's part of the bound: fma(M_group, k_B, e_B)
+                const uint32_t bgb = __float_as_uint(__builtin_fmaf(bad ? 0.0f : __uint_as_float(mb), A.bound_k,
+                                                                    A.bound_eta));
+                static_assert(kGroup == 5, "one case per group size");
                 switch (nj) {
-                case 1: wave_unit<1, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
-                case 2: wave_unit<2, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
-                case 3: wave_unit<3, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
-                case 4: wave_unit<4, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
-                case 5: wave_unit<5, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
-                case 6: wave_unit<6, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
-                case 7: wave_unit<7, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
-                default: wave_unit<8, STATS>(ya, yb, nx, ny, cc, mg, bad, M, slice, nslices, s_py, s_pt, s_acc, A.bound_k, A.bound_eta, n_und); break;
+                case 1: wave_unit<1, STATS>(ya, yb, nx, ny, cc, bgb, bad, M, slice, nslices, s_pp, s_bp, s_acc, n_und); break;
+                case 2: wave_unit<2, STATS>(ya, yb, nx, ny, cc, bgb, bad, M, slice, nslices, s_pp, s_bp, s_acc, n_und); break;
+                case 3: wave_unit<3, STATS>(ya, yb, nx, ny, cc, bgb, bad, M, slice, nslices, s_pp, s_bp, s_acc, n_und); break;
+                case 4: wave_unit<4, STATS>(ya, yb, nx, ny, cc, bgb, bad, M, slice, nslices, s_pp, s_bp, s_acc, n_und); break;
+                default: wave_unit<5, STATS>(ya, yb, nx, ny, cc, bgb, bad, M, slice, nslices, s_pp, s_bp, s_acc, n_und); break;
                 }
             }
             __syncthreads();
@@ -227,7 +246,7 @@ __global__ __launch_bounds__(256) void k_wave_rings(WaveArgs A)
             int64_t ip = 0;
             if (tid < M) {
                 const unsigned acc = s_acc[tid];
-                ip = q0 + __float_as_int(s_pt[tid].w);
+                ip = q0 + s_off[tid];
                 und = (acc >> 16) != 0 || A.force_recheck;
                 if (!und)
                     A.inside[ip] = (uint8_t)(acc & 1u);

@@ -20,7 +20,7 @@ def test_kernel_digest_ignores_comments(tmp_path, monkeypatch):
     csrc.mkdir(parents=True)
     src = {"kernels_batched.hip": "int f(int a) { return a + 1; } // one\n/* block */\n",
            "staged_exact.h": "#pragma once\nint h();\n", "ring_walk.h": "#pragma once\nint g();\n",
-           "filter_bound.h": "#pragma once\nint b();\n"}
+           "filter_bound.h": "#pragma once\nint b();\n", "kernels_wave.hip": "int w();\n"}
     for name, text in src.items():
         (csrc / name).write_text(text)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
