@@ -273,12 +273,12 @@ int classify_filtered(const Problem &p, DeviceInfo *dev, const pip_options &o, h
     }
     unsigned *count = (unsigned *)ws;
     int32_t *list = (int32_t *)((unsigned char *)ws + kScratchHead);
-    int rc = launch_fill(count, 1, 0u, s);
+    int rc = launch_fill(count, 2, 0u, s);   // list length, long-ring entries
     if (rc == PIP_OK)
         rc = launch_batched(p, s, true, u, tile, o.bound_scale, o.force_recheck, list, count, nullptr, nullptr,
                             nullptr, (int)((p.n_points + 256 * u - 1) / (256 * u)));
     if (rc == PIP_OK)
-        rc = launch_recheck(p, s, list, count, dev->cu_count * 8);
+        rc = launch_recheck(p, s, list, count, count + 1, dev->cu_count * 8);
     if (!fixed)
         pool_release(ws, pooled, s);
     return rc;

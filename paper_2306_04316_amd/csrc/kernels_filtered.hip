@@ -449,14 +449,18 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
 }
 
 // Binary64 recheck, in the rule's operation order, of the listed pairs, in
-// two passes over the list with a fixed grid (its length is read on the
-// device, so the launch does not depend on it: graph-safe):
-//   1. every pair whose ring has at most kRecheckWide vertices is walked by
-//      one lane, four vertices' loads issued together;
-//   2. every longer ring is walked by one wavefront per pair, wavefronts
-//      spread over the list (not one wavefront taking a run of long pairs in
-//      turn), lane l taking edges l, l + 64, ... (coalesced loads, four edges
-//      per round), the crossings' parity gathered with one ballot.
+// two kernels over the list with fixed grids (the lengths are read on the
+// device, so the launches do not depend on them: graph-safe):
+//   1. k_recheck_lanes: every pair whose ring has at most kRecheckWide
+//      vertices is walked by one lane, four vertices' loads issued together;
+//      a longer ring's pair is appended to a second list in the free tail of
+//      the same array (one counter, aggregated per wavefront), or, when the
+//      tail is full, walked by its lane as well;
+//   2. k_recheck_wide: one wavefront per appended pair, lane l taking edges
+//      l, l + 64, ... (coalesced loads, four edges per round), the
+//      crossings' parity gathered with one ballot.  (A wavefront taking a run
+//      of long pairs in turn took 0.68 ms for 592 pairs of 4096-vertex rings;
+//      a wavefront per list entry paid the list's load chain for every entry.)
 __device__ __forceinline__ void recheck_ring(const double *__restrict__ px, const double *__restrict__ py,
                                              const int64_t *__restrict__ offsets, int64_t n_polys,
                                              int64_t nv, const int32_t *__restrict__ point_poly, int64_t i,
@@ -471,24 +475,28 @@ __device__ __forceinline__ void recheck_ring(const double *__restrict__ px, cons
     y = py[i];
 }
 
-__global__ __launch_bounds__(256) void k_recheck_fp64(
+__global__ __launch_bounds__(256) void k_recheck_lanes(
     const double *__restrict__ px, const double *__restrict__ py,
     const int64_t *__restrict__ offsets, int64_t n_polys,
     const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
     const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside,
-    const int32_t *__restrict__ list, const unsigned *__restrict__ count, int64_t cap)
+    int32_t *list, const unsigned *__restrict__ count, unsigned *wide_count, int64_t cap)
 {
     int64_t m = (int64_t)*count;
     m = m < cap ? m : cap;
-    const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += stride) {
         const int64_t i = list[t];
         double x, y;
         int64_t b, e;
         recheck_ring(px, py, offsets, n_polys, nv, point_poly, i, x, y, b, e);
-        if (e - b > kRecheckWide)
-            continue;
+        if (e - b > kRecheckWide) {
+            const int64_t at = m + (int64_t)atomicAdd(wide_count, 1u);
+            if (at < cap) {
+                list[at] = (int32_t)i;
+                continue;
+            }
+        }
         unsigned par = 0;
         if (e > b) {
             double ax = vx[e - 1], ay = vy[e - 1];
@@ -516,16 +524,29 @@ __global__ __launch_bounds__(256) void k_recheck_fp64(
         }
         inside[i] = (uint8_t)par;
     }
-    // wide rings: one wavefront per pair (the loop bound is wave-uniform)
-    const int64_t nwaves = stride >> 6;
-    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < m; t += nwaves) {
-        const int64_t i = list[t];
+}
+
+__global__ __launch_bounds__(256) void k_recheck_wide(
+    const double *__restrict__ px, const double *__restrict__ py,
+    const int64_t *__restrict__ offsets, int64_t n_polys,
+    const double *__restrict__ vx, const double *__restrict__ vy, int64_t nv,
+    const int32_t *__restrict__ point_poly, uint8_t *__restrict__ inside,
+    const int32_t *__restrict__ list, const unsigned *__restrict__ count,
+    const unsigned *__restrict__ wide_count, int64_t cap)
+{
+    int64_t m = (int64_t)*count;
+    m = m < cap ? m : cap;
+    int64_t nw = (int64_t)*wide_count;
+    nw = nw < cap - m ? nw : cap - m;
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    // the loop bound is the same for every lane of a wavefront
+    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < nw; t += nwaves) {
+        const int64_t i = list[m + t];
         double x, y;
         int64_t b, e;
         recheck_ring(px, py, offsets, n_polys, nv, point_poly, i, x, y, b, e);
         const int64_t k = e - b;
-        if (k <= kRecheckWide)
-            continue;
         unsigned lp = 0;
         int64_t j = lane;
         for (; j + 192 < k; j += 256) {
@@ -622,12 +643,15 @@ int filtered_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu)
     return PIP_OK;
 }
 
-int launch_recheck(const Problem &p, hipStream_t stream, const int32_t *list, const unsigned *count, int grid)
+int launch_recheck(const Problem &p, hipStream_t stream, int32_t *list, const unsigned *count,
+                   unsigned *wide_count, int grid)
 {
     if (p.poly_rings)
         return fail(PIP_ENOTSUP, "the filtered mode takes one ring per polygon");
-    hipLaunchKernelGGL(k_recheck_fp64, dim3(grid), dim3(256), 0, stream, p.px, p.py, p.offsets, p.n_polys, p.vx,
-                       p.vy, p.n_vertices, p.point_poly, p.inside, list, count, (int64_t)p.n_points);
+    hipLaunchKernelGGL(k_recheck_lanes, dim3(grid), dim3(256), 0, stream, p.px, p.py, p.offsets, p.n_polys, p.vx,
+                       p.vy, p.n_vertices, p.point_poly, p.inside, list, count, wide_count, (int64_t)p.n_points);
+    hipLaunchKernelGGL(k_recheck_wide, dim3(grid), dim3(256), 0, stream, p.px, p.py, p.offsets, p.n_polys, p.vx,
+                       p.vy, p.n_vertices, p.point_poly, p.inside, list, count, wide_count, (int64_t)p.n_points);
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
 }

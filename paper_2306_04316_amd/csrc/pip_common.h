@@ -122,7 +122,10 @@ int filtered_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu);
 int launch_filtered(const Problem &p, hipStream_t stream, int pairs_per_lane, int max_edges, float bound_scale,
                     int force_recheck, int32_t *recheck, unsigned *recheck_count, const int32_t *order,
                     int n_items, unsigned *queue, int grid);
-int launch_recheck(const Problem &p, hipStream_t stream, const int32_t *list, const unsigned *count, int grid);
+// list: count[0] undecided pair ids, the rest of the n_points entries free
+// (used for the pairs of long rings); wide_count zeroed before the launch.
+int launch_recheck(const Problem &p, hipStream_t stream, int32_t *list, const unsigned *count,
+                   unsigned *wide_count, int grid);
 
 // ---------------------------------------------------------------- batched kernel (both modes, LDS tiles)
 // A work item's place in the inputs, written once per execution by the

@@ -53,7 +53,8 @@ constexpr int kRecheckCount = 65;
 constexpr int kSpan = 66;        // [66, 99): item span maximum and log2 histogram
 constexpr int kTaskCount = 100;  // wave kernel: tasks listed, queue cursor
 constexpr int kTaskCursor = 101;
-constexpr int kCounters = 102;
+constexpr int kRecheckWideCount = 102;   // recheck: pairs of long rings appended to the list
+constexpr int kCounters = 103;
 constexpr int kStatWords = 1024;   // [256][2] 64-bit counters of the batched kernel's stats variant
 
 int item_pairs_of(const pip_plan_config &c) { return 256 * c.pairs_per_lane; }
@@ -143,8 +144,7 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
     const bool lpt = staged_kind(c) && c.order == 1 && p.point_poly;
     if (ph == kPrep) {
         PIP_TRY(launch_fill(pl->counters + kQueue, kSpan - kQueue, 0u, s));
-        if (c.wave_k > 0)
-            PIP_TRY(launch_fill(pl->counters + kTaskCount, 2, 0u, s));
+        PIP_TRY(launch_fill(pl->counters + kTaskCount, 3, 0u, s));   // tasks, cursor, long-ring rechecks
         if (pl->stats && c.kernel == PIP_KERNEL_BATCHED)
             PIP_TRY(launch_fill((unsigned *)pl->stats, kStatWords, 0u, s));
         if (c.kernel == PIP_KERNEL_BATCHED)
@@ -183,7 +183,8 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
         return launch_staged_batched(p, s, c.pairs_per_lane, c.lds_slots, order, c.n_items, c.persistent != 0,
                                      use_tiles(pl, c.lds_slots), c.grid);
     }
-    return launch_recheck(p, s, pl->recheck, pl->counters + kRecheckCount, pl->cu_count * 8);
+    return launch_recheck(p, s, pl->recheck, pl->counters + kRecheckCount, pl->counters + kRecheckWideCount,
+                          pl->cu_count * 8);
 }
 
 // Enqueue one eager execution of the step sequence with configuration c,
