@@ -247,18 +247,20 @@ PIP_API int pip_classify(const double *px, const double *py, int64_t n_points,
                  const int32_t *point_poly, uint8_t *inside,
                  const pip_options *opts, void *stream);
 
-/* Largest n_points that pip_classify_noalloc takes in the filtered mode. */
+/* Largest n_points that pip_classify_noalloc takes on the batched kernel
+   (the filtered mode, or PIP_KERNEL_BATCHED in the exact mode). */
 #define PIP_NOALLOC_MAX_POINTS 4194304
 
 /*
  * For callers that cannot allocate device memory -- code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc: pip_classify
  * with its workspace taken from a static device array of the library's own
- * instead of an allocation.  The array holds the filtered mode's count word
- * and list of undecided pairs for up to PIP_NOALLOC_MAX_POINTS points (16 MiB
- * and 256 bytes; one copy per device, held until the process ends); the exact
- * mode needs none.  Same arguments, results and errors as pip_classify, plus
- * PIP_EINVAL for n_points > PIP_NOALLOC_MAX_POINTS in the filtered mode
+ * instead of an allocation.  The array holds the batched kernel's work-item
+ * descriptors and the filtered mode's count words and list of undecided pairs
+ * for up to PIP_NOALLOC_MAX_POINTS points (16 MiB + 384 KiB + 256 bytes; one
+ * copy per device, held until the process ends); the other exact-mode kernels
+ * need none.  Same arguments, results and errors as pip_classify, plus
+ * PIP_EINVAL for n_points > PIP_NOALLOC_MAX_POINTS on the batched kernel
  * (checked before any device call).  Calls nothing that allocates device
  * memory.  Every call on one device shares that device's array, which keeps
  * the last call's contents (the count word is cleared by a kernel at the

@@ -19,12 +19,16 @@ thread_local char g_err[512] = "";
 // validating calls on one device share it).
 __device__ unsigned g_validate_word;
 
-// The workspace of pip_classify_noalloc: a count word (padded to 256 bytes)
-// and the list of undecided pairs, PIP_NOALLOC_MAX_POINTS entries.  Host code
-// uses only the address hipGetSymbolAddress gives for the current device
-// (DeviceInfo::scratch), never the array's name.
+// The workspace of pip_classify_noalloc, laid out as batched_ws below for
+// PIP_NOALLOC_MAX_POINTS pairs: count words (padded to 256 bytes), the item
+// descriptors of the batched kernel (one item per 256 pairs at most), the
+// list of undecided pairs.  Host code uses only the address
+// hipGetSymbolAddress gives for the current device (DeviceInfo::scratch),
+// never the array's name.
 constexpr size_t kScratchHead = 256;
-__device__ __align__(256) unsigned char scratch[kScratchHead + (size_t)PIP_NOALLOC_MAX_POINTS * sizeof(int32_t)];
+constexpr size_t kScratchDesc = (((size_t)PIP_NOALLOC_MAX_POINTS + 255) / 256 * sizeof(ItemDesc) + 255) & ~(size_t)255;
+__device__ __align__(256) unsigned char
+    scratch[kScratchHead + kScratchDesc + (size_t)PIP_NOALLOC_MAX_POINTS * sizeof(int32_t)];
 
 std::mutex g_dev_mu;
 std::vector<DeviceInfo *> g_devs;
@@ -252,32 +256,40 @@ const char *pip_last_error(void) { return g_err; }
 
 namespace pip {
 namespace {
-// The filtered mode of pip_classify: the batched kernel in binary32 with its
-// list of undecided pairs (list length word, padded to 256 bytes, then
-// n_points list entries), then the binary64 recheck of the list.  The
-// workspace is a pooled, stream-ordered allocation, or `fixed` (the static
-// scratch array of pip_classify_noalloc, which allocates nothing).
-int classify_filtered(const Problem &p, DeviceInfo *dev, const pip_options &o, hipStream_t s, unsigned char *fixed)
+// The batched kernel in pip_classify: the item descriptors, the kernel (in
+// binary32 with its list of undecided pairs, or in binary64), then in the
+// filtered mode the binary64 recheck of the list.  Workspace: the list's two
+// count words (padded to 256 bytes), the descriptors (padded to 256 bytes),
+// the n_points list entries (filtered mode).  It is a pooled, stream-ordered
+// allocation, or `fixed` (the static scratch array of pip_classify_noalloc,
+// which allocates nothing).
+int classify_batched(const Problem &p, DeviceInfo *dev, const pip_options &o, hipStream_t s, bool filtered,
+                     unsigned char *fixed)
 {
     const int u = o.pairs_per_lane == 1 ? 1 : (o.pairs_per_lane == 4 ? 4 : 2);
-    const int tile = clamp_batched_tile(o.lds_slots > 0 ? o.lds_slots : 512, true, u, dev);
+    const int tile = clamp_batched_tile(o.lds_slots > 0 ? o.lds_slots : 512, filtered, u, dev);
+    const int n_items = (int)((p.n_points + 256 * u - 1) / (256 * u));
+    const size_t desc_bytes = ((size_t)n_items * sizeof(ItemDesc) + 255) & ~(size_t)255;
+    const size_t bytes = kScratchHead + desc_bytes + (filtered ? (size_t)p.n_points * sizeof(int32_t) : 0);
     void *ws = fixed;
     bool pooled = false;
-    const size_t bytes = kScratchHead + (size_t)p.n_points * sizeof(int32_t);
     if (!fixed) {
         hipError_t e = pool_alloc(&ws, bytes, dev->device, s, &pooled);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            return fail(PIP_ENOMEM, "filtered workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+            return fail(PIP_ENOMEM, "batched workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
         }
     }
     unsigned *count = (unsigned *)ws;
-    int32_t *list = (int32_t *)((unsigned char *)ws + kScratchHead);
-    int rc = launch_fill(count, 2, 0u, s);   // list length, long-ring entries
+    ItemDesc *desc = (ItemDesc *)((unsigned char *)ws + kScratchHead);
+    int32_t *list = (int32_t *)((unsigned char *)ws + kScratchHead + (fixed ? kScratchDesc : desc_bytes));
+    int rc = filtered ? launch_fill(count, 2, 0u, s) : PIP_OK;   // list length, long-ring entries
     if (rc == PIP_OK)
-        rc = launch_batched(p, s, true, u, tile, o.bound_scale, o.force_recheck, list, count, nullptr, nullptr,
-                            nullptr, (int)((p.n_points + 256 * u - 1) / (256 * u)));
+        rc = launch_item_desc(p, s, 256 * u, n_items, desc, nullptr, nullptr, nullptr, nullptr);
     if (rc == PIP_OK)
+        rc = launch_batched(p, s, filtered, u, tile, filtered ? o.bound_scale : 1.0f, filtered ? o.force_recheck : 0,
+                            filtered ? list : nullptr, filtered ? count : nullptr, nullptr, desc, n_items);
+    if (rc == PIP_OK && filtered)
         rc = launch_recheck(p, s, list, count, count + 1, dev->cu_count * 8);
     if (!fixed)
         pool_release(ws, pooled, s);
@@ -308,10 +320,14 @@ int classify_problem(Problem p, const pip_options *opts, void *stream, bool noal
         if (p.n_points > INT32_MAX)
             return fail(PIP_EINVAL, "n_points=%lld: the filtered mode takes fewer than 2^31 pairs",
                         (long long)p.n_points);
-        if (noalloc && p.n_points > PIP_NOALLOC_MAX_POINTS)
-            return fail(PIP_EINVAL, "n_points=%lld exceeds the static scratch of pip_classify_noalloc (%d points)",
-                        (long long)p.n_points, PIP_NOALLOC_MAX_POINTS);
     }
+    const bool batched = o.mode == PIP_MODE_FILTERED_FP32 || o.kernel == PIP_KERNEL_BATCHED;
+    if (batched && noalloc && p.n_points > PIP_NOALLOC_MAX_POINTS)
+        return fail(PIP_EINVAL, "n_points=%lld exceeds the static scratch of pip_classify_noalloc (%d points)",
+                    (long long)p.n_points, PIP_NOALLOC_MAX_POINTS);
+    if (batched && p.n_points > INT32_MAX)
+        return fail(PIP_EINVAL, "n_points=%lld: the batched kernel takes fewer than 2^31 pairs",
+                    (long long)p.n_points);
     if (o.kernel == PIP_KERNEL_BATCHED && (p.poly_rings || o.predicate != PIP_PRED_SIDE))
         return fail(PIP_ENOTSUP, "the batched kernel takes one ring per polygon and the side test only");
     if (o.predicate != PIP_PRED_SIDE && o.predicate != PIP_PRED_INTERSECTION)
@@ -325,14 +341,8 @@ int classify_problem(Problem p, const pip_options *opts, void *stream, bool noal
         PIP_TRY(validate_on_device(p, dev, s));
     if (p.n_points == 0)
         return PIP_OK;
-    if (o.mode == PIP_MODE_FILTERED_FP32)
-        return classify_filtered(p, dev, o, s, noalloc ? dev->scratch : nullptr);
-    if (o.kernel == PIP_KERNEL_BATCHED) {
-        const int u = o.pairs_per_lane == 1 ? 1 : (o.pairs_per_lane == 4 ? 4 : 2);
-        return launch_batched(p, s, false, u, clamp_batched_tile(o.lds_slots > 0 ? o.lds_slots : 512, false, u, dev),
-                              1.0f, 0, nullptr, nullptr,
-                              nullptr, nullptr, nullptr, (int)((p.n_points + 256 * u - 1) / (256 * u)));
-    }
+    if (batched)
+        return classify_batched(p, dev, o, s, o.mode == PIP_MODE_FILTERED_FP32, noalloc ? dev->scratch : nullptr);
     if (o.kernel == PIP_KERNEL_PER_PAIR)
         return launch_per_pair(p, s);
     if (o.kernel == PIP_KERNEL_SEGMENTED)

@@ -46,7 +46,7 @@
 // components stay at or above 2^-121, normal in binary32) and |p - c|,
 // |a - c| <= 2^60; outside that the pair is undecided.  A pair whose smallest
 // |S| over its straddling edges is at most B joins the recheck list and is
-// re-run in binary64 by k_recheck_fp64 in the rule's order.
+// re-run in binary64 in the rule's order (k_recheck_lanes, k_recheck_wide).
 //
 // Items whose pairs are not sorted by polygon, or whose polygons outnumber
 // the ring table, are classified exactly by the staged binary64 item
@@ -81,9 +81,8 @@ struct BatchedArgs {
     int32_t *recheck;
     unsigned *recheck_count;
     unsigned long long *stats;   // [256][2]: point-edge tests, undecided side tests (stats kernels)
-    const int32_t *order;
-    const ItemDesc *desc;        // per workgroup (or NULL: the range is found from the pairs)
-    int wave_k;                  // filtered: rings of at least wave_k vertices go to the wave kernel (0: none)
+    const ItemDesc *desc;        // per workgroup, in launch order
+    int wave_k;                  // rings of at least wave_k vertices go to the wave kernel (W variants)
     WaveTask *tasks;
     unsigned *task_count;
     unsigned max_tasks;
@@ -232,7 +231,7 @@ __device__ __forceinline__ void walk_part(const BatchedLds &L, int base, int k, 
         und = und || !(__uint_as_float(amin) > bnd);
 }
 
-template <bool F, int U, bool STATS>
+template <bool F, int U, bool STATS, bool W>
 __device__ __forceinline__ void batched_item(int64_t p0, const ItemRows<U> &P, const ItemRange &R,
                                              const BatchedArgs &A, unsigned char *smem)
 {
@@ -286,7 +285,7 @@ __device__ __forceinline__ void batched_item(int64_t p0, const ItemRows<U> &P, c
         if (F)
             for (int r = tid; r < nr; r += 256)
                 L.RM[r] = 0u;
-        if (F && A.wave_k > 0 && tid < kNeedWords)
+        if (W && tid < kNeedWords)
             s_need[tid] = 0u;
     }
     if (tid == 0) {
@@ -301,7 +300,7 @@ __device__ __forceinline__ void batched_item(int64_t p0, const ItemRows<U> &P, c
     // the rings this item's pairs use, marked with a stamp unique to the
     // workgroup (no clearing needed)
     const int stamp = (int)blockIdx.x + 1;
-    const bool wave = F && A.wave_k > 0 && tables;
+    const bool wave = W && tables;   // W: filtered, with the wave kernel after this one
     if (wave) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -488,61 +487,51 @@ __device__ __forceinline__ void batched_item(int64_t p0, const ItemRows<U> &P, c
     }
 }
 
-// One workgroup per item; workgroup b takes item order[b], or b.  Eight
-// waves per SIMD for one and two pairs per lane; four pairs per lane need
-// more registers than that leaves (they would spill).
-template <bool F, int U, bool STATS>
+// One workgroup per item: workgroup b takes descriptor b (the preparation's
+// item order).  Eight waves per SIMD for one and two pairs per lane; four
+// pairs per lane need more registers than that leaves (they would spill).
+template <bool F, int U, bool STATS, bool W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(U == 4 ? 5 : 8))) void k_batched(BatchedArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    if (A.desc) {
-        // one scalar load gives the item and its range; the pairs, the ring
-        // table and the first tile then load together
-        const ItemDesc d = A.desc[blockIdx.x];
-        const int64_t p0 = (int64_t)d.item * (256 * U);
-        const ItemRows<U> P = load_rows<U>(p0, A.px, A.py, A.n, A.point_poly);
-        ItemRange R;
-        R.vb = d.vb;
-        R.rf = d.qf;
-        R.qf = d.qf;
-        R.ql = d.ql;
-        R.ok = d.nv >= 0;
-        R.nr = d.nv >= 0 ? d.ql - d.qf + 1 : 0;
-        R.nv = d.nv >= 0 ? d.nv : 0;
-        batched_item<F, U, STATS>(p0, P, R, A, smem);
-    } else {
-        const int item = A.order ? A.order[blockIdx.x] : (int)blockIdx.x;
-        const int64_t p0 = (int64_t)item * (256 * U);
-        const ItemRows<U> P = load_rows<U>(p0, A.px, A.py, A.n, A.point_poly);
-        const ItemRange R = uniform_range(item_range<false>(p0, 256 * U, A.n, A.offsets, A.n_polys, nullptr,
-                                                            A.n_polys, A.nv, A.point_poly));
-        batched_item<F, U, STATS>(p0, P, R, A, smem);
-    }
+    // one scalar load gives the item and its range; the pairs, the ring
+    // table and the first tile then load together
+    const ItemDesc d = A.desc[blockIdx.x];
+    const int64_t p0 = (int64_t)d.item * (256 * U);
+    const ItemRows<U> P = load_rows<U>(p0, A.px, A.py, A.n, A.point_poly);
+    ItemRange R;
+    R.vb = d.vb;
+    R.rf = d.qf;
+    R.qf = d.qf;
+    R.ql = d.ql;
+    R.ok = d.nv >= 0;
+    R.nr = d.nv >= 0 ? d.ql - d.qf + 1 : 0;
+    R.nv = d.nv >= 0 ? d.nv : 0;
+    batched_item<F, U, STATS, W>(p0, P, R, A, smem);
 }
 
-template <bool F, int U, bool STATS>
+template <bool F, int U, bool STATS, bool W>
 void launch_batched_one(const BatchedArgs &A, int grid, size_t shmem, hipStream_t stream)
 {
-    PIP_LAUNCH((k_batched<F, U, STATS>), dim3(grid), dim3(256), shmem, stream, A);
+    PIP_LAUNCH((k_batched<F, U, STATS, W>), dim3(grid), dim3(256), shmem, stream, A);
 }
 
-template <bool F, bool STATS>
+template <bool F, bool STATS, bool W>
 void launch_batched_u(const BatchedArgs &A, int U, int grid, size_t shmem, hipStream_t stream)
 {
     if (U == 1)
-        launch_batched_one<F, 1, STATS>(A, grid, shmem, stream);
+        launch_batched_one<F, 1, STATS, W>(A, grid, shmem, stream);
     else if (U == 2)
-        launch_batched_one<F, 2, STATS>(A, grid, shmem, stream);
+        launch_batched_one<F, 2, STATS, W>(A, grid, shmem, stream);
     else
-        launch_batched_one<F, 4, STATS>(A, grid, shmem, stream);
+        launch_batched_one<F, 4, STATS, W>(A, grid, shmem, stream);
 }
 
 }  // namespace
 
 int launch_batched(const Problem &p, hipStream_t stream, bool filtered, int pairs_per_lane, int tile,
                    float bound_scale, int force_recheck, int32_t *recheck, unsigned *recheck_count,
-                   unsigned long long *stats, const int32_t *order, const ItemDesc *desc, int n_items,
-                   const WaveOut &wave)
+                   unsigned long long *stats, const ItemDesc *desc, int n_items, const WaveOut &wave)
 {
     if (p.poly_rings)
         return fail(PIP_ENOTSUP, "the batched kernel takes one ring per polygon");
@@ -561,13 +550,15 @@ int launch_batched(const Problem &p, hipStream_t stream, bool filtered, int pair
         return fail(PIP_EINVAL, "the filtered mode needs a recheck list");
     if (n_items <= 0)
         return PIP_OK;
+    if (!desc)
+        return fail(PIP_EINVAL, "the batched kernel needs the item descriptors");
     // the threshold's two coefficients, rounded up so that the one rounding of
     // fma(M, k, eta) keeps B at or above 8 u M N1 + 4 eta (N1 + 1)
     const double n1 = 2.0 + 0x1p-20;
     const double kb = 8.0 * 0x1p-24 * n1 * (double)bound_scale * (1.0 + 0x1p-20);
     const double eb = 4.0 * 0x1p-126 * (n1 + 1.0) * (double)bound_scale * (1.0 + 0x1p-20);
     BatchedArgs A{p.px, p.py, p.n_points, p.offsets, p.n_polys, p.vx, p.vy, p.n_vertices, p.point_poly, p.inside,
-                  tile, max_rings, fb, (float)kb, (float)eb, force_recheck, recheck, recheck_count, stats, order, desc,
+                  tile, max_rings, fb, (float)kb, (float)eb, force_recheck, recheck, recheck_count, stats, desc,
                   0, nullptr, nullptr, 0};
     if (filtered) {
         const bool w = wave.wave_k > 0 && wave.tasks && wave.task_count && wave.cursor && wave.grid > 0;
@@ -582,10 +573,17 @@ int launch_batched(const Problem &p, hipStream_t stream, bool filtered, int pair
         const KernelTimer saved = kt;
         if (w)
             kt.stop = nullptr;
-        if (stats)
-            launch_batched_u<true, true>(A, U, n_items, shmem, stream);
-        else
-            launch_batched_u<true, false>(A, U, n_items, shmem, stream);
+        if (w) {
+            if (stats)
+                launch_batched_u<true, true, true>(A, U, n_items, shmem, stream);
+            else
+                launch_batched_u<true, false, true>(A, U, n_items, shmem, stream);
+        } else {
+            if (stats)
+                launch_batched_u<true, true, false>(A, U, n_items, shmem, stream);
+            else
+                launch_batched_u<true, false, false>(A, U, n_items, shmem, stream);
+        }
         kt = saved;
         PIP_HIP_TRY(hipGetLastError());
         if (w) {
@@ -598,9 +596,9 @@ int launch_batched(const Problem &p, hipStream_t stream, bool filtered, int pair
         }
     } else {
         if (stats)
-            launch_batched_u<false, true>(A, U, n_items, shmem, stream);
+            launch_batched_u<false, true, false>(A, U, n_items, shmem, stream);
         else
-            launch_batched_u<false, false>(A, U, n_items, shmem, stream);
+            launch_batched_u<false, false, false>(A, U, n_items, shmem, stream);
     }
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;

@@ -159,12 +159,10 @@ struct WaveOut {
 };
 size_t batched_smem_bytes(int tile, int max_rings, bool filtered);
 // stats: NULL, or [256][2] counters (point-edge tests, undecided side tests) added to.
-// desc: NULL (each workgroup finds its item's range itself, item order[b] or
-// b), or one descriptor per workgroup (in launch order).
+// desc: one descriptor per workgroup, in launch order (launch_item_desc).
 int launch_batched(const Problem &p, hipStream_t stream, bool filtered, int pairs_per_lane, int tile,
                    float bound_scale, int force_recheck, int32_t *recheck, unsigned *recheck_count,
-                   unsigned long long *stats, const int32_t *order, const ItemDesc *desc, int n_items,
-                   const WaveOut &wave = WaveOut());
+                   unsigned long long *stats, const ItemDesc *desc, int n_items, const WaveOut &wave = WaveOut());
 int launch_wave_rings(const Problem &p, hipStream_t stream, const WaveTask *tasks, const unsigned *task_count,
                       unsigned max_tasks, unsigned *cursor, float bound_k, float bound_eta, int force_recheck,
                       int32_t *recheck, unsigned *recheck_count, unsigned long long *stats, int grid);

@@ -169,7 +169,7 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
             }
             return launch_batched(p, s, c.mode == PIP_MODE_FILTERED_FP32, c.pairs_per_lane, c.lds_slots,
                                   pl->o.bound_scale, pl->o.force_recheck, pl->recheck, pl->counters + kRecheckCount,
-                                  pl->stats, nullptr, lpt ? pl->sdesc : pl->desc, c.n_items, wave);
+                                  pl->stats, lpt ? pl->sdesc : pl->desc, c.n_items, wave);
         }
         if (c.mode == PIP_MODE_FILTERED_FP32)
             return launch_filtered(p, s, c.pairs_per_lane, c.lds_slots, pl->o.bound_scale, pl->o.force_recheck,
