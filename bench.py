@@ -85,6 +85,8 @@ PROFILED: dict = {
 
 KERNEL_SOURCES = {
     "k_batched": ("kernels_batched.hip", "kernels_wave.hip", "staged_exact.h", "ring_walk.h", "filter_bound.h"),
+    "k_batched+k_wave_rings": ("kernels_batched.hip", "kernels_wave.hip", "staged_exact.h", "ring_walk.h",
+                               "filter_bound.h"),
     "k_filtered_fp32": ("kernels_filtered.hip", "staged_exact.h", "ring_walk.h", "filter_bound.h"),
     "k_staged_batched_fp64": ("kernels_exact.hip", "staged_exact.h", "ring_walk.h"),
     "k_runs_batched_fp64": ("kernels_exact.hip", "ring_walk.h"),
@@ -96,7 +98,7 @@ def kernel_name(cfg) -> str:
     """The main kernel a plan configuration launches."""
     k, mode = cfg["kernel"], cfg["mode"]
     if k == 5:
-        return "k_batched"
+        return "k_batched+k_wave_rings" if cfg.get("wave_k", 0) > 0 else "k_batched"
     if k == 1:
         return "k_per_pair_fp64"
     if k == 4:
@@ -734,6 +736,10 @@ def main():
         other = "filtered" if a.mode == "exact" else "exact"
         runs = [("mode_" + other, plan_options(a, other, "auto", pairs_per_lane=0, lds_slots=0)),
                 ("staged_filtered_kernel", plan_options(a, "filtered", "staged", pairs_per_lane=0, lds_slots=0)),
+                ("batched_kernel", plan_options(a, "filtered", "batched", pairs_per_lane=0, lds_slots=0,
+                                                wave_k=-1)),
+                ("batched_kernel_wave_ring_256", plan_options(a, "filtered", "batched", pairs_per_lane=0,
+                                                              lds_slots=0, wave_k=256)),
                 ("per_pair_baseline", plan_options(a, "exact", "per_pair", use_graph=False))]
         for label, o in runs:
             progress(f"comparison: {label}")
@@ -741,6 +747,8 @@ def main():
                               parity=want is not None, ktimes=a.compare_steps)
             e["roofline"] = hbm_roofline(a.config, o["mode"], e["main_kernel"], alg_bytes, e["main_kernel_ms"],
                                          "the main kernel's own dispatch timestamps")
+            e["roofline"]["valu"] = valu_entry(a.config, o["mode"], e["main_kernel"], e["main_kernel_ms"], clock[0],
+                                               clock[1], alg_lane_ops(w, o["mode"], sf))
             compare[label] = e
         pp = compare["per_pair_baseline"]["main_kernel_ms"]
         compare["main_kernel_speedup_vs_per_pair"] = pp / main_ms
