@@ -78,9 +78,19 @@ PAPER_CONTEXT = {
 # stops applying when the sources change, and the figures it feeds are then reported as null.
 # fetch/write: FETCH_SIZE and WRITE_SIZE scaled by their reading of a copy kernel of known size.
 PROFILED: dict = {
-    (4, "filtered", "k_filtered_fp32", "519e538e64e5"): {
-        "fetch_bytes": 2413930019, "write_bytes": 100029869, "valu_insts": 498057611, "waves": 390656,
+    (4, "filtered", "k_filtered_fp32", "5108b99f135d"): {
+        "fetch_bytes": 2414023435, "write_bytes": 100030073, "valu_insts": 498057611, "waves": 390656,
         "source": "profiles/filtered_batched.md"},
+    (4, "exact", "k_staged_batched_fp64", "3490bb00a683"): {
+        "fetch_bytes": 2414989064, "write_bytes": 100027928, "valu_insts": 431314460, "waves": 390656,
+        "source": "profiles/staged_batched_exact.md"},
+    (4, "filtered", "k_batched", "cfa634536c00"): {
+        "fetch_bytes": 2473456991, "write_bytes": 100148806, "valu_insts": 503289813, "waves": 781308,
+        "source": "profiles/batched_kernel_batched.md"},
+    (4, "filtered", "k_batched+k_wave_rings", "cfa634536c00"): {
+        "fetch_bytes": (1169920 + 111204) * 1024 * 2, "write_bytes": (97833 + 1605) * 1024,
+        "valu_insts": 443473305 + 160270146, "waves": 781308 + 6144,
+        "source": "profiles/batched_kernel_wave_ring_256_batched.md"},
 }
 
 KERNEL_SOURCES = {
@@ -740,7 +750,10 @@ def main():
                                                 wave_k=-1)),
                 ("batched_kernel_wave_ring_256", plan_options(a, "filtered", "batched", pairs_per_lane=0,
                                                               lds_slots=0, wave_k=256)),
-                ("per_pair_baseline", plan_options(a, "exact", "per_pair", use_graph=False))]
+                ("per_pair_baseline", plan_options(a, "exact", "per_pair", use_graph=False)),
+                # the headline's tuned plan replayed as one HIP graph per step (the tuner may keep eager
+                # launches when they issue the sequence as fast)
+                ("tuned_plan_as_graph", dict(tuned, use_graph=True, tune=0, tune_cache=None))]
         for label, o in runs:
             progress(f"comparison: {label}")
             e, _, _ = measure(P, w, copies, o, a.compare_steps, 2, a.config, o["mode"], th, want=want,
