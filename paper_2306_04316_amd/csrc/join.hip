@@ -134,6 +134,7 @@ __global__ __launch_bounds__(256) void k_extent_final(const double4 *__restrict_
 // The grid cell of a point as the sort key (cells of at most 2^22, as the
 // join sizes the grid: 2048 coarse digits of 2048 fine digits).
 struct CellKey {
+    static constexpr bool kUsesX = true;
     const GridParams *g;
     struct Ready {
         GridParams G;

@@ -87,8 +87,12 @@ __device__ __forceinline__ int ybucket(double y, double lo, double scale)
 }
 
 // The points are counting-sorted by y bucket in two levels (sort_staged.h):
-// 1024 coarse digits of 64 fine digits each.
+// 512 coarse digits of 128 fine digits each.  The coarse pass orders pieces
+// of 4096 points, so that a digit leaves a piece as a run of about eight
+// points (whole memory lines rather than single scattered points); the fine
+// pass, one workgroup per coarse digit, orders pieces of 2048.
 struct YKey {
+    static constexpr bool kUsesX = false;
     const double2 *root;
     struct Ready {
         double lo, scale;
@@ -100,8 +104,10 @@ struct YKey {
         return Ready{lo, hi > lo ? (double)kYBuckets / (hi - lo) : 0.0};
     }
 };
-constexpr int kCoarse = 1024;
+constexpr int kCoarse = 512;
 constexpr int kFine = kYBuckets / kCoarse;
+constexpr int kSortPer = 16;   // points per thread of a sorted piece, pass 1
+constexpr int kFinePer = 8;    // the same, pass 2
 
 struct Tree {
     const double2 *b0, *b1, *b2;
@@ -389,7 +395,7 @@ int launch_index_prep(const Problem &p, hipStream_t s, const IndexLayout &L, uns
     hipLaunchKernelGGL(k_bounds_up, dim3(grid_for(L.n1, 256)), dim3(256), 0, s, b0, L.n0, b1, L.n1);
     hipLaunchKernelGGL(k_bounds_up, dim3(grid_for(L.n2, 256)), dim3(256), 0, s, b1, L.n1, b2, L.n2);
     hipLaunchKernelGGL(k_bounds_root, dim3(1), dim3(256), 0, s, b2, L.n2, root);
-    PIP_TRY((launch_sort_staged<YKey, kCoarse, kFine>(p.px, p.py, p.n_points, YKey{root}, L.nb, table, off, scan_ws,
+    PIP_TRY((launch_sort_staged<YKey, kCoarse, kFine, kSortPer, kFinePer>(p.px, p.py, p.n_points, YKey{root}, L.nb, table, off, scan_ws,
                                                      (double2 *)(ws + L.o_txy), (int32_t *)(ws + L.o_tidx),
                                                      (double2 *)(ws + L.o_spt), (int32_t *)(ws + L.o_sidx), nullptr,
                                                      s)));

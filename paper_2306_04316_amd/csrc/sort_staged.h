@@ -2,8 +2,10 @@
 // [0, NC * NF), without a global atomic per point and with coalesced writes.
 // Pass 1 orders by the coarse digit key / NF: each workgroup counts a chunk of
 // kSortChunk points in LDS, the (digit, chunk) count table is scanned, then
-// the workgroup writes its chunk out in pieces of kSortPiece points sorted by
-// digit in LDS, each digit's points leaving as one contiguous run.  Pass 2:
+// the workgroup writes its chunk out in pieces of points sorted by
+// digit in LDS, each digit's points leaving as one contiguous run (256*PER
+// points a piece, PER a template parameter: the longer a digit's run in a
+// piece, the fewer partial memory lines the scattered writes touch).  Pass 2:
 // one workgroup per coarse digit orders its run by the fine digit key % NF
 // the same way.  The order inside a key is not specified.  Used for the
 // y-index's y buckets and the candidate join's grid cells.
@@ -15,7 +17,6 @@ namespace pip {
 namespace {
 
 constexpr int kSortChunk = 16384;   // points per workgroup in pass 1
-constexpr int kSortPiece = 1024;    // points ordered in LDS at a time (4 per thread)
 
 // In-place exclusive prefix of a[0..ND) (LDS), by a workgroup of 256 threads;
 // returns the total.  Each thread sums its ND/256 entries, the wavefronts
@@ -61,12 +62,13 @@ __device__ __forceinline__ uint32_t lds_exclusive_scan(uint32_t *a, uint32_t *pa
     return total;
 }
 
-// Digits of up to kSortPiece points (4 per thread, digit -1 = no point) are
+// Digits of up to 256*PER points (PER per thread, digit -1 = no point) are
 // counted, placed in digit order in LDS and written at cur[digit] onwards
 // (cur advanced).  cnt, cur: LDS arrays of ND entries.
-template <int ND>
-__device__ __forceinline__ void write_piece_sorted(const double (&x)[4], const double (&y)[4], const int32_t (&id)[4],
-                                                   const int (&dg)[4], uint32_t *cnt, uint32_t *cur, uint32_t *part,
+template <int ND, int PER>
+__device__ __forceinline__ void write_piece_sorted(const double (&x)[PER], const double (&y)[PER],
+                                                   const int32_t (&id)[PER], const int (&dg)[PER], uint32_t *cnt,
+                                                   uint32_t *cur, uint32_t *part,
                                                    double2 *sxy, int32_t *sid, uint16_t *sdg,
                                                    double2 *__restrict__ oxy, int32_t *__restrict__ oid)
 {
@@ -74,14 +76,14 @@ __device__ __forceinline__ void write_piece_sorted(const double (&x)[4], const d
     for (int d = t; d < ND; d += 256)
         cnt[d] = 0;
     __syncthreads();
-    uint32_t rk[4];
+    uint32_t rk[PER];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < PER; ++k)
         rk[k] = dg[k] >= 0 ? atomicAdd(&cnt[dg[k]], 1u) : 0u;
     __syncthreads();
     const uint32_t total = lds_exclusive_scan<ND>(cnt, part);   // cnt: each digit's first slot
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < PER; ++k) {
         if (dg[k] >= 0) {
             const uint32_t slot = cnt[dg[k]] + rk[k];
             sxy[slot] = make_double2(x[k], y[k]);
@@ -104,6 +106,8 @@ __device__ __forceinline__ void write_piece_sorted(const double (&x)[4], const d
     __syncthreads();
 }
 
+// Key::kUsesX: whether the key reads the x coordinate (its loads are skipped
+// if not).
 template <class Key, int NC, int NF>
 __global__ __launch_bounds__(256) void k_sort_coarse_hist(const double *__restrict__ px,
                                                           const double *__restrict__ py, int64_t n, Key key, int nb,
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(256) void k_sort_coarse_hist(const double *__restri
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int64_t i = b + k * 256 + threadIdx.x;
-            x[k] = i < c1 ? px[i] : 0.0;
+            x[k] = Key::kUsesX && i < c1 ? px[i] : 0.0;
             y[k] = i < c1 ? py[i] : 0.0;
         }
 #pragma unroll
@@ -135,50 +139,51 @@ __global__ __launch_bounds__(256) void k_sort_coarse_hist(const double *__restri
         table[(int64_t)c * nb + blockIdx.x] = h[c];
 }
 
-template <class Key, int NC, int NF>
+template <class Key, int NC, int NF, int PER>
 __global__ __launch_bounds__(256) void k_sort_coarse_scatter(const double *__restrict__ px,
                                                              const double *__restrict__ py, int64_t n, Key key,
                                                              int nb, const int64_t *__restrict__ off,
                                                              double2 *__restrict__ txy, int32_t *__restrict__ tidx)
 {
+    constexpr int PIECE = 256 * PER;
     __shared__ uint32_t cnt[NC], cur[NC];   // positions fit 32 bits (fewer than 2^31 points)
     __shared__ uint32_t part[4];
-    __shared__ double2 sxy[kSortPiece];
-    __shared__ int32_t sid[kSortPiece];
-    __shared__ uint16_t sdg[kSortPiece];
+    __shared__ double2 sxy[PIECE];
+    __shared__ int32_t sid[PIECE];
+    __shared__ uint16_t sdg[PIECE];
     const auto kf = key.ready();
     for (int c = threadIdx.x; c < NC; c += 256)
         cur[c] = (uint32_t)off[(int64_t)c * nb + blockIdx.x];
     const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
     const int64_t c1 = c0 + kSortChunk < n ? c0 + kSortChunk : n;
-    // pieces of 1024 points; the next piece's loads are issued before the
+    // pieces of PIECE points; the next piece's loads are issued before the
     // current piece is ordered and written
-    double x[4], y[4];
+    double x[PER], y[PER];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < PER; ++k) {
         const int64_t i = c0 + k * 256 + threadIdx.x;
         x[k] = i < c1 ? px[i] : 0.0;
         y[k] = i < c1 ? py[i] : 0.0;
     }
-    for (int64_t p0 = c0; p0 < c1; p0 += kSortPiece) {
-        int32_t id[4];
-        int dg[4];
+    for (int64_t p0 = c0; p0 < c1; p0 += PIECE) {
+        int32_t id[PER];
+        int dg[PER];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < PER; ++k) {
             const int64_t i = p0 + k * 256 + threadIdx.x;
             id[k] = (int32_t)i;
             dg[k] = i < c1 ? (int)(kf(x[k], y[k]) / NF) : -1;
         }
-        double nx[4], ny[4];
+        double nx[PER], ny[PER];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int64_t i = p0 + kSortPiece + k * 256 + threadIdx.x;
+        for (int k = 0; k < PER; ++k) {
+            const int64_t i = p0 + PIECE + k * 256 + threadIdx.x;
             nx[k] = i < c1 ? px[i] : 0.0;
             ny[k] = i < c1 ? py[i] : 0.0;
         }
-        write_piece_sorted<NC>(x, y, id, dg, cnt, cur, part, sxy, sid, sdg, txy, tidx);
+        write_piece_sorted<NC, PER>(x, y, id, dg, cnt, cur, part, sxy, sid, sdg, txy, tidx);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < PER; ++k) {
             x[k] = nx[k];
             y[k] = ny[k];
         }
@@ -187,17 +192,18 @@ __global__ __launch_bounds__(256) void k_sort_coarse_scatter(const double *__res
 
 // One workgroup per coarse digit c: its run [off[c*nb], off[(c+1)*nb]).
 // key_start (optional, NC*NF + 1 entries): the first position of every key.
-template <class Key, int NC, int NF>
+template <class Key, int NC, int NF, int PER>
 __global__ __launch_bounds__(256) void k_sort_fine(const double2 *__restrict__ txy, const int32_t *__restrict__ tidx,
                                                    Key key, int nb, const int64_t *__restrict__ off,
                                                    double2 *__restrict__ oxy, int32_t *__restrict__ oidx,
                                                    int64_t *__restrict__ key_start)
 {
+    constexpr int PIECE = 256 * PER;
     __shared__ uint32_t cnt[NF], cur[NF];
     __shared__ uint32_t part[4];
-    __shared__ double2 sxy[kSortPiece];
-    __shared__ int32_t sid[kSortPiece];
-    __shared__ uint16_t sdg[kSortPiece];
+    __shared__ double2 sxy[PIECE];
+    __shared__ int32_t sid[PIECE];
+    __shared__ uint16_t sdg[PIECE];
     const auto kf = key.ready();
     const int c = blockIdx.x;
     const int64_t s = off[(int64_t)c * nb];
@@ -229,40 +235,41 @@ __global__ __launch_bounds__(256) void k_sort_fine(const double2 *__restrict__ t
     if (key_start && c == NC - 1 && t == 0)
         key_start[(int64_t)NC * NF] = e;
     __syncthreads();
-    double2 v[4];
-    int32_t id[4];
+    double2 v[PER];
+    int32_t id[PER];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < PER; ++k) {
         const int64_t i = s + k * 256 + t;
         v[k] = i < e ? txy[i] : make_double2(0.0, 0.0);
         id[k] = i < e ? tidx[i] : 0;
     }
-    for (int64_t p0 = s; p0 < e; p0 += kSortPiece) {
-        double x[4], y[4];
-        int dg[4];
+    for (int64_t p0 = s; p0 < e; p0 += PIECE) {
+        double x[PER], y[PER];
+        int dg[PER];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < PER; ++k) {
             x[k] = v[k].x;
             y[k] = v[k].y;
             dg[k] = p0 + k * 256 + t < e ? (int)(kf(x[k], y[k]) % NF) : -1;
         }
-        int32_t cid[4];
+        int32_t cid[PER];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < PER; ++k) {
             cid[k] = id[k];
-            const int64_t i = p0 + kSortPiece + k * 256 + t;
+            const int64_t i = p0 + PIECE + k * 256 + t;
             v[k] = i < e ? txy[i] : make_double2(0.0, 0.0);
             id[k] = i < e ? tidx[i] : 0;
         }
-        write_piece_sorted<NF>(x, y, cid, dg, cnt, cur, part, sxy, sid, sdg, oxy, oidx);
+        write_piece_sorted<NF, PER>(x, y, cid, dg, cnt, cur, part, sxy, sid, sdg, oxy, oidx);
     }
 }
 
-// Sort n points (< 2^31) by Key (values in [0, NC*NF)).  nb = chunks of
+// Sort n points (< 2^31) by Key (values in [0, NC*NF)) in pieces of 256*PER
+// points in pass 1 and 256*FPER in pass 2.  nb = chunks of
 // kSortChunk points; table: NC*nb words; off: NC*nb + 1 int64; scan_ws:
 // scan_ws_entries(NC*nb) int64; txy/tidx: n entries of intermediate storage;
 // oxy/oidx: the sorted output; key_start: optional NC*NF + 1 first positions.
-template <class Key, int NC, int NF>
+template <class Key, int NC, int NF, int PER = 4, int FPER = PER>
 int launch_sort_staged(const double *px, const double *py, int64_t n, Key key, int nb, uint32_t *table,
                        int64_t *off, int64_t *scan_ws, double2 *txy, int32_t *tidx, double2 *oxy, int32_t *oidx,
                        int64_t *key_start, hipStream_t s)
@@ -270,9 +277,9 @@ int launch_sort_staged(const double *px, const double *py, int64_t n, Key key, i
     hipLaunchKernelGGL((k_sort_coarse_hist<Key, NC, NF>), dim3(nb), dim3(256), 0, s, px, py, n, key, nb, table);
     PIP_HIP_TRY(hipGetLastError());
     PIP_TRY(launch_scan_u32(table, (int64_t)NC * nb, off, scan_ws, s));
-    hipLaunchKernelGGL((k_sort_coarse_scatter<Key, NC, NF>), dim3(nb), dim3(256), 0, s, px, py, n, key, nb, off,
+    hipLaunchKernelGGL((k_sort_coarse_scatter<Key, NC, NF, PER>), dim3(nb), dim3(256), 0, s, px, py, n, key, nb, off,
                        txy, tidx);
-    hipLaunchKernelGGL((k_sort_fine<Key, NC, NF>), dim3(NC), dim3(256), 0, s, (const double2 *)txy,
+    hipLaunchKernelGGL((k_sort_fine<Key, NC, NF, FPER>), dim3(NC), dim3(256), 0, s, (const double2 *)txy,
                        (const int32_t *)tidx, key, nb, (const int64_t *)off, oxy, oidx, key_start);
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;

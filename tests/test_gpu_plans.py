@@ -304,6 +304,45 @@ def test_plan_index_degenerate(P):
         check_plan(P, w, f"index ring k={vx.size}", index=True)
 
 
+@pytest.mark.parametrize("layout", ["one_bucket", "one_piece", "piece_plus_one", "wide_sparse", "clustered",
+                                    "descending", "three_pieces_wide"])
+def test_plan_index_point_layouts(P, layout):
+    """Point sets that stress the y-index's banded sort: every point in one
+    bucket, a single piece (2048 points) and one point more, fewer points
+    than coarse digits spread over the whole range (pieces spanning many
+    coarse digits), half the points in a band of 1e-9, points in descending
+    y.  The output is prefilled, so a point lost or duplicated by the sort
+    shows as a mismatch."""
+    import torch
+    rng = np.random.default_rng(61)
+    t = np.sort(rng.uniform(0, 2 * np.pi, 3000))
+    r = 1.0 + 0.2 * rng.uniform(-1, 1, 3000)
+    vx, vy = r * np.cos(t), r * np.sin(t)
+    n = {"one_piece": 2048, "piece_plus_one": 2049, "wide_sparse": 700, "three_pieces_wide": 3 * 2048 + 5}.get(layout,
+                                                                                                              20_000)
+    px = rng.uniform(-1.3, 1.3, n)
+    py = rng.uniform(-1.3, 1.3, n)
+    if layout == "one_bucket":
+        py[:] = 0.25
+    elif layout == "clustered":
+        py[: n // 2] = 0.1 + rng.uniform(0, 1e-9, n // 2)
+    elif layout == "descending":
+        py = np.sort(py)[::-1].copy()
+    elif layout == "three_pieces_wide":
+        py[:5] = [-1e3, 1e3, -1.25, 1.25, 0.0]
+    w = W.Workload("index-layout", px, py, np.array([0, vx.size], dtype=np.int64), vx, vy, None, {})
+    note(f"index layout {layout} N={n}")
+    d = to_dev(w)
+    pl = P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], d["point_poly"], index=True)
+    assert pl.config()["index"] == 1
+    for _ in range(2):
+        pl.out.fill_(7)
+        pl.execute()
+        torch.cuda.synchronize()
+        assert_same_mask(pl.out.cpu().numpy(), oracle.classify_workload(w), f"index layout {layout}", w.px, w.py)
+    pl.close()
+
+
 def test_plan_index_rejects_pair_index(P):
     w = W.footprints(scale=0.001)
     d = to_dev(w)
