@@ -147,6 +147,10 @@ struct CellKey {
 };
 constexpr int kCellCoarse = 2048;
 constexpr int kCellFine = 2048;
+// points per thread of a sorted piece in the coarse and the fine pass (pieces
+// of 4096 and 2048 points: longer runs per digit, fewer partial lines written)
+constexpr int kCellPer = 16;
+constexpr int kCellFinePer = 8;
 
 // ---------------------------------------------------------------- 3. polygon boxes and their rows
 struct PolyCells {
@@ -414,9 +418,9 @@ int pip_join_create(pip_join **out, const double *px, const double *py, int64_t 
             rc = fail(PIP_EHIP, "join grid kernels failed to launch");
     }
     // points sorted by cell; cell_start[c] = first position of cell c
-    step(launch_sort_staged<CellKey, kCellCoarse, kCellFine>(px, py, N, CellKey{j->grid}, nb, table, toff, scan_ws,
-                                                              (double2 *)(w + o_txy), (int32_t *)(w + o_tidx),
-                                                              j->sxy, j->spt, j->cell_start, s));
+    step(launch_sort_staged<CellKey, kCellCoarse, kCellFine, kCellPer, kCellFinePer>(
+        px, py, N, CellKey{j->grid}, nb, table, toff, scan_ws, (double2 *)(w + o_txy), (int32_t *)(w + o_tidx),
+        j->sxy, j->spt, j->cell_start, s));
     if (rc == PIP_OK) {
         const unsigned gq = std::min<unsigned>(grid_for(P, 4), 65536u);
         hipLaunchKernelGGL(k_poly_cells, dim3(gq), dim3(256), 0, s, offsets, P, poly_rings, p.n_rings, vx, vy,

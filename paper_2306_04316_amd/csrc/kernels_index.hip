@@ -395,10 +395,9 @@ int launch_index_prep(const Problem &p, hipStream_t s, const IndexLayout &L, uns
     hipLaunchKernelGGL(k_bounds_up, dim3(grid_for(L.n1, 256)), dim3(256), 0, s, b0, L.n0, b1, L.n1);
     hipLaunchKernelGGL(k_bounds_up, dim3(grid_for(L.n2, 256)), dim3(256), 0, s, b1, L.n1, b2, L.n2);
     hipLaunchKernelGGL(k_bounds_root, dim3(1), dim3(256), 0, s, b2, L.n2, root);
-    PIP_TRY((launch_sort_staged<YKey, kCoarse, kFine, kSortPer, kFinePer>(p.px, p.py, p.n_points, YKey{root}, L.nb, table, off, scan_ws,
-                                                     (double2 *)(ws + L.o_txy), (int32_t *)(ws + L.o_tidx),
-                                                     (double2 *)(ws + L.o_spt), (int32_t *)(ws + L.o_sidx), nullptr,
-                                                     s)));
+    PIP_TRY((launch_sort_staged<YKey, kCoarse, kFine, kSortPer, kFinePer>(
+        p.px, p.py, p.n_points, YKey{root}, L.nb, table, off, scan_ws, (double2 *)(ws + L.o_txy),
+        (int32_t *)(ws + L.o_tidx), (double2 *)(ws + L.o_spt), (int32_t *)(ws + L.o_sidx), nullptr, s)));
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
 }
