@@ -71,9 +71,9 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 
 // One unit: the group's NJ chunks (in registers) against the points m =
 // slice, slice + nslices, ... of the table.  Per chunk and point, on every
-// lane (edge): the sign bits of p_y - y_a and p_y - y_b (binary64, p_y + 0.0
-// so that p_y - y is -0 only for y > p_y... never: x - x is +0), their XOR (bit
-// 31: the edge straddles), S, then two three-input bit operations: the lane's
+// lane (edge): the sign bits of p_y - y_a and p_y - y_b (binary64; with p_y
+// + 0.0, never -0, the difference is negative exactly when y > p_y, and x - x
+// is +0), their XOR (bit 31: the edge straddles), S, then two three-input bit operations: the lane's
 // crossing word x ^= straddle & S (bit 31: S < 0) and its undecided word
 // u |= straddle & (|S| - B') with B' the float after B (bit 31: |S| <= B).
 // The point's parity is the popcount parity of ballot(x bit 31) and it is
