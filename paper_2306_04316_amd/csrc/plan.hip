@@ -546,10 +546,6 @@ int check_options(const pip_options *opts, pip_options &o)
 
 using namespace pip;
 
-extern "C" {
-
-}  // extern "C"
-
 namespace pip {
 namespace {
 int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream)
