@@ -77,6 +77,29 @@ def test_join_degenerate(P):
     assert got["point"].size == 0
 
 
+def test_join_clustered_points(P):
+    """Most points in one grid cell, many times a sort piece (4,096 points in
+    the coarse pass, 2,048 in the fine pass) and across several 16,384-point
+    chunks, beside a tight cluster and a spread; boxes over the cluster,
+    beside it and over everything."""
+    rng = np.random.default_rng(8)
+    px = np.concatenate([np.full(40_000, 0.25), 0.25 + rng.uniform(-1e-7, 1e-7, 10_000), rng.uniform(-5, 5, 20_000)])
+    py = np.concatenate([np.full(40_000, -0.5), -0.5 + rng.uniform(-1e-7, 1e-7, 10_000), rng.uniform(-5, 5, 20_000)])
+    perm = rng.permutation(px.size)
+    px, py = px[perm], py[perm]
+    rings = [[(0.2, -0.6), (0.3, -0.6), (0.3, -0.4), (0.2, -0.4)], [(0.25, -0.5), (0.26, -0.5), (0.26, -0.49)],
+             [(1.0, 1.0), (2.0, 1.0), (2.0, 2.0)], [(-6, -6), (6, -6), (6, 6), (-6, 6)],
+             [(0.25 - 1e-8, -0.5 - 1e-8), (0.25 + 1e-8, -0.5 - 1e-8), (0.25, -0.5 + 1e-8)]]
+    off = np.zeros(len(rings) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(r) for r in rings])
+    vx = np.array([a for r in rings for a, _ in r], dtype=np.float64)
+    vy = np.array([b for r in rings for _, b in r], dtype=np.float64)
+    note(f"join clustered N={px.size}")
+    got = gpu_join(P, px, py, off, vx, vy)
+    wp, wq = oracle.bbox_join(px, py, off, vx, vy)
+    check_join(got, px, py, wp, wq, "join clustered")
+
+
 def test_join_one_large_polygon(P):
     """The paper's preparation step: many points against one large polygon's box."""
     w = W.fractal(scale=0.01, n_vertices=50_000)
