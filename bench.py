@@ -246,16 +246,23 @@ def clock_under_load(run_steps, seconds=1.5):
 
 
 # ---------------------------------------------------------------- device helpers
+VALU_PROBE_ITERS = 8192   # rounds of eight binary64 additions per thread (about 1 ms)
+
+
 def measured_peaks(P, dev, nbytes: int = 1 << 30, reps: int = 10):
     """HBM rates of plain streaming kernels over nbytes (median of reps launches):
-    a read-only stream (pip_probe_read) and a copy (pip_probe_copy)."""
+    a read-only stream (pip_probe_read) and a copy (pip_probe_copy); and the
+    vector-ALU issue rate of independent binary64 additions (pip_probe_valu)."""
     import torch
     src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    sink64 = torch.zeros(1, dtype=torch.float64, device=dev)
+    lane_ops = P.probe_valu(VALU_PROBE_ITERS, sink64)
     out = {}
     for name, fn, moved in (("read_stream", lambda: P.probe_read(src, sink), nbytes),
-                            ("copy", lambda: P.probe_copy(dst, src), 2 * nbytes)):
+                            ("copy", lambda: P.probe_copy(dst, src), 2 * nbytes),
+                            ("valu", lambda: P.probe_valu(VALU_PROBE_ITERS, sink64), lane_ops)):
         for _ in range(3):
             fn()
         ts = []
@@ -266,11 +273,27 @@ def measured_peaks(P, dev, nbytes: int = 1 << 30, reps: int = 10):
             b.record()
             b.synchronize()
             ts.append(a.elapsed_time(b) * 1e-3)
-        out[name + "_GBs"] = moved / float(np.median(ts)) / 1e9
+        if name == "valu":
+            out["valu_lane_ops_per_s"] = moved / float(np.median(ts))
+        else:
+            out[name + "_GBs"] = moved / float(np.median(ts)) / 1e9
     del src, dst
     torch.cuda.empty_cache()
-    out["probe"] = f"pip_probe_read / pip_probe_copy over {nbytes >> 20} MiB, median of {reps} launches"
+    out["probe"] = (f"pip_probe_read / pip_probe_copy over {nbytes >> 20} MiB; pip_probe_valu, {lane_ops} lane "
+                    f"operations (binary64 additions, eight waves per SIMD); median of {reps} launches")
     return out
+
+
+def attach_valu_peak(v, kernel_ms, measured):
+    """The measured VALU issue rate beside a roofline's VALU figures: the method's
+    lane operations and (when recorded) the kernel's executed lane instructions
+    per second as fractions of what the probe issues."""
+    if not v:
+        return
+    v["measured_peak_lane_ops_per_s"] = measured
+    v["algorithmic_frac_of_measured_peak"] = v["algorithmic_lane_ops"] / (kernel_ms * 1e-3) / measured
+    if v.get("insts_per_launch"):
+        v["issue_frac_of_measured_peak"] = v["insts_per_launch"] * 64 / (kernel_ms * 1e-3) / measured
 
 
 def device_copies(P, w, dev, min_bytes=1 << 30):
@@ -790,6 +813,13 @@ def main():
     peaks = measured_peaks(P, dev)
     peaks["frac_of_read_stream"] = roof["achieved"] / peaks["read_stream_GBs"]
     roof["measured_peaks"] = peaks
+    attach_valu_peak(roof.get("valu"), roof["kernel_ms"], peaks["valu_lane_ops_per_s"])
+    for e in list((configs or {}).values()) + list(compare.values() if isinstance(compare, dict) else []):
+        r = e.get("roofline") if isinstance(e, dict) else None
+        if r:
+            attach_valu_peak(r.get("valu"), r["kernel_ms"], peaks["valu_lane_ops_per_s"])
+            if r.get("bound") == "alu":
+                r["frac_of_measured_peak"] = r["valu"]["algorithmic_frac_of_measured_peak"]
     rec = {
         "metric": METRIC,
         "value": T / (head["ms_per_step"] * 1e-3),

@@ -427,6 +427,19 @@ PIP_API int pip_probe_copy(void *dst, const void *src, int64_t nbytes, void *str
  */
 PIP_API int pip_probe_read(const void *src, int64_t nbytes, uint32_t *sink, void *stream);
 
+/*
+ * Diagnostic: the vector-ALU issue rate.  Launches eight 256-thread
+ * workgroups per compute unit (eight wavefronts per SIMD), each thread
+ * running `iterations` (1 .. 2^24) rounds of eight independent binary64
+ * additions, one full-rate vector instruction each; *lane_ops receives the
+ * number of lane operations the launch performs (set before the launch).
+ * At most one 8-byte word of the device buffer sink is written (its contents
+ * are meaningless).  Time the launch to get lane operations per second, the
+ * measured counterpart of the VALU lane peak that instruction-bound kernels
+ * are compared with.  Asynchronous on `stream`.
+ */
+PIP_API int pip_probe_valu(int64_t iterations, double *sink, int64_t *lane_ops, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import PipError  # noqa: F401
 
 __all__ = ["classify", "classify_rings", "candidate_pairs", "Plan", "PipError", "abi_version", "probe_copy",
-           "probe_read", "to_device"]
+           "probe_read", "probe_valu", "to_device"]
 
 
 def _require(t, dtype, name, numel=None):
@@ -262,6 +262,17 @@ def probe_read(src, sink, stream=None):
         raise ValueError("sink must hold at least 4 bytes")
     nbytes = src.numel() * src.element_size()
     _lib.check(_lib.load().pip_probe_read(_ptr(src), nbytes, _ptr(sink), _stream_handle(stream)))
+
+
+def probe_valu(iterations, sink, stream=None) -> int:
+    """Vector-ALU issue probe (binary64 additions); sink: a device tensor of at
+    least 8 bytes that may receive one meaningless word.  Returns the lane
+    operations the launch performs."""
+    if sink.numel() * sink.element_size() < 8:
+        raise ValueError("sink must hold at least 8 bytes")
+    n = ctypes.c_int64(0)
+    _lib.check(_lib.load().pip_probe_valu(int(iterations), _ptr(sink), ctypes.byref(n), _stream_handle(stream)))
+    return int(n.value)
 
 
 def abi_version() -> int:

@@ -60,6 +60,7 @@ _SIGS = {
                                             ctypes.POINTER(pip_options), _VP]),
     "pip_probe_copy": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "pip_probe_read": (ctypes.c_int, [_VP, _I64, _VP, _VP]),
+    "pip_probe_valu": (ctypes.c_int, [_I64, _VP, ctypes.POINTER(ctypes.c_int64), _VP]),
     "pip_plan_create": (ctypes.c_int, [ctypes.POINTER(_VP), _VP, _VP, _I64, _VP, _I64, _VP, _VP, _I64, _VP, _VP,
                                        ctypes.POINTER(pip_options), _VP]),
     "pip_classify_rings": (ctypes.c_int, [_VP, _VP, _I64, _VP, _I64, _VP, _I64, _VP, _VP, _I64, _VP, _VP,

@@ -417,4 +417,14 @@ int pip_probe_read(const void *src, int64_t nbytes, uint32_t *sink, void *stream
     return launch_read(src, nbytes, sink, (hipStream_t)stream);
 }
 
+int pip_probe_valu(int64_t iterations, double *sink, int64_t *lane_ops, void *stream)
+{
+    clear_error();
+    if (iterations < 1 || iterations > (1 << 24) || !sink || !lane_ops)
+        return fail(PIP_EINVAL, "pip_probe_valu: NULL pointer or iterations outside [1, 2^24]");
+    DeviceInfo *dev = nullptr;
+    PIP_TRY(current_device(&dev));
+    return launch_valu_probe((int)iterations, sink, dev->cu_count, lane_ops, (hipStream_t)stream);
+}
+
 }  // extern "C"

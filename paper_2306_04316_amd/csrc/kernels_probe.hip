@@ -1,6 +1,7 @@
-// Bandwidth probe: a read-only stream over device memory, the rate that
+// Device probes: a read-only stream over device memory, the rate that
 // read-dominated kernels are compared with (the copy probe sits beside the
-// exact kernels).
+// exact kernels), and a vector-ALU issue probe, the rate of binary64 additions
+// that instruction-bound kernels are compared with.
 
 #include "pip_common.h"
 
@@ -23,7 +24,45 @@ __global__ __launch_bounds__(256) void k_read16(const u32x4 *__restrict__ src, i
         sink[0] = v;
 }
 
+constexpr int kValuChains = 8;   // independent binary64 addition chains per thread
+constexpr int kValuBlocksPerCu = 8;   // eight wavefronts per SIMD
+
+// Every thread runs `iters` rounds of kValuChains independent binary64
+// additions of the uniform `step` (one full-rate vector instruction each, no
+// fused or packed forms); the sum is stored only if it equals a value it
+// cannot reach from these inputs, so the additions must happen and at most
+// one word of sink is written.
+__global__ __launch_bounds__(256) void k_valu_probe(double *sink, int iters, double step)
+{
+    double a[kValuChains];
+#pragma unroll
+    for (int c = 0; c < kValuChains; ++c)
+        a[c] = (double)(threadIdx.x * kValuChains + c);
+#pragma unroll 4
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int c = 0; c < kValuChains; ++c)
+            a[c] += step;
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < kValuChains; ++c)
+        t += a[c];
+    if (t == -1.0)
+        sink[0] = t;
+}
+
 }  // namespace
+
+int launch_valu_probe(int iters, double *sink, int cu_count, int64_t *lane_ops, hipStream_t stream)
+{
+    const unsigned g = (unsigned)(cu_count > 0 ? cu_count : 1) * kValuBlocksPerCu;
+    *lane_ops = (int64_t)g * 256 * (int64_t)iters * kValuChains;
+    // a step the additions cannot be folded over (a power of two: every sum is exact)
+    hipLaunchKernelGGL(k_valu_probe, dim3(g), dim3(256), 0, stream, sink, iters, 0.5);
+    PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
 
 int launch_read(const void *src, int64_t nbytes, unsigned *sink, hipStream_t stream)
 {

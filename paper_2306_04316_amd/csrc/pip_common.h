@@ -189,6 +189,7 @@ int launch_item_desc(const Problem &p, hipStream_t stream, int item_pairs, int n
                      uint8_t *bucket, unsigned *counters, int32_t *order, ItemDesc *sdesc);
 int launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t stream);
 int launch_read(const void *src, int64_t nbytes, unsigned *sink, hipStream_t stream);
+int launch_valu_probe(int iters, double *sink, int cu_count, int64_t *lane_ops, hipStream_t stream);
 // Exclusive scan of n uint32 counts into out[0..n] (int64; out[n] = total);
 // block_ws holds scan_ws_entries(n) int64 entries.  Kernels only.
 int64_t scan_ws_entries(int64_t n);

@@ -113,6 +113,13 @@ def test_host_argument_errors(lib):
     assert rc == _lib.PIP_EINVAL
     rc = lib.pip_probe_read(dummy, 16, None, None)
     assert rc == _lib.PIP_EINVAL
+    # VALU probe: iterations out of range, NULL sink or count
+    n = ctypes.c_int64(-1)
+    for it, sk, cnt in ((0, dummy, ctypes.byref(n)), ((1 << 24) + 1, dummy, ctypes.byref(n)),
+                        (16, None, ctypes.byref(n)), (16, dummy, None)):
+        rc = lib.pip_probe_valu(it, sk, cnt, None)
+        assert rc == _lib.PIP_EINVAL and b"pip_probe_valu" in lib.pip_last_error()
+    assert n.value == -1
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):

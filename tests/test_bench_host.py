@@ -115,3 +115,17 @@ def test_alu_roofline_of_an_issue_bound_kernel():
     r = bench.alu_roofline(hbm)
     assert r["bound"] == "alu" and r["achieved"] == 20.0 and r["peak"] == 40.0 and r["frac"] == 0.5
     assert r["hbm"]["frac"] == 1.25e-4 and "valu" in r
+
+
+def test_attach_valu_peak():
+    """The measured VALU peak beside a roofline's VALU figures."""
+    import bench
+    v = {"algorithmic_lane_ops": 2e9, "insts_per_launch": 1e6}
+    bench.attach_valu_peak(v, 1.0, 4e13)
+    assert v["measured_peak_lane_ops_per_s"] == 4e13
+    assert abs(v["algorithmic_frac_of_measured_peak"] - 2e9 / 1e-3 / 4e13) < 1e-12
+    assert abs(v["issue_frac_of_measured_peak"] - 1e6 * 64 / 1e-3 / 4e13) < 1e-12
+    w = {"algorithmic_lane_ops": 1e9, "insts_per_launch": None}
+    bench.attach_valu_peak(w, 2.0, 1e13)
+    assert "issue_frac_of_measured_peak" not in w
+    bench.attach_valu_peak(None, 1.0, 1e13)   # no VALU figures: nothing to do

@@ -204,3 +204,15 @@ def test_bandwidth_probes(P):
     assert torch.equal(dst, src)
     with pytest.raises(P.PipError):
         P.probe_read(src[:3], sink)   # 12 bytes: not a multiple of 16
+    # VALU probe: eight 256-thread workgroups per compute unit, eight
+    # additions per round; the sink is not written (the sum cannot be -1)
+    sink64 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = P.probe_valu(100, sink64)
+    torch.cuda.synchronize()
+    assert n == cus * 8 * 256 * 100 * 8
+    assert sink64.item() == 0.0
+    with pytest.raises(P.PipError):
+        P.probe_valu(0, sink64)
+    with pytest.raises(ValueError):
+        P.probe_valu(10, sink)   # 4 bytes: too small
