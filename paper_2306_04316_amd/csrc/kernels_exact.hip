@@ -278,6 +278,82 @@ __global__ __launch_bounds__(256) void k_runs_batched_fp64(
     }
 }
 
+// ---------------------------------------------------------------- one ring, cut into segments
+// Every point against the one ring [offsets[0], offsets[1]) (no pair index).
+// The ring's edges (by end vertex) are cut into nseg = 8 * ns_hi segments of
+// equal length and workgroup b takes 1024 points against one segment:
+// s_lo = b % 8, then the point block, then s_hi = b / (8 * blocks).
+// Consecutive workgroups go to the eight XCDs in turn, so XCD x walks
+// segments s_hi * 8 + x, one s_hi group after the other: its share of the
+// ring's y values (about 1 MB per segment) stays in its own L2 while every
+// point block passes over it.  A segment's walk is the runs kernel's
+// wave-uniform chunk walk started with the above bit of the vertex before the
+// segment; the segments' parities of each 64-point run are combined by a
+// 64-bit XOR into mask[run] (cleared before, turned into bytes after).  The
+// segment length follows the ring size read on the device, so any ring
+// (even one that changed since the plan chose nseg) is covered exactly.
+template <int PRED>
+__global__ __launch_bounds__(256) void k_ring_segments(const double *__restrict__ px, const double *__restrict__ py,
+                                                       int64_t n, const int64_t *__restrict__ offsets,
+                                                       const double *__restrict__ vx, const double *__restrict__ vy,
+                                                       int64_t nv, int ns_hi, int64_t nblk,
+                                                       unsigned long long *__restrict__ mask)
+{
+    const int64_t bid = blockIdx.x;
+    const int s_lo = (int)(bid & 7);
+    const int64_t r = bid >> 3;
+    const int64_t blk = r % nblk;
+    const int s = (int)(r / nblk) * 8 + s_lo;
+    int64_t b0 = offsets[0], e0 = offsets[1];
+    clamp_ring(b0, e0, nv);
+    const int k = (int)(e0 - b0);
+    const int nseg = 8 * ns_hi;
+    const int seg = (int)(((int64_t)k + nseg - 1) / nseg);
+    const int c_begin = (int)((int64_t)s * seg);
+    const int c_end = c_begin + seg < k ? c_begin + seg : k;
+    if (k <= 0 || c_begin >= c_end)
+        return;
+    const double *rx = vx + b0, *ry = vy + b0;
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i0 = blk * 1024 + (int64_t)(u * 4 + wid) * 64;
+        if (i0 >= n)
+            break;
+        const int64_t i = i0 + lane;
+        const bool member = i < n;
+        double x = 0.0, y = 0.0;
+        if (member) {
+            x = px[i];
+            y = py[i];
+        }
+        const double yq = y + 0.0;
+        uint32_t prev = shift_in_above(0u, yq, ry[c_begin == 0 ? k - 1 : c_begin - 1]);
+        uint64_t par = 0;
+        for (int c0 = c_begin; c0 < c_end; c0 += 32)
+            par ^= chunk_parity_uniform<PRED>(x, y, yq, member, rx, ry, k, c0, prev, c_end);
+        // each lane's copy of par is exact in its own bit only (the side-test
+        // loop's ballots reach the lanes still in it), so the run's mask is
+        // gathered from every lane's own bit
+        const uint64_t run = __builtin_amdgcn_ballot_w64((par >> lane) & 1u);
+        if (lane == 0 && run)
+            atomicXor(&mask[i0 >> 6], (unsigned long long)run);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_words(unsigned *__restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_mask_bytes(const unsigned long long *__restrict__ mask, int64_t n,
+                                                    uint8_t *__restrict__ inside)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        inside[i] = (uint8_t)((mask[i >> 6] >> (i & 63)) & 1ull);
+}
+
 // ---------------------------------------------------------------- validation
 __global__ __launch_bounds__(256) void k_validate_points(
     const double *__restrict__ px, const double *__restrict__ py, int64_t n,
@@ -513,6 +589,49 @@ int launch_runs_batched(const Problem &p, hipStream_t stream, int pairs_per_lane
     else
         PIP_LAUNCH_R(2);
 #undef PIP_LAUNCH_R
+    PIP_HIP_TRY(hipGetLastError());
+    return PIP_OK;
+}
+
+int ring_segments_hi(int64_t k)
+{
+    // segments of at most 131,072 vertices (1 MB of y values) per XCD at a time
+    const int64_t per = 8 * (int64_t)kSegmentVertices;
+    const int64_t h = (k + per - 1) / per;
+    return (int)(h < 1 ? 1 : (h > 4096 ? 4096 : h));
+}
+
+int launch_ring_segments(const Problem &p, hipStream_t stream, int ns_hi, unsigned long long *mask)
+{
+    if (p.poly_rings || p.point_poly || p.n_polys != 1)
+        return fail(PIP_EINVAL, "the segmented walk takes one polygon of one ring and no pair index");
+    if (!mask || ns_hi < 1)
+        return fail(PIP_EINVAL, "the segmented walk needs its mask");
+    if (p.n_points <= 0)
+        return PIP_OK;
+    const int64_t nblk = (p.n_points + 1023) / 1024;
+    const int64_t words = (p.n_points + 63) / 64;
+    const int64_t grid = nblk * 8 * ns_hi;
+    if (grid > 0x7fffffffll)
+        return fail(PIP_EINVAL, "too many points for the segmented walk");
+    // the main-kernel timer spans the clear, the walk and the bytes
+    KernelTimer &kt = kernel_timer();
+    const KernelTimer saved = kt;
+    kt.stop = nullptr;
+    const int64_t g1 = grid_for(words * 2, 256) < 65536 ? grid_for(words * 2, 256) : 65536;
+    PIP_LAUNCH(k_fill_words, dim3((unsigned)g1), dim3(256), 0, stream, (unsigned *)mask, words * 2);
+    kt = KernelTimer{};
+    if (p.pred == kIntersection)
+        PIP_LAUNCH(k_ring_segments<kIntersection>, dim3((unsigned)grid), dim3(256), 0, stream, p.px, p.py,
+                   p.n_points, p.offsets, p.vx, p.vy, p.n_vertices, ns_hi, nblk, mask);
+    else
+        PIP_LAUNCH(k_ring_segments<kSide>, dim3((unsigned)grid), dim3(256), 0, stream, p.px, p.py, p.n_points,
+                   p.offsets, p.vx, p.vy, p.n_vertices, ns_hi, nblk, mask);
+    kt.stop = saved.stop;
+    const int64_t g2 = grid_for(p.n_points, 256) < 65536 ? grid_for(p.n_points, 256) : 65536;
+    PIP_LAUNCH(k_mask_bytes, dim3((unsigned)g2), dim3(256), 0, stream, (const unsigned long long *)mask, p.n_points,
+               p.inside);
+    kt = saved;
     PIP_HIP_TRY(hipGetLastError());
     return PIP_OK;
 }

@@ -106,6 +106,14 @@ size_t runs_smem_bytes(int pairs_per_lane);
 int runs_occupancy(int pairs_per_lane, int *blocks_per_cu);
 int launch_runs_batched(const Problem &p, hipStream_t stream, int pairs_per_lane, const int32_t *order,
                         int n_items, unsigned *queue, int grid);
+// One polygon of one ring for every point (no pair index), its edges walked in
+// segments laid out over the XCDs (kernels_exact.hip): plans use it from
+// kSegmentMinVertices vertices on.  ring_segments_hi: segment groups for a
+// ring of k vertices; mask: (n_points + 63) / 64 64-bit words of workspace.
+constexpr int kSegmentVertices = 131072;
+constexpr int64_t kSegmentMinVertices = 65536;
+int ring_segments_hi(int64_t k);
+int launch_ring_segments(const Problem &p, hipStream_t stream, int ns_hi, unsigned long long *mask);
 int staged_max_rings(int pairs_per_lane);
 int staged_occupancy(int pairs_per_lane, int max_edges, int *blocks_per_cu);
 // tiles: use the form that walks rings larger than max_edges in LDS tiles

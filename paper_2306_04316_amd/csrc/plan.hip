@@ -35,6 +35,8 @@ struct pip_plan {
     unsigned max_tasks = 0;
     unsigned char *index_ws = nullptr;
     pip::IndexLayout index;
+    unsigned long long *segmask = nullptr;   // one ring, no pair index: segment parities per 64-point run
+    int seg_hi = 0;                          // segment groups of that walk (0: the runs kernel's own walk)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -178,6 +180,8 @@ int enqueue_phase(pip_plan *pl, const pip_plan_config &c, hipStream_t s, int ph)
             return launch_per_pair(p, s);
         if (c.kernel == PIP_KERNEL_SEGMENTED)
             return launch_segmented(p, s, c.pairs_per_lane, 256);
+        if (c.kernel == PIP_KERNEL_RUNS && pl->seg_hi > 0)
+            return launch_ring_segments(p, s, pl->seg_hi, pl->segmask);
         if (c.kernel == PIP_KERNEL_RUNS)
             return launch_runs_batched(p, s, c.pairs_per_lane, order, c.n_items, queue, c.grid);
         return launch_staged_batched(p, s, c.pairs_per_lane, c.lds_slots, order, c.n_items, c.persistent != 0,
@@ -651,6 +655,19 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
         c.order = 0;
     }
     const size_t o_idx = take(o.index ? pl->index.bytes : 0);
+    // one ring for every point: the segmented walk's run masks, used when the
+    // ring (its size read now; a later change only changes which exact walk
+    // runs) has at least kSegmentMinVertices vertices
+    const bool one_ring = !point_poly && !p.poly_rings && p.n_polys == 1 && n_points > 0 && !o.index;
+    int seg_hi = 0;
+    if (one_ring) {
+        int64_t o2[2] = {0, 0};
+        if (hipMemcpy(o2, offsets, sizeof o2, hipMemcpyDeviceToHost) == hipSuccess &&
+            o2[1] - o2[0] >= kSegmentMinVertices)
+            seg_hi = ring_segments_hi(o2[1] - o2[0]);
+        (void)hipGetLastError();
+    }
+    const size_t o_seg = take(seg_hi > 0 ? (size_t)((n_points + 63) / 64) * 8 : 0);
     pl->ws_bytes = off;
     hipError_t e = hipMalloc(&pl->ws, pl->ws_bytes);
     if (e != hipSuccess) {
@@ -669,6 +686,8 @@ int plan_create(pip_plan **out, Problem p, const pip_options *opts, void *stream
     pl->tasks = mt ? (WaveTask *)(w + o_tsk) : nullptr;
     pl->max_tasks = (unsigned)mt;
     pl->index_ws = o.index ? w + o_idx : nullptr;
+    pl->segmask = seg_hi > 0 ? (unsigned long long *)(w + o_seg) : nullptr;
+    pl->seg_hi = seg_hi;
     for (int k = 0; k < 4 && rc == PIP_OK; ++k) {
         e = hipEventCreate(&pl->ev[k]);
         if (e != hipSuccess)

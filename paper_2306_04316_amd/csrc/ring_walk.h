@@ -107,21 +107,26 @@ __device__ __forceinline__ bool block_all(bool v, int *flags)
     return (flags[0] & flags[1] & flags[2] & flags[3]) != 0;
 }
 
-// One 32-edge chunk of a wave-uniform ring with compacted side tests: edges
-// c0 .. c0+m-1 (m <= 32), i.e. vertices v_{c0-1} -> v_{c0} onwards.  The ring's
+// One 32-edge chunk of a wave-uniform ring of k vertices with compacted side
+// tests: edges c0 .. c0+m-1, m = min(32, end - c0) (end <= k: the last edge
+// the walk takes, for walks over a part of the ring), i.e. vertices
+// v_{c0-1} -> v_{c0} onwards.  The ring's
 // y values stream through scalar loads into each lane's 32-bit "above" word
 // (two vector instructions per vertex); each member lane then evaluates the
 // side value only for its own straddling edges, fetching those two vertices
 // itself.  `prev` holds the above bit of v_{c0-1} on entry and of the chunk's
 // last vertex on exit.  Returns the lanes with an odd number of crossings in
-// the chunk.
+// the chunk: each lane's own bit of the result is exact; the other bits are
+// those of the side-test ballots that lane took part in (the loop is
+// divergent), so a caller that needs the whole mask gathers it with one
+// ballot of each lane's own bit.
 template <int PRED>
 __device__ __forceinline__ uint64_t chunk_parity_uniform(double x, double y, double yq, bool member,
                                                          const double *__restrict__ rx,
                                                          const double *__restrict__ ry, int k, int c0,
-                                                         uint32_t &prev)
+                                                         uint32_t &prev, int end)
 {
-    const int m = k - c0 < 32 ? k - c0 : 32;
+    const int m = end - c0 < 32 ? end - c0 : 32;
     uint32_t above = 0;
     if (m == 32) {
 #pragma unroll
@@ -173,7 +178,7 @@ __device__ __forceinline__ uint64_t ring_parity_compact_uniform(double x, double
     const double yq = y + 0.0;
     uint32_t prev = shift_in_above(0u, yq, ry[k - 1]);
     for (int c0 = 0; c0 < k; c0 += 32)
-        par ^= chunk_parity_uniform<PRED>(x, y, yq, member, rx, ry, k, c0, prev);
+        par ^= chunk_parity_uniform<PRED>(x, y, yq, member, rx, ry, k, c0, prev, k);
     return par;
 }
 

@@ -343,6 +343,63 @@ def test_plan_index_point_layouts(P, layout):
     pl.close()
 
 
+def one_ring(k, n, seed):
+    """A star-like ring of k vertices and n points over its box, some level
+    with vertices and some on them."""
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.uniform(0, 2 * np.pi, k))
+    r = 1.0 + 0.3 * rng.uniform(-1, 1, k)
+    vx, vy = r * np.cos(t), r * np.sin(t)
+    px = rng.uniform(-1.4, 1.4, n)
+    py = rng.uniform(-1.4, 1.4, n)
+    j = rng.integers(0, k, n // 10)
+    py[: n // 10] = vy[j]
+    px[n // 10: n // 5], py[n // 10: n // 5] = vx[j[: n // 5 - n // 10]], vy[j[: n // 5 - n // 10]]
+    return W.Workload("one-ring", px, py, np.array([0, k], dtype=np.int64), vx, vy, None, {})
+
+
+@pytest.mark.parametrize("k", [65_535, 65_536, 65_537, 131_072 * 8, 131_072 * 8 + 1, 300_001])
+@pytest.mark.parametrize("pred", ["side", "intersection"])
+def test_plan_one_ring_segments(P, k, pred):
+    """One ring for every point (no pair index): from 65,536 vertices on, plans
+    walk the ring in segments laid out over the XCDs (one and two segment
+    groups here), combining each 64-point run's segment parities; every point
+    of a ragged count against the oracle, eager and over graph replays."""
+    import torch
+    w = one_ring(k, 2_111, seed=k % 97)
+    want = oracle.classify_workload(w, predicate=2 if pred == "intersection" else 1)
+    d = to_dev(w)
+    for graph in (False, True):
+        note(f"one ring k={k} pred={pred} graph={graph}")
+        pl = P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], None, predicate=pred, use_graph=graph)
+        for _ in range(3 if graph else 1):
+            pl.out.fill_(7)
+            pl.execute()
+            torch.cuda.synchronize()
+            assert_same_mask(pl.out.cpu().numpy(), want, f"one ring k={k} {pred} graph={graph}", w.px, w.py)
+        pl.close()
+
+
+def test_plan_one_ring_changes_between_executions(P):
+    """The segmented walk reads the ring's size on the device: a plan made for
+    a ring of 200,000 vertices stays exact when the buffers then hold a ring
+    of 1,000 vertices (offsets rewritten) and one of 150,000."""
+    import torch
+    w = one_ring(200_000, 1_500, seed=3)
+    d = to_dev(w)
+    pl = P.Plan(d["px"], d["py"], d["offsets"], d["vx"], d["vy"], None)
+    for kk in (200_000, 1_000, 150_000):
+        sub = W.Workload("one-ring prefix", w.px, w.py, np.array([0, kk], dtype=np.int64), w.vx[:kk], w.vy[:kk],
+                         None, {})
+        d["offsets"].copy_(torch.tensor([0, kk], dtype=torch.int64, device="cuda"))
+        note(f"one ring changed to k={kk}")
+        pl.out.fill_(7)
+        pl.execute()
+        torch.cuda.synchronize()
+        assert_same_mask(pl.out.cpu().numpy(), oracle.classify_workload(sub), f"ring of {kk}", w.px, w.py)
+    pl.close()
+
+
 def test_plan_index_rejects_pair_index(P):
     w = W.footprints(scale=0.001)
     d = to_dev(w)
