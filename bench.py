@@ -78,18 +78,17 @@ PAPER_CONTEXT = {
 # stops applying when the sources change, and the figures it feeds are then reported as null.
 # fetch/write: FETCH_SIZE and WRITE_SIZE scaled by their reading of a copy kernel of known size.
 PROFILED: dict = {
-    (4, "filtered", "k_filtered_fp32", "5108b99f135d"): {
-        "fetch_bytes": 2414023435, "write_bytes": 100030073, "valu_insts": 498057611, "waves": 390656,
+    (4, "filtered", "k_filtered_fp32", "84956aede086"): {
+        "fetch_bytes": 2413978994, "write_bytes": 100029746, "valu_insts": 498057611, "waves": 390656,
         "source": "profiles/filtered_batched.md"},
-    (4, "exact", "k_staged_batched_fp64", "3490bb00a683"): {
-        "fetch_bytes": 2414989064, "write_bytes": 100027928, "valu_insts": 431314460, "waves": 390656,
+    (4, "exact", "k_staged_batched_fp64", "20bc7d20b8e6"): {
+        "fetch_bytes": 2414966565, "write_bytes": 100027707, "valu_insts": 431314460, "waves": 390656,
         "source": "profiles/staged_batched_exact.md"},
-    (4, "filtered", "k_batched", "cfa634536c00"): {
-        "fetch_bytes": 2473456991, "write_bytes": 100148806, "valu_insts": 503289813, "waves": 781308,
+    (4, "filtered", "k_batched", "ca9bc706ed9c"): {
+        "fetch_bytes": 2473433098, "write_bytes": 100148905, "valu_insts": 503289813, "waves": 781308,
         "source": "profiles/batched_kernel_batched.md"},
-    (4, "filtered", "k_batched+k_wave_rings", "cfa634536c00"): {
-        "fetch_bytes": (1169920 + 111204) * 1024 * 2, "write_bytes": (97833 + 1605) * 1024,
-        "valu_insts": 443473305 + 160270146, "waves": 781308 + 6144,
+    (4, "filtered", "k_batched+k_wave_rings", "ca9bc706ed9c"): {
+        "fetch_bytes": 2623426984, "write_bytes": 101822759, "valu_insts": 603743450, "waves": 787452,
         "source": "profiles/batched_kernel_wave_ring_256_batched.md"},
 }
 
@@ -100,18 +99,30 @@ KERNEL_SOURCES = {
     "k_filtered_fp32": ("kernels_filtered.hip", "staged_exact.h", "ring_walk.h", "filter_bound.h"),
     "k_staged_batched_fp64": ("kernels_exact.hip", "staged_exact.h", "ring_walk.h"),
     "k_runs_batched_fp64": ("kernels_exact.hip", "ring_walk.h"),
+    "k_ring_segments": ("kernels_exact.hip", "ring_walk.h"),
+    "k_runs_indexed_fp64": ("kernels_index.hip", "sort_staged.h", "ring_walk.h"),
     "k_per_pair_fp64": ("kernels_exact.hip", "ring_walk.h"),
 }
 
 
-def kernel_name(cfg) -> str:
-    """The main kernel a plan configuration launches."""
+SEGMENT_MIN_VERTICES = 65536   # plans walk one ring for every point in segments from this size on
+
+
+def kernel_name(cfg, w=None) -> str:
+    """The main kernel a plan configuration launches (on workload w, when given:
+    a plan of the runs kernel over one ring for every point walks it in
+    segments from SEGMENT_MIN_VERTICES vertices on)."""
     k, mode = cfg["kernel"], cfg["mode"]
     if k == 5:
         return "k_batched+k_wave_rings" if cfg.get("wave_k", 0) > 0 else "k_batched"
     if k == 1:
         return "k_per_pair_fp64"
     if k == 4:
+        if cfg.get("index"):
+            return "k_runs_indexed_fp64"
+        if (w is not None and w.point_poly is None and getattr(w, "poly_rings", None) is None and w.n_polys == 1
+                and w.n_vertices >= SEGMENT_MIN_VERTICES):
+            return "k_ring_segments"
         return "k_runs_batched_fp64"
     return "k_filtered_fp32" if mode == 1 else "k_staged_batched_fp64"
 
@@ -519,7 +530,7 @@ def measure(P, w, copies, opts, steps, warmup, config, mode, th, parity=True, wa
     rk = Runner(P, copies, dict(tuned, use_graph=False, timing=1))
     ph = rk.phase_times(ktimes or max(10, min(steps, 50)))
     rk.close()
-    name = kernel_name(cfg)
+    name = kernel_name(cfg, w)
     main_ms = float(np.mean(ph[:, 1]))
     e = {"ms_per_step": ms, "tests_per_s": w.n_tests / (ms * 1e-3), "points_per_s": w.n_points / (ms * 1e-3),
          "pairs": w.n_points, "tests": w.n_tests, "steps": steps, "warmup": warmup, "wall_s_timed": wall,

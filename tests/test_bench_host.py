@@ -11,6 +11,7 @@ import sys
 import numpy as np
 
 import bench
+from paper_2306_04316_amd import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -40,6 +41,12 @@ def test_kernel_names():
     assert bench.kernel_name({"kernel": 3, "mode": 1}) == "k_filtered_fp32"
     assert bench.kernel_name({"kernel": 3, "mode": 0}) == "k_staged_batched_fp64"
     assert bench.kernel_name({"kernel": 4, "mode": 0}) == "k_runs_batched_fp64"
+    assert bench.kernel_name({"kernel": 4, "mode": 0, "index": 1}) == "k_runs_indexed_fp64"
+    ring = W.fractal(scale=0.0001, n_vertices=70_000)
+    assert bench.kernel_name({"kernel": 4, "mode": 0, "index": 0}, ring) == "k_ring_segments"
+    small = W.fractal(scale=0.0001, n_vertices=60_000)
+    assert bench.kernel_name({"kernel": 4, "mode": 0, "index": 0}, small) == "k_runs_batched_fp64"
+    assert bench.kernel_name({"kernel": 4, "mode": 0, "index": 0}, W.footprints(scale=0.001)) == "k_runs_batched_fp64"
     assert bench.kernel_name({"kernel": 1, "mode": 0}) == "k_per_pair_fp64"
 
 
