@@ -90,6 +90,9 @@ PROFILED: dict = {
     (4, "filtered", "k_batched+k_wave_rings", "ca9bc706ed9c"): {
         "fetch_bytes": 2623426984, "write_bytes": 101822759, "valu_insts": 603743450, "waves": 787452,
         "source": "profiles/batched_kernel_wave_ring_256_batched.md"},
+    (3, "exact", "k_ring_segments", "501d20328a6a"): {
+        "fetch_bytes": 1335002027, "write_bytes": 34495968, "valu_insts": 347753019004, "waves": 312512,
+        "source": "profiles/ring_segments_fractal.md"},
 }
 
 KERNEL_SOURCES = {
@@ -772,6 +775,8 @@ def main():
                         "timed steps")
     sf = straddle_fraction(w)
     roof["valu"] = valu_entry(a.config, a.mode, name, main_ms, clock[0], clock[1], alg_lane_ops(w, a.mode, sf))
+    if a.config == 3:   # every point tests every edge of one ring: bound by vector issue
+        roof = alu_roofline(roof)
     rf = recheck_figures(P, w, copies, tuned)
 
     # ---- the same workload: the other mode, the staged filtered kernel, the per-pair kernel
@@ -822,9 +827,12 @@ def main():
 
     progress("bandwidth probes")
     peaks = measured_peaks(P, dev)
-    peaks["frac_of_read_stream"] = roof["achieved"] / peaks["read_stream_GBs"]
+    hbm_gbs = roof["hbm"]["achieved"] if roof["bound"] == "alu" else roof["achieved"]
+    peaks["frac_of_read_stream"] = hbm_gbs / peaks["read_stream_GBs"]
     roof["measured_peaks"] = peaks
     attach_valu_peak(roof.get("valu"), roof["kernel_ms"], peaks["valu_lane_ops_per_s"])
+    if roof["bound"] == "alu":
+        roof["frac_of_measured_peak"] = roof["valu"]["algorithmic_frac_of_measured_peak"]
     for e in list((configs or {}).values()) + list(compare.values() if isinstance(compare, dict) else []):
         r = e.get("roofline") if isinstance(e, dict) else None
         if r:

@@ -436,6 +436,10 @@ int autotune(pip_plan *pl, hipStream_t s)
     std::vector<int> wave_opts = {0};
     if (pl->o.wave_k == 0 && pl->o.mode == PIP_MODE_FILTERED_FP32 && !pl->p.poly_rings)
         wave_opts = {0, 256, 1024};
+    // the plan's own untuned choice first: when steps are long the budget ends
+    // the search after a few candidates, and it must not end worse than that
+    if (kernel_allowed(pl, pl->cfg.kernel))
+        cands.push_back(pl->cfg);
     std::vector<int> kernels;
     for (int kern : {PIP_KERNEL_BATCHED, PIP_KERNEL_STAGED, PIP_KERNEL_RUNS})
         if (kernel_allowed(pl, kern))
